@@ -1,0 +1,191 @@
+/*
+ * sph.h -- C ABI of libsph, the MI355X (gfx950) hot path of differentiable
+ * weakly compressible SPH: cell-list neighbour search, the fused delta-SPH
+ * pair sweeps, a fixed-step semi-implicit Euler integrator, and the adjoint
+ * of one step.
+ *
+ * Paper: diffSPH, Winchenbach & Thuerey, arXiv 2507.21684.  The problem
+ * statement the calls follow (Sec. 2.2): a state u = (x, f, sigma) is
+ * advanced by a step P built from an update function f : P x C -> U (the
+ * time derivatives, App. C) and a neighbourhood function g (App. B); its
+ * gradient is the vector-Jacobian product (dP/du)^T a.
+ *
+ * Conventions shared by every call
+ *  - Memory: the library never allocates device memory.  The caller owns the
+ *    state, the outputs, the checkpoints and one workspace whose size
+ *    sph_workspace_size() reports.  All pointers named "device" point to GPU
+ *    memory; "host" pointers to CPU memory.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the default
+ *    stream).  Calls enqueue work asynchronously on it unless documented as
+ *    synchronous.  Calls on one plan must be ordered (one stream, or the
+ *    caller's own synchronisation); distinct plans are independent.
+ *  - Batches: a plan describes nsims independent simulations of one
+ *    dimension and one dtype, packed back to back: simulation s owns
+ *    particles [off_s, off_s + counts[s]) of every array, off_s being the
+ *    sum of the earlier counts.  A single simulation is a batch of one; there
+ *    is one code path.
+ *  - State layout: SoA in the plan's dtype (float for SPH_F32, double for
+ *    SPH_F64), in the caller's particle order ("original order").
+ *    x[k] is coordinate k (k < dim) of all packed particles, likewise v[k].
+ *    Positions are unwrapped (absolute); the periodic box is applied inside
+ *    (Sec. 3.2, "Periodic Boundary Conditions").
+ *  - Errors: every call returns an sph_status; it never throws.  The return
+ *    code covers argument checks and launch errors.  Faults detected on the
+ *    device (non-finite values, neighbour-list overflow) are recorded per
+ *    simulation and read with sph_poll().  sph_last_error() returns a
+ *    thread-local message for the last failing call of the calling thread.
+ *  - Determinism: results are bitwise reproducible for identical inputs, and
+ *    a simulation's results do not depend on which other simulations share
+ *    its batch (every particle sums its neighbours in a fixed order: stencil
+ *    cells by relative offset, then particles by original index).
+ */
+#ifndef SPH_H
+#define SPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sph_status;
+
+#define SPH_OK 0
+#define SPH_ERR_INVALID_ARG (-1)   /* bad dim/dtype/pointer/size, or H >= L/2 */
+#define SPH_ERR_TOO_FEW_CELLS (-2) /* fewer than 3 cells of side >= H per box side */
+#define SPH_ERR_CAPACITY (-3)      /* an output or neighbour list is too small */
+#define SPH_ERR_NONFINITE (-4)     /* a non-finite value was found on the device */
+#define SPH_ERR_DEVICE (-5)        /* a HIP call failed */
+#define SPH_ERR_UNSUPPORTED (-6)
+#define SPH_ERR_STATE (-7)         /* call order violated (e.g. plan not bound) */
+
+/* per-simulation device status bits, read by sph_poll() */
+#define SPH_FLAG_NONFINITE 1
+#define SPH_FLAG_NEIGHBOR_OVERFLOW 2
+
+#define SPH_F32 0
+#define SPH_F64 1
+
+/* Parameters of one simulation (Sec. 2.3 governing equations, App. A.1 kernel,
+ * Sec. 3.4 fixed time step).  "support" is the kernel support radius H, the
+ * distance at which the Wendland-C4 kernel vanishes; the paper calls it h
+ * (App. A.1) and so it also enters dt, delta*H*c0 and alpha*H*c0. */
+typedef struct sph_params {
+    int32_t dim;      /* 2 or 3 */
+    int32_t dtype;    /* SPH_F32 or SPH_F64; equal for every simulation of a plan */
+    double box;       /* periodic box side L (the box is [0, L)^dim) */
+    double support;   /* H; must satisfy 2 H < L */
+    double mass;      /* particle mass m (equal for all particles of the simulation) */
+    double rho0;      /* rest density of the Tait equation of state */
+    double c0;        /* speed of sound */
+    double delta;     /* delta-SPH density-diffusion coefficient */
+    double alpha;     /* artificial-viscosity coefficient */
+    double eps;       /* regulariser in 1/(r^2 + eps H^2) */
+    double dt;        /* fixed time step */
+} sph_params;
+
+/* Device pointers to one packed state in the plan's dtype.  Entries k >= dim
+ * of x and v are ignored. */
+typedef struct sph_state {
+    void* x[3];
+    void* v[3];
+    void* rho;
+} sph_state;
+
+typedef struct sph_plan sph_plan;
+
+/* Create a host-side plan for nsims simulations.  sims[s] (host) holds the
+ * parameters of simulation s and counts[s] (host) its particle count (>= 0).
+ * max_neighbors bounds the neighbours stored per particle, self included
+ * (0 = automatic: 1.6 times the particles of a support sphere at the initial
+ * spacing implied by mass and rho0, rounded up to 8).  Allocates host memory
+ * only.  Errors: INVALID_ARG, TOO_FEW_CELLS (cells per side are chosen with
+ * side >= H (1 + 2^-10) or >= H/2 (1 + 2^-10), at least 3 resp. 5 of them). */
+sph_status sph_plan_create(const sph_params* sims, int32_t nsims, const int64_t* counts,
+                           int32_t max_neighbors, sph_plan** out);
+
+/* Destroy a plan (host memory only; the workspace stays the caller's). */
+void sph_plan_destroy(sph_plan* plan);
+
+/* Workspace bytes the plan needs (host out-parameter). */
+sph_status sph_workspace_size(const sph_plan* plan, size_t* bytes);
+
+/* Total particles, simulations and the neighbour-list width of the plan. */
+sph_status sph_plan_info(const sph_plan* plan, int64_t* total_particles, int32_t* nsims,
+                         int32_t* max_neighbors);
+
+/* Bind a device workspace of at least sph_workspace_size() bytes, 256-byte
+ * aligned, and upload the plan's tables into it (asynchronous on stream).
+ * The workspace must stay valid until the plan is destroyed or rebound. */
+sph_status sph_bind(sph_plan* plan, void* workspace, size_t bytes, void* stream);
+
+/* Cell list of the state s (App. B, steps 1-2): every particle is mapped into
+ * the box, assigned to its cell, and the particles are counting-sorted by
+ * cell (cells in Morton order of cell blocks) with ties ordered by original
+ * index.  The sorted copy lives in the workspace and is what the other calls
+ * use; this call exists to time and test the sort on its own. */
+sph_status sph_build_cells(sph_plan* plan, const sph_state* s, void* stream);
+
+/* Neighbour lists of the state s (App. B step 3, Sec. 3.2): for every
+ * particle i the set N(i) = { j : |x_i - x_j| < H } (minimum image, self
+ * included) as CSR over original indices, each row ascending.  The
+ * predicate is evaluated in the plan's dtype, in this order and with no fused
+ * multiply-add: u = x - L floor(x (1/L)); d = u_i - u_j; d = d - L rint(d (1/L));
+ * r2 = (d0 d0 + d1 d1) + d2 d2; r2 < H H.
+ * offsets (device, int64[N+1]) receives row starts; nbr (device,
+ * int32[capacity]) the entries.  *total (host) receives the number of
+ * entries.  SYNCHRONOUS (waits on stream).  Returns CAPACITY, writing only
+ * offsets and *total, when total > capacity; returns CAPACITY too when a
+ * particle has more than max_neighbors neighbours. */
+sph_status sph_neighbors(sph_plan* plan, const sph_state* s, int64_t* offsets, int32_t* nbr,
+                         int64_t capacity, int64_t* total, void* stream);
+
+/* One evaluation of the update function f (App. C) at the state s:
+ *   drho_i = -rho_i sum_j V_j (v_j - v_i).gW_ij
+ *            + delta H c0 sum_j V_j 2 (rho_j - rho_i) (x_ji.gW_ij) / (r^2 + eps H^2)
+ *   a_i    = -(1/rho_i) sum_j V_j (p_i + p_j) gW_ij
+ *            + alpha H c0 (rho0/rho_i) sum_j V_j pi_ij gW_ij,
+ *   pi_ij  = (v_i - v_j).x_ij / (r^2 + eps H^2),   V_j = m / rho_j,
+ *   p      = rho0 c0^2 / 7 ((rho/rho0)^7 - 1)           (Tait, Sec. 2.3)
+ *   rho_sum_i = m sum_j W_ij   (summation density, self included)
+ * with the Wendland-C4 kernel W and gW_ij = grad_i W(x_ij) (App. A.1) and the
+ * continuity, momentum and delta-SPH terms of Sec. 2.3 (signs as in the
+ * physical equations).  drho (device, N), acc (device, dim*N, SoA rows)
+ * and rho_sum (device, N, nullable) are in original order. */
+sph_status sph_rhs(sph_plan* plan, const sph_state* s, void* drho, void* acc, void* rho_sum, void* stream);
+
+/* Advance s in place by nsteps semi-implicit Euler steps (Sec. 3.4):
+ *   v' = v + dt a,  rho' = rho + dt drho,  x' = x + dt v'.
+ * If ckpt (host array of sph_state, device pointers inside) is non-NULL, it
+ * must hold ceil(nsteps / ckpt_every) states; slot k receives the state at
+ * step k * ckpt_every (slot 0 = the input state), in original order.  These
+ * are the segment starts for checkpointed recomputation (Sec. 3: gradient
+ * checkpointing with on-the-fly recompute). */
+sph_status sph_step(sph_plan* plan, sph_state* s, int32_t nsteps, const sph_state* ckpt, int32_t ckpt_every,
+                    void* stream);
+
+/* Adjoint of one step (Sec. 2.2, vector-Jacobian product): s_n (device) is
+ * the state at the START of the step; cot (device) holds on entry the
+ * cotangents (x', v', rho') of the step's output and on exit those of
+ * (x, v, rho), in place:
+ *   vt = v'_bar + dt x'_bar,  abar = dt vt,  rbar = dt rho'_bar,
+ *   x_bar = x'_bar + (da/dx)^T abar + (ddrho/dx)^T rbar,
+ *   v_bar = vt     + (da/dv)^T abar + (ddrho/dv)^T rbar,
+ *   rho_bar = rho'_bar + (da/drho)^T abar + (ddrho/drho)^T rbar.
+ * The neighbour list is held fixed (Sec. 3.2: adjacency is not
+ * differentiated; the kernel's compact support makes the omitted terms 0). */
+sph_status sph_step_adjoint(sph_plan* plan, const sph_state* s_n, sph_state* cot, void* stream);
+
+/* Copy the per-simulation status words (host int32[nsims], SPH_FLAG_* bits)
+ * and clear them.  SYNCHRONOUS. */
+sph_status sph_poll(sph_plan* plan, int32_t* per_sim_status, void* stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* sph_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPH_H */

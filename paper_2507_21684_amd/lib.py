@@ -1,0 +1,219 @@
+"""Thin ctypes binding of libsph.so (the C ABI declared in include/sph.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP library.  If the
+library has not been built, loading raises; there is no other implementation to fall
+back to.  Tensors are torch tensors on the GPU (PyTorch provides device memory and the
+stream); states are (x[dim, N], v[dim, N], rho[N]) in the plan's dtype, contiguous.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsph.so")
+
+SPH_OK = 0
+SPH_F32 = 0
+SPH_F64 = 1
+FLAG_NONFINITE = 1
+FLAG_NEIGHBOR_OVERFLOW = 2
+ERR_NAMES = {-1: "INVALID_ARG", -2: "TOO_FEW_CELLS", -3: "CAPACITY", -4: "NONFINITE", -5: "DEVICE",
+             -6: "UNSUPPORTED", -7: "STATE"}
+
+
+class SphError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (ERR_NAMES.get(code, "?"), code, msg))
+        self.code = code
+
+
+class SphParams(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("dtype", ctypes.c_int32), ("box", ctypes.c_double),
+                ("support", ctypes.c_double), ("mass", ctypes.c_double), ("rho0", ctypes.c_double),
+                ("c0", ctypes.c_double), ("delta", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("eps", ctypes.c_double), ("dt", ctypes.c_double)]
+
+
+class SphState(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p * 3), ("v", ctypes.c_void_p * 3), ("rho", ctypes.c_void_p)]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+
+
+def lib():
+    """Open libsph.so (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libsph.so is not built (python -m paper_2507_21684_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        st = ctypes.c_int32
+        L.sph_plan_create.restype = st
+        L.sph_plan_create.argtypes = [ctypes.POINTER(SphParams), ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.c_int32, ctypes.POINTER(_VP)]
+        L.sph_plan_destroy.restype = None
+        L.sph_plan_destroy.argtypes = [_VP]
+        L.sph_workspace_size.restype = st
+        L.sph_workspace_size.argtypes = [_VP, ctypes.POINTER(ctypes.c_size_t)]
+        L.sph_plan_info.restype = st
+        L.sph_plan_info.argtypes = [_VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_int32)]
+        L.sph_bind.restype = st
+        L.sph_bind.argtypes = [_VP, _VP, ctypes.c_size_t, _VP]
+        L.sph_build_cells.restype = st
+        L.sph_build_cells.argtypes = [_VP, ctypes.POINTER(SphState), _VP]
+        L.sph_neighbors.restype = st
+        L.sph_neighbors.argtypes = [_VP, ctypes.POINTER(SphState), _VP, _VP, ctypes.c_int64,
+                                    ctypes.POINTER(ctypes.c_int64), _VP]
+        L.sph_rhs.restype = st
+        L.sph_rhs.argtypes = [_VP, ctypes.POINTER(SphState), _VP, _VP, _VP, _VP]
+        L.sph_step.restype = st
+        L.sph_step.argtypes = [_VP, ctypes.POINTER(SphState), ctypes.c_int32, ctypes.POINTER(SphState),
+                               ctypes.c_int32, _VP]
+        L.sph_step_adjoint.restype = st
+        L.sph_step_adjoint.argtypes = [_VP, ctypes.POINTER(SphState), ctypes.POINTER(SphState), _VP]
+        L.sph_poll.restype = st
+        L.sph_poll.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32), _VP]
+        L.sph_last_error.restype = ctypes.c_char_p
+        L.sph_last_error.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != SPH_OK:
+        raise SphError(rc, lib().sph_last_error().decode())
+
+
+def exported_symbols() -> List[str]:
+    """Names the binding expects libsph.so to export."""
+    return ["sph_plan_create", "sph_plan_destroy", "sph_workspace_size", "sph_plan_info", "sph_bind",
+            "sph_build_cells", "sph_neighbors", "sph_rhs", "sph_step", "sph_step_adjoint", "sph_poll",
+            "sph_last_error"]
+
+
+def _stream_ptr(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def make_params(p: dict, dtype: str) -> SphParams:
+    """dict with keys dim, L, H, m, rho0, c0, delta, alpha, eps, dt -> SphParams."""
+    return SphParams(int(p["dim"]), SPH_F64 if dtype == "f64" else SPH_F32, float(p["L"]), float(p["H"]),
+                     float(p["m"]), float(p["rho0"]), float(p["c0"]), float(p["delta"]), float(p["alpha"]),
+                     float(p["eps"]), float(p["dt"]))
+
+
+class Plan:
+    """A bound plan: host plan + device workspace for a batch of simulations."""
+
+    def __init__(self, sims: Sequence[dict], counts: Sequence[int], dtype: str = "f32",
+                 max_neighbors: int = 0, device: Optional[torch.device] = None, stream=None):
+        L = lib()
+        self.dtype = dtype
+        self.torch_dtype = torch.float64 if dtype == "f64" else torch.float32
+        self.dim = int(sims[0]["dim"])
+        n = len(sims)
+        arr = (SphParams * n)(*[make_params(p, dtype) for p in sims])
+        cnt = (ctypes.c_int64 * n)(*[int(c) for c in counts])
+        h = _VP()
+        _check(L.sph_plan_create(arr, n, cnt, int(max_neighbors), ctypes.byref(h)))
+        self._h = h
+        self.counts = [int(c) for c in counts]
+        self.offsets = np.concatenate([[0], np.cumsum(self.counts)]).astype(np.int64)
+        self.nsims = n
+        size = ctypes.c_size_t()
+        _check(L.sph_workspace_size(h, ctypes.byref(size)))
+        tot, ns, mn = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        _check(L.sph_plan_info(h, ctypes.byref(tot), ctypes.byref(ns), ctypes.byref(mn)))
+        self.N = int(tot.value)
+        self.max_neighbors = int(mn.value)
+        self.workspace_bytes = int(size.value)
+        self.device = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        _check(L.sph_bind(h, self._ws_ptr, self.workspace_bytes, _stream_ptr(stream)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.sph_plan_destroy(h)
+            self._h = None
+
+    # -- marshalling
+    def state(self, x: torch.Tensor, v: torch.Tensor, rho: torch.Tensor) -> SphState:
+        d, N = self.dim, self.N
+        for name, t, shape in (("x", x, (d, N)), ("v", v, (d, N)), ("rho", rho, (N,))):
+            if tuple(t.shape) != shape:
+                raise ValueError("%s has shape %s, expected %s" % (name, tuple(t.shape), shape))
+            if t.dtype != self.torch_dtype or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("%s must be a contiguous %s GPU tensor" % (name, self.torch_dtype))
+        s = SphState()
+        es = x.element_size()
+        for k in range(3):
+            s.x[k] = x.data_ptr() + k * N * es if k < d else None
+            s.v[k] = v.data_ptr() + k * N * es if k < d else None
+        s.rho = rho.data_ptr()
+        return s
+
+    def empty_state(self):
+        d, N = self.dim, self.N
+        return (torch.empty((d, N), dtype=self.torch_dtype, device=self.device),
+                torch.empty((d, N), dtype=self.torch_dtype, device=self.device),
+                torch.empty((N,), dtype=self.torch_dtype, device=self.device))
+
+    # -- calls
+    def build_cells(self, x, v, rho, stream=None):
+        s = self.state(x, v, rho)
+        _check(lib().sph_build_cells(self._h, ctypes.byref(s), _stream_ptr(stream)))
+
+    def neighbors(self, x, v, rho, capacity: Optional[int] = None, stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+        """CSR (offsets int64[N+1], nbr int32[total]) over original indices, rows ascending, self included."""
+        s = self.state(x, v, rho)
+        off = torch.empty(self.N + 1, dtype=torch.int64, device=self.device)
+        cap = capacity if capacity is not None else self.N * self.max_neighbors
+        nbr = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+        total = ctypes.c_int64()
+        _check(lib().sph_neighbors(self._h, ctypes.byref(s), off.data_ptr(), nbr.data_ptr(), int(cap),
+                                   ctypes.byref(total), _stream_ptr(stream)))
+        return off, nbr[: total.value]
+
+    def rhs(self, x, v, rho, rho_sum: bool = True, stream=None):
+        """(drho[N], a[dim, N], rho_sum[N] or None), original order."""
+        s = self.state(x, v, rho)
+        drho = torch.empty(self.N, dtype=self.torch_dtype, device=self.device)
+        acc = torch.empty((self.dim, self.N), dtype=self.torch_dtype, device=self.device)
+        rs = torch.empty(self.N, dtype=self.torch_dtype, device=self.device) if rho_sum else None
+        _check(lib().sph_rhs(self._h, ctypes.byref(s), drho.data_ptr(), acc.data_ptr(),
+                             rs.data_ptr() if rs is not None else None, _stream_ptr(stream)))
+        return drho, acc, rs
+
+    def step(self, x, v, rho, nsteps: int, ckpt: Optional[List[tuple]] = None, ckpt_every: int = 0, stream=None):
+        """Advance (x, v, rho) in place.  ckpt: list of ceil(nsteps/ckpt_every) (x, v, rho) slots."""
+        s = self.state(x, v, rho)
+        cp = None
+        if ckpt is not None:
+            need = (nsteps + ckpt_every - 1) // ckpt_every if ckpt_every > 0 else 0
+            if len(ckpt) < need:
+                raise ValueError("need %d checkpoint slots" % need)
+            cp = (SphState * max(need, 1))(*[self.state(*c) for c in ckpt[:need]])
+        _check(lib().sph_step(self._h, ctypes.byref(s), int(nsteps), cp, int(ckpt_every), _stream_ptr(stream)))
+
+    def step_adjoint(self, x, v, rho, gx, gv, grho, stream=None):
+        """Map the output cotangents (gx, gv, grho) of one step started at (x, v, rho) to its inputs, in place."""
+        s = self.state(x, v, rho)
+        c = self.state(gx, gv, grho)
+        _check(lib().sph_step_adjoint(self._h, ctypes.byref(s), ctypes.byref(c), _stream_ptr(stream)))
+
+    def poll(self, stream=None) -> np.ndarray:
+        out = (ctypes.c_int32 * self.nsims)()
+        _check(lib().sph_poll(self._h, out, _stream_ptr(stream)))
+        return np.frombuffer(out, dtype=np.int32).copy()

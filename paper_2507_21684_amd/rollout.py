@@ -1,0 +1,61 @@
+"""Differentiable rollouts: the HIP step and step-adjoint wrapped in a torch.autograd.Function.
+
+The forward pass advances the state with `sph_step`, keeping only a checkpoint of the state
+every K steps (the paper's gradient checkpointing, Sec. 3: only particle data are retained,
+intermediate pair quantities are recomputed).  The backward pass walks the segments in
+reverse: it recomputes the segment's states from its checkpoint with `sph_step` and applies
+`sph_step_adjoint` step by step, which returns (dP/du)^T a for one step (Sec. 2.2).
+"""
+from __future__ import annotations
+
+import math
+from typing import Optional, Tuple
+
+import torch
+
+from .lib import Plan
+
+
+class SPHRollout(torch.autograd.Function):
+    """(x0, v0, rho0) -> (x_T, v_T, rho_T) after `nsteps` steps of the plan's simulations."""
+
+    @staticmethod
+    def forward(ctx, x0: torch.Tensor, v0: torch.Tensor, rho0: torch.Tensor, plan: Plan, nsteps: int,
+                ckpt_every: int):
+        K = max(1, int(ckpt_every))
+        nseg = math.ceil(nsteps / K) if nsteps > 0 else 0
+        x, v, rho = x0.detach().clone(), v0.detach().clone(), rho0.detach().clone()
+        ckpts = [plan.empty_state() for _ in range(nseg)]
+        if nsteps > 0:
+            plan.step(x, v, rho, nsteps, ckpts, K)
+        ctx.plan, ctx.nsteps, ctx.K, ctx.nseg = plan, int(nsteps), K, nseg
+        flat = [t for c in ckpts for t in c]
+        ctx.save_for_backward(*flat)
+        return x, v, rho
+
+    @staticmethod
+    def backward(ctx, gx: Optional[torch.Tensor], gv: Optional[torch.Tensor], grho: Optional[torch.Tensor]):
+        plan: Plan = ctx.plan
+        flat = ctx.saved_tensors
+        ckpts = [tuple(flat[3 * k:3 * k + 3]) for k in range(ctx.nseg)]
+        ref = plan.empty_state()
+        cx = gx.detach().clone().contiguous() if gx is not None else torch.zeros_like(ref[0])
+        cv = gv.detach().clone().contiguous() if gv is not None else torch.zeros_like(ref[1])
+        cr = grho.detach().clone().contiguous() if grho is not None else torch.zeros_like(ref[2])
+        T, K = ctx.nsteps, ctx.K
+        for seg in reversed(range(ctx.nseg)):
+            start = seg * K
+            length = min(K, T - start)
+            states = [ckpts[seg]]
+            for _ in range(1, length):
+                s = tuple(t.clone() for t in states[-1])
+                plan.step(*s, 1)
+                states.append(s)
+            for i in reversed(range(length)):
+                plan.step_adjoint(*states[i], cx, cv, cr)
+        return cx, cv, cr, None, None, None
+
+
+def rollout(plan: Plan, x0, v0, rho0, nsteps: int, ckpt_every: int = 8) -> Tuple[torch.Tensor, ...]:
+    """Differentiable T-step rollout of all simulations of `plan`."""
+    return SPHRollout.apply(x0, v0, rho0, plan, nsteps, ckpt_every)

@@ -1,0 +1,104 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every symbol
+include/sph.h declares, and plan creation validates its arguments."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2507_21684_amd import lib as L
+from paper_2507_21684_amd.inputs import SimSpec
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "sph.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sph_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    lib = L.lib()
+    declared = _declared()
+    assert len(declared) >= 12
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(L.exported_symbols()) == declared
+
+
+def _plan(params, counts, maxn=0):
+    arr = (L.SphParams * len(params))(*params)
+    cnt = (ctypes.c_int64 * len(counts))(*counts)
+    h = ctypes.c_void_p()
+    rc = L.lib().sph_plan_create(arr, len(params), cnt, maxn, ctypes.byref(h))
+    return rc, h
+
+
+def _p(spec, dtype="f32", **kw):
+    d = spec.params()
+    d.update(kw)
+    return L.make_params(d, dtype)
+
+
+def test_plan_create_and_sizes():
+    spec = SimSpec(2, 256)
+    rc, h = _plan([_p(spec)], [spec.n])
+    assert rc == 0
+    size = ctypes.c_size_t()
+    assert L.lib().sph_workspace_size(h, ctypes.byref(size)) == 0
+    tot, ns, mn = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+    assert L.lib().sph_plan_info(h, ctypes.byref(tot), ctypes.byref(ns), ctypes.byref(mn)) == 0
+    assert tot.value == 65536 and ns.value == 1
+    # automatic width: 1.6 x (pi H^2 / dx^2) rounded up to 8
+    assert mn.value == 88
+    # the neighbour list dominates: width x padded N x 4 bytes, plus O(N) arrays
+    assert mn.value * 65536 * 4 < size.value < mn.value * 65536 * 4 + 400 * 65536
+    L.lib().sph_plan_destroy(h)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(dim=4), -1),
+    (dict(H=0.6), -1),          # 2H >= L
+    (dict(m=-1.0), -1),
+    (dict(eps=0.0), -1),
+    (dict(H=0.4), -2),          # L/H < 3: fewer than 3 cells of side >= H
+])
+def test_plan_create_rejects(kw, code):
+    spec = SimSpec(2, 16)
+    d = spec.params()
+    d.update(kw)
+    p = L.make_params(d, "f32")
+    rc, h = _plan([p], [spec.n])
+    assert rc == code, L.lib().sph_last_error()
+    assert L.lib().sph_last_error()
+
+
+def test_plan_rejects_mixed_batches():
+    a, b = SimSpec(2, 16), SimSpec(3, 16)
+    rc, _ = _plan([_p(a), _p(b)], [a.n, b.n])
+    assert rc == -1
+    rc, _ = _plan([_p(a), _p(a, "f64")], [a.n, a.n])
+    assert rc == -1
+    rc, _ = _plan([_p(a)], [-5])
+    assert rc == -1
+
+
+def test_batched_plan():
+    from paper_2507_21684_amd.inputs import batched_512_specs
+    sims, _ = batched_512_specs()
+    params = [_p(s) for s in sims]
+    rc, h = _plan(params, [s.n for s in sims])
+    assert rc == 0, L.lib().sph_last_error()
+    tot = ctypes.c_int64()
+    L.lib().sph_plan_info(h, ctypes.byref(tot), None, None)
+    assert tot.value == sum(s.n for s in sims)
+    L.lib().sph_plan_destroy(h)
+
+
+def test_calls_need_bound_plan():
+    spec = SimSpec(2, 16)
+    rc, h = _plan([_p(spec)], [spec.n])
+    st = L.SphState()
+    assert L.lib().sph_build_cells(h, ctypes.byref(st), None) == -7
+    L.lib().sph_plan_destroy(h)
