@@ -99,11 +99,16 @@ typedef struct sph_plan sph_plan;
  * parameters of simulation s and counts[s] (host) its particle count (>= 0).
  * max_neighbors bounds the neighbours stored per particle, self included
  * (0 = automatic: 1.6 times the particles of a support sphere at the initial
- * spacing implied by mass and rho0, rounded up to 8).  Allocates host memory
- * only.  Errors: INVALID_ARG, TOO_FEW_CELLS (cells per side are chosen with
- * side >= H (1 + 2^-10) or >= H/2 (1 + 2^-10), at least 3 resp. 5 of them). */
+ * spacing implied by mass and rho0; rounded up to a multiple of 8).
+ * tape_depth is the number of steps whose sorted states and neighbour lists
+ * the workspace can hold at once; sph_rollout_backward() needs it to be at
+ * least the checkpoint interval (0 = no tape).  Allocates host memory only.
+ * Errors: INVALID_ARG, TOO_FEW_CELLS (cells per side are chosen with side
+ * >= H/2 (1 + 2^-10), at least 5 of them, else side >= H (1 + 2^-10), at
+ * least 3 of them), UNSUPPORTED (more than 2^31 particles or 1024 cell blocks
+ * of 4^2 / 2^3 cells per side). */
 sph_status sph_plan_create(const sph_params* sims, int32_t nsims, const int64_t* counts,
-                           int32_t max_neighbors, sph_plan** out);
+                           int32_t max_neighbors, int32_t tape_depth, sph_plan** out);
 
 /* Destroy a plan (host memory only; the workspace stays the caller's). */
 void sph_plan_destroy(sph_plan* plan);
@@ -114,6 +119,15 @@ sph_status sph_workspace_size(const sph_plan* plan, size_t* bytes);
 /* Total particles, simulations and the neighbour-list width of the plan. */
 sph_status sph_plan_info(const sph_plan* plan, int64_t* total_particles, int32_t* nsims,
                          int32_t* max_neighbors);
+
+/* Lanes that share one particle in the forward sweep and in the adjoint sweep
+ * (1, 2 or 4).  A particle's pair sums are always formed as four partial sums
+ * over list positions k mod 4 combined as (s0 + s1) + (s2 + s3), so results
+ * are bitwise the same for every setting; only speed changes.  The default
+ * gives every SIMD several wavefronts (4 up to 2^18 particles, 2 up to 2^20,
+ * else 1). */
+sph_status sph_set_tuning(sph_plan* plan, int32_t lanes_fwd, int32_t lanes_adj);
+sph_status sph_get_tuning(const sph_plan* plan, int32_t* lanes_fwd, int32_t* lanes_adj);
 
 /* Bind a device workspace of at least sph_workspace_size() bytes, 256-byte
  * aligned, and upload the plan's tables into it (asynchronous on stream).
@@ -177,9 +191,45 @@ sph_status sph_step(sph_plan* plan, sph_state* s, int32_t nsteps, const sph_stat
  * differentiated; the kernel's compact support makes the omitted terms 0). */
 sph_status sph_step_adjoint(sph_plan* plan, const sph_state* s_n, sph_state* cot, void* stream);
 
+/* Gradient of a checkpointed rollout (Sec. 3: checkpoints of the particle
+ * state only, intermediate quantities recomputed; Sec. 2.2: chained
+ * vector-Jacobian products).  ckpt (host array of sph_state, device pointers)
+ * holds the ceil(nsteps / ckpt_every) checkpoints that sph_step() wrote for the
+ * same initial state, nsteps and ckpt_every.  cot (device) holds on entry the
+ * cotangents of the state after nsteps steps and on exit those of the initial
+ * state, in place.  Segments are processed last to first: each is recomputed
+ * from its checkpoint keeping every step's sorted state and neighbour lists in
+ * the workspace tape, then its steps' adjoints run in reverse on the taped
+ * data (each equal to sph_step_adjoint() on that step's start state).
+ * Needs tape_depth >= min(ckpt_every, nsteps) (else CAPACITY). */
+sph_status sph_rollout_backward(sph_plan* plan, const sph_state* ckpt, int32_t nsteps, int32_t ckpt_every,
+                                sph_state* cot, void* stream);
+
 /* Copy the per-simulation status words (host int32[nsims], SPH_FLAG_* bits)
  * and clear them.  SYNCHRONOUS. */
 sph_status sph_poll(sph_plan* plan, int32_t* per_sim_status, void* stream);
+
+/* Number of directed neighbour pairs (i, j), j != i, found by the neighbour-list builds
+ * since the last call (host out-parameter), then reset.  This is the unit of the pair
+ * interaction rate.  SYNCHRONOUS. */
+sph_status sph_pair_count(sph_plan* plan, int64_t* pairs, void* stream);
+
+/* Kernel classes timed by the profiler. */
+#define SPH_KERN_SORT 0      /* cell assignment, scan, scatter, within-cell order, gather */
+#define SPH_KERN_BUILD 1     /* neighbour-list build */
+#define SPH_KERN_SWEEP 2     /* fused forward sweep (RHS + integrator) */
+#define SPH_KERN_ADJOINT 3   /* adjoint sweep */
+#define SPH_KERN_OTHER 4     /* unsort, adjoint prologue */
+#define SPH_KERN_COUNT 5
+
+/* Enable (1) or disable (0) per-launch HIP-event timing of the plan's kernels; events are
+ * recorded on the stream each kernel is launched on. */
+sph_status sph_profile_enable(sph_plan* plan, int32_t enable);
+
+/* Accumulated device time in milliseconds (host double[SPH_KERN_COUNT]) and launch counts
+ * (host int64[SPH_KERN_COUNT]) per kernel class since the last read, then reset.
+ * SYNCHRONOUS (waits for the recorded events). */
+sph_status sph_profile_read(sph_plan* plan, double* ms, int64_t* launches);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* sph_last_error(void);

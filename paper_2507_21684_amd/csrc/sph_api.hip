@@ -36,6 +36,12 @@ sph_status fail(sph_status code, const std::string& msg)
         if (e_ != hipSuccess) return fail(SPH_ERR_DEVICE, std::string("launch ") + name + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+#define RC_TRY(expr)                  \
+    do {                              \
+        sph_status rc_ = (expr);      \
+        if (rc_ != SPH_OK) return rc_; \
+    } while (0)
+
 constexpr double kCellMargin = 1.0 + 1.0 / 1024.0;  // cell side exceeds H/sub by more than rounding
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -57,30 +63,58 @@ uint64_t morton(int bx, int by, int bz, int dim)
 }
 
 struct SimHost {
-    int64_t p0, n;
-    int32_t cell0, blk0, nc, sub, B, nb, Bd, nblk;
+    int64_t p0, n, st0;
+    int32_t cell0, blk0, nc, sub, B, nb, Bd, nblk, ncu;
+};
+
+// Per-step data kept in one tape slot: the sorted state, the packed per-particle data read
+// by the sweeps, the original indices and the neighbour lists.
+struct SlotLayout {
+    size_t SA, jd0, jd1, orig, nbr, cnt;
 };
 
 }  // namespace
 
 struct sph_plan {
-    int32_t dim = 0, dtype = 0, nsims = 0, maxnbr = 0;
-    int64_t N = 0, ld = 0;
+    int32_t dim = 0, dtype = 0, nsims = 0, width = 0, tape_depth = 0, nslots = 2;
+    int32_t lpp_fwd = 4, lpp_adj = 4;
+    int64_t N = 0;
     int64_t ncell = 0, nblk = 0;
     std::vector<sph_params> prm;
     std::vector<SimHost> sim;
-    std::vector<int32_t> h_psim, h_blk_sim, h_blk_coord, h_blk_rank;
+    std::vector<int32_t> h_psim, h_cell_sim, h_blk_coord, h_blk_rank, h_stencil;
+    int64_t nstencil = 0;
     std::vector<unsigned char> h_simc;
     // workspace layout (byte offsets)
-    size_t o_simc = 0, o_psim = 0, o_blk_sim = 0, o_blk_coord = 0, o_blk_rank = 0;
+    size_t o_simc = 0, o_psim = 0, o_cell_sim = 0, o_blk_coord = 0, o_blk_rank = 0, o_stencil = 0;
     size_t o_cell_count = 0, o_cell_start = 0, o_part = 0, o_cell_of = 0, o_slot_of = 0, o_tmp = 0;
-    size_t o_orig[2] = {0, 0}, o_SA = 0, o_SB = 0, o_jd0 = 0, o_jd1 = 0, o_jdA = 0, o_jdB = 0;
-    size_t o_nbr = 0, o_cnt = 0, o_status = 0, o_part64 = 0;
+    size_t o_SB = 0, o_jdA = 0, o_jdB = 0, o_status = 0, o_part64 = 0, o_pairs = 0, o_ticket = 0;
+    std::vector<SlotLayout> slot;
     int64_t nparts = 0, nparts64 = 0;
     size_t bytes = 0;
     char* ws = nullptr;
     bool bound = false;
-    int cur_orig = 0;  // index of the orig array written by the last sort
+    // per-launch timing (sph_profile_enable)
+    bool prof = false;
+    struct Ev {
+        hipEvent_t a, b;
+        int kind;
+    };
+    std::vector<Ev> ev_used;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+    double prof_ms[SPH_KERN_COUNT] = {0, 0, 0, 0, 0};
+    int64_t prof_n[SPH_KERN_COUNT] = {0, 0, 0, 0, 0};
+    ~sph_plan()
+    {
+        for (auto& e : ev_used) {
+            (void)hipEventDestroy(e.a);
+            (void)hipEventDestroy(e.b);
+        }
+        for (auto& e : ev_pool) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+    }
 };
 
 namespace {
@@ -89,6 +123,38 @@ template <typename T>
 T* wsp(const sph_plan* p, size_t off) { return reinterpret_cast<T*>(p->ws + off); }
 
 size_t tsize(const sph_plan* p) { return p->dtype == SPH_F64 ? 8 : 4; }
+
+// Brackets a group of launches of one kernel class with HIP events on the launch stream
+// when profiling is enabled.
+struct ProfScope {
+    sph_plan* P;
+    hipStream_t st;
+    int kind;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(sph_plan* P_, hipStream_t st_, int kind_) : P(P_), st(st_), kind(kind_)
+    {
+        if (!P->prof) return;
+        if (P->ev_pool.empty()) {
+            hipEvent_t e1, e2;
+            if (hipEventCreate(&e1) != hipSuccess) return;
+            if (hipEventCreate(&e2) != hipSuccess) {
+                (void)hipEventDestroy(e1);
+                return;
+            }
+            P->ev_pool.push_back({e1, e2});
+        }
+        a = P->ev_pool.back().first;
+        b = P->ev_pool.back().second;
+        P->ev_pool.pop_back();
+        (void)hipEventRecord(a, st);
+    }
+    ~ProfScope()
+    {
+        if (!a) return;
+        (void)hipEventRecord(b, st);
+        P->ev_used.push_back({a, b, kind});
+    }
+};
 
 template <typename T>
 void fill_simconst(const sph_plan* P, std::vector<unsigned char>& out)
@@ -129,6 +195,8 @@ void fill_simconst(const sph_plan* P, std::vector<unsigned char>& out)
         c.B = h.B;
         c.nb = h.nb;
         c.Bd = h.Bd;
+        c.ncu = h.ncu;
+        c.st0 = h.st0;
         sc[s] = c;
     }
 }
@@ -160,31 +228,33 @@ StatePtrs<T, D> ws_state(const sph_plan* P, size_t off)
     return p;
 }
 
+// Exclusive scan in two launches: tile sums with the last workgroup scanning them, then the
+// tiles' own scans plus their offsets.
 template <typename I>
-sph_status scan_exclusive(sph_plan* P, I* in, int64_t n, I* part, int64_t np, I* out, bool zero_in, hipStream_t st)
+sph_status scan_exclusive(I* in, int64_t n, I* part, unsigned int* ticket, I* out, bool zero_in, hipStream_t st)
 {
     if (n == 0) {
         k_fill<I><<<1, 1, 0, st>>>(out, 1, I(0));
         LAUNCH_CHECK("fill");
         return SPH_OK;
     }
-    unsigned g = grid_for(n, kScanTile);
-    k_scan_reduce<I><<<g, kScanThreads, 0, st>>>(in, n, part);
+    const unsigned g = grid_for(n, kScanTile);
+    k_scan_reduce_last<I><<<g, kScanThreads, 0, st>>>(in, n, part, ticket);
     LAUNCH_CHECK("scan_reduce");
-    k_scan_top<I><<<1, 1024, 0, st>>>(part, (int64_t)g);
-    LAUNCH_CHECK("scan_top");
     k_scan_apply<I><<<g, kScanThreads, 0, st>>>(in, n, part, (int64_t)g, out, zero_in ? 1 : 0);
     LAUNCH_CHECK("scan_apply");
-    (void)np;
     return SPH_OK;
 }
 
-// Sort `src` (orig ids in orig_in, or identity when null) into the workspace's sorted state SA.
+// Cell list of `src` (original indices in orig_in, or the identity when null) into tape slot
+// `slot`: sorted state, packed sweep data and original indices.
 template <typename T, int D>
-sph_status sort_into_SA(sph_plan* P, StatePtrs<T, D> src, const int32_t* orig_in, hipStream_t st)
+sph_status sort_into(sph_plan* P, StatePtrs<T, D> src, const int32_t* orig_in, int slot, hipStream_t st,
+                     bool assigned = false)
 {
     const int64_t N = P->N;
     if (N == 0) return SPH_OK;
+    const SlotLayout& L = P->slot[slot];
     int32_t* cell_count = wsp<int32_t>(P, P->o_cell_count);
     int32_t* cell_start = wsp<int32_t>(P, P->o_cell_start);
     int32_t* cell_of = wsp<int32_t>(P, P->o_cell_of);
@@ -194,56 +264,114 @@ sph_status sort_into_SA(sph_plan* P, StatePtrs<T, D> src, const int32_t* orig_in
     const SimConst<T>* simc = wsp<SimConst<T>>(P, P->o_simc);
     const int32_t* blk_rank = wsp<int32_t>(P, P->o_blk_rank);
     int32_t* status = wsp<int32_t>(P, P->o_status);
+    int32_t* orig_out = wsp<int32_t>(P, L.orig);
+    if (orig_in == orig_out) return fail(SPH_ERR_STATE, "sort source and destination slot coincide");
     const unsigned g = grid_for(N, 256);
-    k_assign<T, D><<<g, 256, 0, st>>>(N, src, psim, simc, blk_rank, cell_count, cell_of, slot_of, status);
-    LAUNCH_CHECK("assign");
-    sph_status rc = scan_exclusive<int32_t>(P, cell_count, P->ncell, wsp<int32_t>(P, P->o_part), P->nparts, cell_start,
-                                            true, st);
-    if (rc != SPH_OK) return rc;
+    ProfScope prof(P, st, SPH_KERN_SORT);
+    if (!assigned) {
+        k_assign<T, D><<<g, 256, 0, st>>>(N, src, psim, simc, blk_rank, cell_count, cell_of, slot_of, status);
+        LAUNCH_CHECK("assign");
+    }
+    RC_TRY(scan_exclusive<int32_t>(cell_count, P->ncell, wsp<int32_t>(P, P->o_part),
+                                   wsp<unsigned int>(P, P->o_ticket), cell_start, true, st));
     k_scatter<<<g, 256, 0, st>>>(N, cell_of, slot_of, cell_start, tmp);
     LAUNCH_CHECK("scatter");
-    const int out = orig_in == wsp<int32_t>(P, P->o_orig[0]) ? 1 : 0;
-    int32_t* orig_out = wsp<int32_t>(P, P->o_orig[out]);
-    k_order_gather<T, D><<<g, 256, 0, st>>>(N, tmp, cell_of, cell_start, orig_in, src, ws_state<T, D>(P, P->o_SA),
-                                            orig_out, wsp<vec4_t<T>>(P, P->o_jd0), wsp<vec4_t<T>>(P, P->o_jd1), psim,
+    k_order_gather<T, D><<<g, 256, 0, st>>>(N, tmp, cell_of, cell_start, orig_in, src, ws_state<T, D>(P, L.SA),
+                                            orig_out, wsp<vec4_t<T>>(P, L.jd0), wsp<vec4_t<T>>(P, L.jd1), psim,
                                             simc);
     LAUNCH_CHECK("order_gather");
-    P->cur_orig = out;
     return SPH_OK;
 }
 
+// Neighbour lists of the state sorted into `slot` (needs the cell starts of that sort, so it
+// runs before the next sort).
 template <typename T, int D>
-sph_status build_lists(sph_plan* P, hipStream_t st)
+sph_status build_lists(sph_plan* P, int slot, hipStream_t st)
 {
-    if (P->N == 0 || P->nblk == 0) return SPH_OK;
-    k_build_list<T, D><<<(unsigned)P->nblk, 64, 0, st>>>(
-        wsp<int32_t>(P, P->o_blk_sim), wsp<int32_t>(P, P->o_blk_coord), wsp<int32_t>(P, P->o_blk_rank),
-        wsp<SimConst<T>>(P, P->o_simc), wsp<int32_t>(P, P->o_cell_start), wsp<vec4_t<T>>(P, P->o_jd0), P->ld,
-        P->maxnbr, wsp<int32_t>(P, P->o_nbr), wsp<int32_t>(P, P->o_cnt), wsp<int32_t>(P, P->o_status));
+    if (P->N == 0 || P->ncell == 0) return SPH_OK;
+    const SlotLayout& L = P->slot[slot];
+    ProfScope prof(P, st, SPH_KERN_BUILD);
+    k_build_list<T, D><<<(unsigned)P->ncell, 64, 0, st>>>(
+        wsp<int32_t>(P, P->o_cell_sim), wsp<int32_t>(P, P->o_stencil), wsp<SimConst<T>>(P, P->o_simc),
+        wsp<int32_t>(P, P->o_cell_start), wsp<vec4_t<T>>(P, L.jd0), P->width,
+        wsp<int32_t>(P, L.nbr), wsp<int32_t>(P, L.cnt), wsp<int32_t>(P, P->o_status),
+        wsp<unsigned long long>(P, P->o_pairs));
     LAUNCH_CHECK("build_list");
     return SPH_OK;
 }
 
+template <typename T, int D, int MODE, int LPP>
+void launch_sweep(sph_plan* P, const SlotLayout& L, T* drho, T* acc, T* rhosum, NextCells next, hipStream_t st)
+{
+    const int64_t lanes = P->N * LPP;
+    k_sweep<T, D, MODE, LPP><<<grid_for(lanes, 256), 256, 0, st>>>(
+        P->N, P->width, wsp<int32_t>(P, L.nbr), wsp<int32_t>(P, L.cnt), wsp<vec4_t<T>>(P, L.jd0),
+        wsp<vec4_t<T>>(P, L.jd1), ws_state<T, D>(P, L.SA), ws_state<T, D>(P, P->o_SB), wsp<int32_t>(P, L.orig), drho,
+        acc, rhosum, wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc), wsp<int32_t>(P, P->o_status), next);
+}
+
+// Forward sweep over the state in `slot`: MODE step integrates into SB (same sorted order),
+// MODE rhs writes the derivatives to the caller's arrays in original order.  With
+// assign_next (MODE step only) the sweep also does the cell assignment of the next sort.
 template <typename T, int D, int MODE>
-sph_status sweep(sph_plan* P, T* drho, T* acc, T* rhosum, hipStream_t st)
+sph_status sweep(sph_plan* P, int slot, T* drho, T* acc, T* rhosum, hipStream_t st, bool assign_next = false)
 {
     if (P->N == 0) return SPH_OK;
-    k_sweep<T, D, MODE><<<grid_for(P->N, 256), 256, 0, st>>>(
-        P->N, P->ld, P->maxnbr, wsp<int32_t>(P, P->o_nbr), wsp<int32_t>(P, P->o_cnt), wsp<vec4_t<T>>(P, P->o_jd0),
-        wsp<vec4_t<T>>(P, P->o_jd1), ws_state<T, D>(P, P->o_SA), ws_state<T, D>(P, P->o_SB),
-        wsp<int32_t>(P, P->o_orig[P->cur_orig]), drho, acc, rhosum, wsp<int32_t>(P, P->o_psim),
-        wsp<SimConst<T>>(P, P->o_simc), wsp<int32_t>(P, P->o_status));
+    const SlotLayout& L = P->slot[slot];
+    NextCells next{wsp<int32_t>(P, P->o_blk_rank), nullptr, wsp<int32_t>(P, P->o_cell_of),
+                   wsp<int32_t>(P, P->o_slot_of)};
+    if (assign_next) next.cell_count = wsp<int32_t>(P, P->o_cell_count);
+    ProfScope prof(P, st, SPH_KERN_SWEEP);
+    switch (P->lpp_fwd) {
+    case 1: launch_sweep<T, D, MODE, 1>(P, L, drho, acc, rhosum, next, st); break;
+    case 2: launch_sweep<T, D, MODE, 2>(P, L, drho, acc, rhosum, next, st); break;
+    default: launch_sweep<T, D, MODE, 4>(P, L, drho, acc, rhosum, next, st); break;
+    }
     LAUNCH_CHECK("sweep");
     return SPH_OK;
 }
 
 template <typename T, int D>
-sph_status unsort_SB(sph_plan* P, StatePtrs<T, D> dst, hipStream_t st)
+sph_status unsort_SB(sph_plan* P, int slot, StatePtrs<T, D> dst, hipStream_t st)
 {
     if (P->N == 0) return SPH_OK;
+    ProfScope prof(P, st, SPH_KERN_OTHER);
     k_unsort<T, D><<<grid_for(P->N, 256), 256, 0, st>>>(P->N, ws_state<T, D>(P, P->o_SB),
-                                                        wsp<int32_t>(P, P->o_orig[P->cur_orig]), dst);
+                                                        wsp<int32_t>(P, P->slot[slot].orig), dst);
     LAUNCH_CHECK("unsort");
+    return SPH_OK;
+}
+
+template <typename T, int D, int LPP>
+void launch_adj(sph_plan* P, const SlotLayout& L, StatePtrs<T, D> cot, hipStream_t st)
+{
+    const int64_t lanes = P->N * LPP;
+    k_adj_sweep<T, D, LPP><<<grid_for(lanes, 256), 256, 0, st>>>(
+        P->N, P->width, wsp<int32_t>(P, L.nbr), wsp<int32_t>(P, L.cnt), wsp<vec4_t<T>>(P, L.jd0),
+        wsp<vec4_t<T>>(P, L.jd1), wsp<vec4_t<T>>(P, P->o_jdA), wsp<vec4_t<T>>(P, P->o_jdB), wsp<int32_t>(P, L.orig),
+        cot, wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc), wsp<int32_t>(P, P->o_status));
+}
+
+// Adjoint of the step that starts from the state in `slot` (sorted with its lists built).
+template <typename T, int D>
+sph_status adjoint(sph_plan* P, int slot, StatePtrs<T, D> cot, hipStream_t st)
+{
+    if (P->N == 0) return SPH_OK;
+    const SlotLayout& L = P->slot[slot];
+    {
+        ProfScope prof(P, st, SPH_KERN_OTHER);
+        k_adj_prologue<T, D><<<grid_for(P->N, 256), 256, 0, st>>>(
+            P->N, wsp<int32_t>(P, L.orig), cot, ws_state<T, D>(P, L.SA), wsp<vec4_t<T>>(P, P->o_jdA),
+            wsp<vec4_t<T>>(P, P->o_jdB), wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc));
+        LAUNCH_CHECK("adj_prologue");
+    }
+    ProfScope prof(P, st, SPH_KERN_ADJOINT);
+    switch (P->lpp_adj) {
+    case 1: launch_adj<T, D, 1>(P, L, cot, st); break;
+    case 2: launch_adj<T, D, 2>(P, L, cot, st); break;
+    default: launch_adj<T, D, 4>(P, L, cot, st); break;
+    }
+    LAUNCH_CHECK("adj_sweep");
     return SPH_OK;
 }
 
@@ -284,62 +412,79 @@ sph_status check_bound(const sph_plan* P)
 template <typename T, int D>
 sph_status do_build_cells(sph_plan* P, const sph_state* s, hipStream_t st)
 {
-    return sort_into_SA<T, D>(P, user_state<T, D>(s), nullptr, st);
+    return sort_into<T, D>(P, user_state<T, D>(s), nullptr, 0, st);
 }
 
 template <typename T, int D>
 sph_status do_rhs(sph_plan* P, const sph_state* s, void* drho, void* acc, void* rhosum, hipStream_t st)
 {
-    sph_status rc = sort_into_SA<T, D>(P, user_state<T, D>(s), nullptr, st);
-    if (rc == SPH_OK) rc = build_lists<T, D>(P, st);
-    if (rc == SPH_OK) rc = sweep<T, D, kModeRhs>(P, (T*)drho, (T*)acc, (T*)rhosum, st);
-    return rc;
+    RC_TRY((sort_into<T, D>(P, user_state<T, D>(s), nullptr, 0, st)));
+    RC_TRY((build_lists<T, D>(P, 0, st)));
+    return sweep<T, D, kModeRhs>(P, 0, (T*)drho, (T*)acc, (T*)rhosum, st);
+}
+
+// nsteps forward steps from `src` (original order).  Without a tape, steps alternate between
+// slots 0 and 1; with a tape, step t keeps its sorted state and lists in slot t.  The sweep of
+// the last step is skipped when `last_sweep` is false (a recomputation needs only the states
+// the adjoint steps start from).  *last_slot receives the slot of the last step.
+template <typename T, int D>
+sph_status run_steps(sph_plan* P, StatePtrs<T, D> src, int32_t nsteps, bool tape, bool last_sweep,
+                     const sph_state* ckpt, int32_t every, int* last_slot, hipStream_t st)
+{
+    int slot = 0;
+    for (int32_t t = 0; t < nsteps; ++t) {
+        const int next = tape ? t : (t & 1);
+        if (t == 0) RC_TRY((sort_into<T, D>(P, src, nullptr, next, st)));
+        else
+            RC_TRY((sort_into<T, D>(P, ws_state<T, D>(P, P->o_SB), wsp<int32_t>(P, P->slot[slot].orig), next, st,
+                                    true)));
+        slot = next;
+        RC_TRY((build_lists<T, D>(P, slot, st)));
+        // the sweep assigns cells for the next step's sort whenever one follows
+        if (t + 1 < nsteps || last_sweep)
+            RC_TRY((sweep<T, D, kModeStep>(P, slot, nullptr, nullptr, nullptr, st, t + 1 < nsteps)));
+        if (ckpt && (t + 1) % every == 0 && t + 1 < nsteps)
+            RC_TRY((unsort_SB<T, D>(P, slot, user_state<T, D>(&ckpt[(t + 1) / every]), st)));
+    }
+    *last_slot = slot;
+    return SPH_OK;
 }
 
 template <typename T, int D>
 sph_status do_step(sph_plan* P, sph_state* s, int32_t nsteps, const sph_state* ckpt, int32_t every, hipStream_t st)
 {
+    if (nsteps == 0) return SPH_OK;
     StatePtrs<T, D> user = user_state<T, D>(s);
-    if (ckpt && nsteps > 0) {
-        sph_status rc = copy_state<T, D>(P, user_state<T, D>(&ckpt[0]), user, st);
-        if (rc != SPH_OK) return rc;
-    }
-    for (int32_t t = 0; t < nsteps; ++t) {
-        sph_status rc;
-        if (t == 0) rc = sort_into_SA<T, D>(P, user, nullptr, st);
-        else rc = sort_into_SA<T, D>(P, ws_state<T, D>(P, P->o_SB), wsp<int32_t>(P, P->o_orig[P->cur_orig]), st);
-        if (rc == SPH_OK) rc = build_lists<T, D>(P, st);
-        if (rc == SPH_OK) rc = sweep<T, D, kModeStep>(P, nullptr, nullptr, nullptr, st);
-        if (rc != SPH_OK) return rc;
-        if (ckpt && (t + 1) % every == 0 && t + 1 < nsteps) {
-            rc = unsort_SB<T, D>(P, user_state<T, D>(&ckpt[(t + 1) / every]), st);
-            if (rc != SPH_OK) return rc;
-        }
-    }
-    if (nsteps > 0) return unsort_SB<T, D>(P, user, st);
-    return SPH_OK;
+    if (ckpt) RC_TRY((copy_state<T, D>(P, user_state<T, D>(&ckpt[0]), user, st)));
+    int last = 0;
+    RC_TRY((run_steps<T, D>(P, user, nsteps, false, true, ckpt, every, &last, st)));
+    return unsort_SB<T, D>(P, last, user, st);
 }
 
 template <typename T, int D>
 sph_status do_step_adjoint(sph_plan* P, const sph_state* sn, sph_state* cot, hipStream_t st)
 {
-    sph_status rc = sort_into_SA<T, D>(P, user_state<T, D>(sn), nullptr, st);
-    if (rc == SPH_OK) rc = build_lists<T, D>(P, st);
-    if (rc != SPH_OK) return rc;
-    if (P->N == 0) return SPH_OK;
-    const unsigned g = grid_for(P->N, 256);
-    const int32_t* orig = wsp<int32_t>(P, P->o_orig[P->cur_orig]);
-    k_adj_prologue<T, D><<<g, 256, 0, st>>>(P->N, orig, user_state<T, D>(cot), ws_state<T, D>(P, P->o_SA),
-                                            wsp<vec4_t<T>>(P, P->o_jdA), wsp<vec4_t<T>>(P, P->o_jdB),
-                                            wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc));
-    LAUNCH_CHECK("adj_prologue");
-    k_adj_sweep<T, D><<<g, 256, 0, st>>>(P->N, P->ld, P->maxnbr, wsp<int32_t>(P, P->o_nbr),
-                                         wsp<int32_t>(P, P->o_cnt), wsp<vec4_t<T>>(P, P->o_jd0),
-                                         wsp<vec4_t<T>>(P, P->o_jd1), wsp<vec4_t<T>>(P, P->o_jdA),
-                                         wsp<vec4_t<T>>(P, P->o_jdB), orig, user_state<T, D>(cot),
-                                         wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc),
-                                         wsp<int32_t>(P, P->o_status));
-    LAUNCH_CHECK("adj_sweep");
+    RC_TRY((sort_into<T, D>(P, user_state<T, D>(sn), nullptr, 0, st)));
+    RC_TRY((build_lists<T, D>(P, 0, st)));
+    return adjoint<T, D>(P, 0, user_state<T, D>(cot), st);
+}
+
+// Checkpointed backward pass: segments in reverse; each is recomputed from its checkpoint
+// with its sorted states and neighbour lists kept in the tape, then its adjoint steps run in
+// reverse on the taped data.
+template <typename T, int D>
+sph_status do_rollout_backward(sph_plan* P, const sph_state* ckpt, int32_t nsteps, int32_t every, sph_state* cot,
+                               hipStream_t st)
+{
+    if (nsteps == 0) return SPH_OK;
+    const int32_t nseg = (nsteps + every - 1) / every;
+    StatePtrs<T, D> c = user_state<T, D>(cot);
+    for (int32_t seg = nseg - 1; seg >= 0; --seg) {
+        const int32_t len = std::min(every, nsteps - seg * every);
+        int last = 0;
+        RC_TRY((run_steps<T, D>(P, user_state<T, D>(&ckpt[seg]), len, true, false, nullptr, 1, &last, st)));
+        for (int32_t t = len - 1; t >= 0; --t) RC_TRY((adjoint<T, D>(P, t, c, st)));
+    }
     return SPH_OK;
 }
 
@@ -347,33 +492,31 @@ template <typename T, int D>
 sph_status do_neighbors(sph_plan* P, const sph_state* s, int64_t* offsets, int32_t* nbr, int64_t capacity,
                         int64_t* total, hipStream_t st)
 {
-    sph_status rc = sort_into_SA<T, D>(P, user_state<T, D>(s), nullptr, st);
-    if (rc == SPH_OK) rc = build_lists<T, D>(P, st);
-    if (rc != SPH_OK) return rc;
+    RC_TRY((sort_into<T, D>(P, user_state<T, D>(s), nullptr, 0, st)));
+    RC_TRY((build_lists<T, D>(P, 0, st)));
     const int64_t N = P->N;
-    const int32_t* orig = wsp<int32_t>(P, P->o_orig[P->cur_orig]);
+    const SlotLayout& L = P->slot[0];
+    const int32_t* orig = wsp<int32_t>(P, L.orig);
     int64_t* rowcnt = wsp<int64_t>(P, P->o_part64) + (P->nparts64 + 1);
     if (N > 0) {
-        k_export_counts<<<grid_for(N, 256), 256, 0, st>>>(N, orig, wsp<int32_t>(P, P->o_cnt), P->maxnbr, rowcnt);
+        k_export_counts<<<grid_for(N, 256), 256, 0, st>>>(N, orig, wsp<int32_t>(P, L.cnt), P->width, rowcnt);
         LAUNCH_CHECK("export_counts");
     }
-    rc = scan_exclusive<int64_t>(P, rowcnt, N, wsp<int64_t>(P, P->o_part64), P->nparts64, offsets, false, st);
-    if (rc != SPH_OK) return rc;
+    RC_TRY(scan_exclusive<int64_t>(rowcnt, N, wsp<int64_t>(P, P->o_part64), wsp<unsigned int>(P, P->o_ticket),
+                                   offsets, false, st));
     int64_t tot = 0;
     HIP_TRY(hipMemcpyAsync(&tot, offsets + N, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     std::vector<int32_t> stat(P->nsims, 0);
-    if (P->nsims > 0)
-        HIP_TRY(hipMemcpyAsync(stat.data(), wsp<int32_t>(P, P->o_status), sizeof(int32_t) * P->nsims,
-                               hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(stat.data(), wsp<int32_t>(P, P->o_status), sizeof(int32_t) * P->nsims,
+                           hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     *total = tot;
     for (int s2 = 0; s2 < P->nsims; ++s2)
-        if (stat[s2] & kFlagOverflow)
-            return fail(SPH_ERR_CAPACITY, "a particle has more neighbours than max_neighbors");
+        if (stat[s2] & kFlagOverflow) return fail(SPH_ERR_CAPACITY, "a particle has more neighbours than max_neighbors");
     if (tot > capacity) return fail(SPH_ERR_CAPACITY, "neighbour capacity too small");
     if (N > 0) {
-        k_export_rows<<<(unsigned)N, 64, 0, st>>>(N, P->ld, orig, wsp<int32_t>(P, P->o_nbr),
-                                                  wsp<int32_t>(P, P->o_cnt), P->maxnbr, offsets, nbr);
+        k_export_rows<<<(unsigned)N, 64, 0, st>>>(N, P->width, orig, wsp<int32_t>(P, L.nbr), wsp<int32_t>(P, L.cnt),
+                                                  offsets, nbr);
         LAUNCH_CHECK("export_rows");
     }
     HIP_TRY(hipStreamSynchronize(st));
@@ -389,12 +532,13 @@ extern "C" {
 const char* sph_last_error(void) { return g_err.c_str(); }
 
 sph_status sph_plan_create(const sph_params* sims, int32_t nsims, const int64_t* counts, int32_t max_neighbors,
-                           sph_plan** out)
+                           int32_t tape_depth, sph_plan** out)
 {
     if (!out) return fail(SPH_ERR_INVALID_ARG, "out is null");
     *out = nullptr;
     if (nsims <= 0 || !sims || !counts) return fail(SPH_ERR_INVALID_ARG, "need nsims > 0, sims and counts");
     if (max_neighbors < 0) return fail(SPH_ERR_INVALID_ARG, "max_neighbors < 0");
+    if (tape_depth < 0 || tape_depth > 4096) return fail(SPH_ERR_INVALID_ARG, "tape_depth out of range");
     sph_plan* P = new sph_plan();
     P->dim = sims[0].dim;
     P->dtype = sims[0].dtype;
@@ -424,7 +568,7 @@ sph_status sph_plan_create(const sph_params* sims, int32_t nsims, const int64_t*
         }
         if (!(q.box > 0) || !(q.support > 0) || !(2.0 * q.support < q.box) || !(q.mass > 0) || !(q.rho0 > 0) ||
             !(q.c0 > 0) || !(q.eps > 0) || !std::isfinite(q.dt) || !std::isfinite(q.delta) ||
-            !std::isfinite(q.alpha)) {
+            !std::isfinite(q.alpha) || !std::isfinite(q.box)) {
             std::snprintf(buf, sizeof buf, "simulation %d: invalid parameters (need 0 < 2H < L, m, rho0, c0, eps > 0)", s);
             delete P;
             return fail(SPH_ERR_INVALID_ARG, buf);
@@ -432,34 +576,37 @@ sph_status sph_plan_create(const sph_params* sims, int32_t nsims, const int64_t*
         SimHost h{};
         h.p0 = p0;
         h.n = counts[s];
-        int nc2 = (int)std::floor(2.0 * q.box / (q.support * kCellMargin));
-        int nc1 = (int)std::floor(q.box / (q.support * kCellMargin));
+        const double nc2 = std::floor(2.0 * q.box / (q.support * kCellMargin));
+        const double nc1 = std::floor(q.box / (q.support * kCellMargin));
         if (nc2 >= 5) {
             h.sub = 2;
-            h.nc = nc2;
+            h.nc = (int)std::min(nc2, 1e6);
         } else if (nc1 >= 3) {
             h.sub = 1;
-            h.nc = nc1;
+            h.nc = (int)nc1;
         } else {
             std::snprintf(buf, sizeof buf, "simulation %d: fewer than 3 cells of side >= H per box side", s);
             delete P;
             return fail(SPH_ERR_TOO_FEW_CELLS, buf);
         }
-        if (h.nc > 1024 * 4) {
-            delete P;
-            return fail(SPH_ERR_UNSUPPORTED, "more than 4096 cells per box side");
-        }
         int B = (d == 3) ? 2 : 4;
-        while (B > 1 && B + 2 * h.sub > h.nc) --B;
         h.B = B;
         h.nb = (h.nc + B - 1) / B;
+        if (h.nb > 1024) {
+            delete P;
+            return fail(SPH_ERR_UNSUPPORTED, "more than 1024 cell blocks per box side");
+        }
         h.Bd = (d == 3) ? B * B * B : B * B;
         h.nblk = (d == 3) ? h.nb * h.nb * h.nb : h.nb * h.nb;
         h.cell0 = (int32_t)cell0;
         h.blk0 = (int32_t)blk0;
+        const int sw = 2 * h.sub + 1;
+        h.ncu = (d == 3) ? sw * sw * sw : sw * sw;
+        h.st0 = P->nstencil;
+        P->nstencil += (int64_t)h.nblk * h.Bd * h.ncu;
         cell0 += (int64_t)h.nblk * h.Bd;
         blk0 += h.nblk;
-        if (cell0 > (int64_t)1 << 30) {
+        if (cell0 >= ((int64_t)1 << kStencilIdBits) - 1) {
             delete P;
             return fail(SPH_ERR_UNSUPPORTED, "too many cells in one plan");
         }
@@ -469,25 +616,32 @@ sph_status sph_plan_create(const sph_params* sims, int32_t nsims, const int64_t*
         const double vol = (d == 2) ? M_PI * q.support * q.support : 4.0 / 3.0 * M_PI * std::pow(q.support, 3);
         nh_max = std::max(nh_max, vol / dxd);
     }
-    if (p0 >= ((int64_t)1 << 31) - 1024) {
+    // the sweeps gather per-particle records with 32-bit byte offsets
+    const int64_t rec = (P->dtype == SPH_F64) ? 32 : 16;
+    if (p0 * rec >= ((int64_t)1 << 32)) {
         delete P;
-        return fail(SPH_ERR_UNSUPPORTED, "more than 2^31 particles in one plan");
+        return fail(SPH_ERR_UNSUPPORTED, "too many particles in one plan (records must fit 32-bit offsets)");
     }
     P->N = p0;
     P->ncell = cell0;
     P->nblk = blk0;
-    P->ld = (int64_t)align_up((size_t)std::max<int64_t>(P->N, 1), 64);
-    P->maxnbr = max_neighbors > 0 ? max_neighbors : (int32_t)align_up((size_t)std::ceil(1.6 * nh_max), 8);
-    if (P->maxnbr < 8) P->maxnbr = 8;
+    P->width = max_neighbors > 0 ? (int32_t)align_up((size_t)max_neighbors, 8)
+                                 : (int32_t)align_up((size_t)std::ceil(1.6 * nh_max), 8);
+    if (P->width < 8) P->width = 8;
+    P->tape_depth = tape_depth;
+    P->nslots = std::max(2, tape_depth);
+    // lanes per particle of the sweeps: enough lanes to give every SIMD several wavefronts
+    P->lpp_fwd = P->lpp_adj = (P->N <= (1 << 18)) ? 4 : (P->N <= (1 << 20) ? 2 : 1);
 
-    // host tables: particle -> simulation, block tables in Morton order per simulation
+    // host tables: particle -> simulation, cell -> simulation, block tables in Morton order
     P->h_psim.resize((size_t)P->N);
-    P->h_blk_sim.resize((size_t)P->nblk);
+    P->h_cell_sim.resize((size_t)P->ncell);
     P->h_blk_coord.resize((size_t)P->nblk);
     P->h_blk_rank.resize((size_t)P->nblk);
     for (int s = 0; s < nsims; ++s) {
         const SimHost& h = P->sim[s];
         for (int64_t i = 0; i < h.n; ++i) P->h_psim[(size_t)(h.p0 + i)] = s;
+        for (int64_t c = 0; c < (int64_t)h.nblk * h.Bd; ++c) P->h_cell_sim[(size_t)(h.cell0 + c)] = s;
         std::vector<std::pair<uint64_t, int32_t>> blocks;
         blocks.reserve((size_t)h.nblk);
         for (int lin = 0; lin < h.nblk; ++lin) {
@@ -498,9 +652,49 @@ sph_status sph_plan_create(const sph_params* sims, int32_t nsims, const int64_t*
         for (int r = 0; r < h.nblk; ++r) {
             int lin = blocks[r].second;
             int bx = lin % h.nb, by = (lin / h.nb) % h.nb, bz = (d == 3) ? lin / (h.nb * h.nb) : 0;
-            P->h_blk_sim[(size_t)(h.blk0 + r)] = s;
             P->h_blk_coord[(size_t)(h.blk0 + r)] = bx | (by << 10) | (bz << 20);
             P->h_blk_rank[(size_t)(h.blk0 + lin)] = r;
+        }
+    }
+    // stencil table: for every cell slot, its stencil cells in lexicographic order of the offset
+    // (z, then y, then x), each with the periodic image it is seen through
+    P->h_stencil.assign((size_t)P->nstencil, 0);
+    for (int s = 0; s < nsims; ++s) {
+        const SimHost& h = P->sim[s];
+        const int sw = 2 * h.sub + 1;
+        for (int rank = 0; rank < h.nblk; ++rank) {
+            const int coord = P->h_blk_coord[(size_t)(h.blk0 + rank)];
+            const int bc[3] = {coord & 1023, (coord >> 10) & 1023, (coord >> 20) & 1023};
+            for (int w = 0; w < h.Bd; ++w) {
+                const int cc[3] = {bc[0] * h.B + w % h.B, bc[1] * h.B + (w / h.B) % h.B,
+                                   (d == 3) ? bc[2] * h.B + w / (h.B * h.B) : 0};
+                const int64_t row = h.st0 + ((int64_t)rank * h.Bd + w) * h.ncu;
+                if (cc[0] >= h.nc || cc[1] >= h.nc || cc[2] >= ((d == 3) ? h.nc : 1)) continue;  // empty slot
+                for (int u = 0; u < h.ncu; ++u) {
+                    const int o[3] = {u % sw - h.sub, (u / sw) % sw - h.sub, (d == 3) ? u / (sw * sw) - h.sub : 0};
+                    int c[3] = {0, 0, 0}, sh[3] = {0, 0, 0};
+                    for (int k = 0; k < d; ++k) {
+                        int rr = cc[k] + o[k];
+                        if (rr < 0) {
+                            rr += h.nc;
+                            sh[k] = -1;
+                        } else if (rr >= h.nc) {
+                            rr -= h.nc;
+                            sh[k] = 1;
+                        }
+                        c[k] = rr;
+                    }
+                    const int bx = c[0] / h.B, by = c[1] / h.B, bz = (d == 3) ? c[2] / h.B : 0;
+                    const int lin = (d == 3) ? (bz * h.nb + by) * h.nb + bx : by * h.nb + bx;
+                    const int rk = P->h_blk_rank[(size_t)(h.blk0 + lin)];
+                    const int wl = (d == 3) ? ((c[2] - bz * h.B) * h.B + (c[1] - by * h.B)) * h.B + (c[0] - bx * h.B)
+                                            : (c[1] - by * h.B) * h.B + (c[0] - bx * h.B);
+                    const int id = h.cell0 + rk * h.Bd + wl;
+                    P->h_stencil[(size_t)(row + u)] = id | ((sh[0] + 1) << kStencilIdBits) |
+                                                     ((sh[1] + 1) << (kStencilIdBits + 2)) |
+                                                     ((sh[2] + 1) << (kStencilIdBits + 4));
+                }
+            }
         }
     }
     if (P->dtype == SPH_F32) fill_simconst<float>(P, P->h_simc);
@@ -519,27 +713,33 @@ sph_status sph_plan_create(const sph_params* sims, int32_t nsims, const int64_t*
     P->nparts64 = ((int64_t)N + kScanTile - 1) / kScanTile;
     P->o_simc = take(P->h_simc.size());
     P->o_psim = take(4 * N);
-    P->o_blk_sim = take(4 * (size_t)P->nblk);
+    P->o_cell_sim = take(4 * (size_t)P->ncell);
     P->o_blk_coord = take(4 * (size_t)P->nblk);
     P->o_blk_rank = take(4 * (size_t)P->nblk);
+    P->o_stencil = take(4 * (size_t)P->nstencil);
     P->o_cell_count = take(4 * (size_t)P->ncell);
     P->o_cell_start = take(4 * ((size_t)P->ncell + 1));
     P->o_part = take(4 * ((size_t)P->nparts + 1));
     P->o_cell_of = take(4 * N);
     P->o_slot_of = take(4 * N);
     P->o_tmp = take(4 * N);
-    P->o_orig[0] = take(4 * N);
-    P->o_orig[1] = take(4 * N);
-    P->o_SA = take(T * N * (2 * d + 1));
     P->o_SB = take(T * N * (2 * d + 1));
-    P->o_jd0 = take(V4 * N);
-    P->o_jd1 = take(V4 * N);
     P->o_jdA = take(V4 * N);
     P->o_jdB = take(V4 * N);
-    P->o_nbr = take(4 * (size_t)P->ld * (size_t)P->maxnbr);
-    P->o_cnt = take(4 * N);
     P->o_status = take(4 * (size_t)nsims);
     P->o_part64 = take(8 * ((size_t)P->nparts64 + 1) + 8 * (N + 1));
+    P->o_pairs = take(8 * (size_t)kPairSlots * kPairStride);
+    P->o_ticket = take(4);
+    P->slot.resize((size_t)P->nslots);
+    for (int k = 0; k < P->nslots; ++k) {
+        SlotLayout& L = P->slot[k];
+        L.SA = take(T * N * (2 * d + 1));
+        L.jd0 = take(V4 * N);
+        L.jd1 = take(V4 * N);
+        L.orig = take(4 * N);
+        L.nbr = take(4 * (size_t)P->width * N);
+        L.cnt = take(4 * N);
+    }
     P->bytes = off;
     *out = P;
     return SPH_OK;
@@ -559,7 +759,25 @@ sph_status sph_plan_info(const sph_plan* plan, int64_t* total_particles, int32_t
     if (!plan) return fail(SPH_ERR_INVALID_ARG, "plan is null");
     if (total_particles) *total_particles = plan->N;
     if (nsims) *nsims = plan->nsims;
-    if (max_neighbors) *max_neighbors = plan->maxnbr;
+    if (max_neighbors) *max_neighbors = plan->width;
+    return SPH_OK;
+}
+
+sph_status sph_set_tuning(sph_plan* plan, int32_t lanes_fwd, int32_t lanes_adj)
+{
+    if (!plan) return fail(SPH_ERR_INVALID_ARG, "plan is null");
+    auto ok = [](int32_t v) { return v == 1 || v == 2 || v == 4; };
+    if (!ok(lanes_fwd) || !ok(lanes_adj)) return fail(SPH_ERR_INVALID_ARG, "lanes per particle must be 1, 2 or 4");
+    plan->lpp_fwd = lanes_fwd;
+    plan->lpp_adj = lanes_adj;
+    return SPH_OK;
+}
+
+sph_status sph_get_tuning(const sph_plan* plan, int32_t* lanes_fwd, int32_t* lanes_adj)
+{
+    if (!plan) return fail(SPH_ERR_INVALID_ARG, "plan is null");
+    if (lanes_fwd) *lanes_fwd = plan->lpp_fwd;
+    if (lanes_adj) *lanes_adj = plan->lpp_adj;
     return SPH_OK;
 }
 
@@ -574,16 +792,25 @@ sph_status sph_bind(sph_plan* P, void* workspace, size_t bytes, void* stream)
     HIP_TRY(hipMemcpyAsync(P->ws + P->o_simc, P->h_simc.data(), P->h_simc.size(), hipMemcpyHostToDevice, st));
     if (P->N > 0)
         HIP_TRY(hipMemcpyAsync(P->ws + P->o_psim, P->h_psim.data(), 4 * (size_t)P->N, hipMemcpyHostToDevice, st));
+    if (P->ncell > 0)
+        HIP_TRY(hipMemcpyAsync(P->ws + P->o_cell_sim, P->h_cell_sim.data(), 4 * (size_t)P->ncell, hipMemcpyHostToDevice, st));
     if (P->nblk > 0) {
-        HIP_TRY(hipMemcpyAsync(P->ws + P->o_blk_sim, P->h_blk_sim.data(), 4 * (size_t)P->nblk, hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(P->ws + P->o_blk_coord, P->h_blk_coord.data(), 4 * (size_t)P->nblk, hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(P->ws + P->o_blk_rank, P->h_blk_rank.data(), 4 * (size_t)P->nblk, hipMemcpyHostToDevice, st));
     }
+    if (P->nstencil > 0)
+        HIP_TRY(hipMemcpyAsync(P->ws + P->o_stencil, P->h_stencil.data(), 4 * (size_t)P->nstencil,
+                               hipMemcpyHostToDevice, st));
     if (P->ncell > 0) {
         k_fill<int32_t><<<grid_for(P->ncell, 256), 256, 0, st>>>(wsp<int32_t>(P, P->o_cell_count), P->ncell, 0);
         LAUNCH_CHECK("fill");
     }
     k_fill<int32_t><<<grid_for(P->nsims, 256), 256, 0, st>>>(wsp<int32_t>(P, P->o_status), P->nsims, 0);
+    LAUNCH_CHECK("fill");
+    k_fill<unsigned int><<<1, 1, 0, st>>>(wsp<unsigned int>(P, P->o_ticket), 1, 0u);
+    LAUNCH_CHECK("fill");
+    k_fill<unsigned long long><<<grid_for(kPairSlots * kPairStride, 256), 256, 0, st>>>(
+        wsp<unsigned long long>(P, P->o_pairs), kPairSlots * kPairStride, 0ull);
     LAUNCH_CHECK("fill");
     // the host tables must outlive the asynchronous copies
     HIP_TRY(hipStreamSynchronize(st));
@@ -593,18 +820,16 @@ sph_status sph_bind(sph_plan* P, void* workspace, size_t bytes, void* stream)
 
 sph_status sph_build_cells(sph_plan* P, const sph_state* s, void* stream)
 {
-    sph_status rc = check_bound(P);
-    if (rc == SPH_OK) rc = check_state(P, s, "state");
-    if (rc != SPH_OK) return rc;
+    RC_TRY(check_bound(P));
+    RC_TRY(check_state(P, s, "state"));
     return DISPATCH(P, do_build_cells, P, s, (hipStream_t)stream);
 }
 
 sph_status sph_neighbors(sph_plan* P, const sph_state* s, int64_t* offsets, int32_t* nbr, int64_t capacity,
                          int64_t* total, void* stream)
 {
-    sph_status rc = check_bound(P);
-    if (rc == SPH_OK) rc = check_state(P, s, "state");
-    if (rc != SPH_OK) return rc;
+    RC_TRY(check_bound(P));
+    RC_TRY(check_state(P, s, "state"));
     if (!offsets || !total) return fail(SPH_ERR_INVALID_ARG, "offsets and total must not be null");
     if (capacity < 0 || (capacity > 0 && !nbr)) return fail(SPH_ERR_INVALID_ARG, "bad neighbour buffer");
     return DISPATCH(P, do_neighbors, P, s, offsets, nbr, capacity, total, (hipStream_t)stream);
@@ -612,9 +837,8 @@ sph_status sph_neighbors(sph_plan* P, const sph_state* s, int64_t* offsets, int3
 
 sph_status sph_rhs(sph_plan* P, const sph_state* s, void* drho, void* acc, void* rho_sum, void* stream)
 {
-    sph_status rc = check_bound(P);
-    if (rc == SPH_OK) rc = check_state(P, s, "state");
-    if (rc != SPH_OK) return rc;
+    RC_TRY(check_bound(P));
+    RC_TRY(check_state(P, s, "state"));
     if (P->N > 0 && (!drho || !acc)) return fail(SPH_ERR_INVALID_ARG, "drho and acc must not be null");
     return DISPATCH(P, do_rhs, P, s, drho, acc, rho_sum, (hipStream_t)stream);
 }
@@ -622,40 +846,94 @@ sph_status sph_rhs(sph_plan* P, const sph_state* s, void* drho, void* acc, void*
 sph_status sph_step(sph_plan* P, sph_state* s, int32_t nsteps, const sph_state* ckpt, int32_t ckpt_every,
                     void* stream)
 {
-    sph_status rc = check_bound(P);
-    if (rc == SPH_OK) rc = check_state(P, s, "state");
-    if (rc != SPH_OK) return rc;
+    RC_TRY(check_bound(P));
+    RC_TRY(check_state(P, s, "state"));
     if (nsteps < 0) return fail(SPH_ERR_INVALID_ARG, "nsteps < 0");
     if (ckpt) {
         if (ckpt_every <= 0) return fail(SPH_ERR_INVALID_ARG, "ckpt_every must be > 0");
-        int32_t nslots = (nsteps + ckpt_every - 1) / ckpt_every;
-        for (int32_t k = 0; k < nslots; ++k) {
-            rc = check_state(P, &ckpt[k], "checkpoint slot");
-            if (rc != SPH_OK) return rc;
-        }
+        const int32_t nslots = (nsteps + ckpt_every - 1) / ckpt_every;
+        for (int32_t k = 0; k < nslots; ++k) RC_TRY(check_state(P, &ckpt[k], "checkpoint slot"));
     }
     return DISPATCH(P, do_step, P, s, nsteps, ckpt, ckpt_every, (hipStream_t)stream);
 }
 
 sph_status sph_step_adjoint(sph_plan* P, const sph_state* s_n, sph_state* cot, void* stream)
 {
-    sph_status rc = check_bound(P);
-    if (rc == SPH_OK) rc = check_state(P, s_n, "state");
-    if (rc == SPH_OK) rc = check_state(P, cot, "cotangent");
-    if (rc != SPH_OK) return rc;
+    RC_TRY(check_bound(P));
+    RC_TRY(check_state(P, s_n, "state"));
+    RC_TRY(check_state(P, cot, "cotangent"));
     return DISPATCH(P, do_step_adjoint, P, s_n, cot, (hipStream_t)stream);
+}
+
+sph_status sph_rollout_backward(sph_plan* P, const sph_state* ckpt, int32_t nsteps, int32_t ckpt_every,
+                                sph_state* cot, void* stream)
+{
+    RC_TRY(check_bound(P));
+    RC_TRY(check_state(P, cot, "cotangent"));
+    if (nsteps < 0 || ckpt_every <= 0) return fail(SPH_ERR_INVALID_ARG, "need nsteps >= 0 and ckpt_every > 0");
+    if (nsteps > 0 && !ckpt) return fail(SPH_ERR_INVALID_ARG, "checkpoints are null");
+    if (std::min(ckpt_every, nsteps) > P->tape_depth)
+        return fail(SPH_ERR_CAPACITY, "plan tape_depth is smaller than the checkpoint interval");
+    const int32_t nseg = nsteps > 0 ? (nsteps + ckpt_every - 1) / ckpt_every : 0;
+    for (int32_t k = 0; k < nseg; ++k) RC_TRY(check_state(P, &ckpt[k], "checkpoint slot"));
+    return DISPATCH(P, do_rollout_backward, P, ckpt, nsteps, ckpt_every, cot, (hipStream_t)stream);
 }
 
 sph_status sph_poll(sph_plan* P, int32_t* per_sim_status, void* stream)
 {
-    sph_status rc = check_bound(P);
-    if (rc != SPH_OK) return rc;
+    RC_TRY(check_bound(P));
     if (!per_sim_status) return fail(SPH_ERR_INVALID_ARG, "per_sim_status is null");
     hipStream_t st = (hipStream_t)stream;
     HIP_TRY(hipMemcpyAsync(per_sim_status, P->ws + P->o_status, sizeof(int32_t) * P->nsims, hipMemcpyDeviceToHost, st));
     k_fill<int32_t><<<grid_for(P->nsims, 256), 256, 0, st>>>(wsp<int32_t>(P, P->o_status), P->nsims, 0);
     LAUNCH_CHECK("fill");
     HIP_TRY(hipStreamSynchronize(st));
+    return SPH_OK;
+}
+
+sph_status sph_pair_count(sph_plan* P, int64_t* pairs, void* stream)
+{
+    RC_TRY(check_bound(P));
+    if (!pairs) return fail(SPH_ERR_INVALID_ARG, "pairs is null");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<unsigned long long> v((size_t)kPairSlots * kPairStride, 0ull);
+    HIP_TRY(hipMemcpyAsync(v.data(), P->ws + P->o_pairs, sizeof(unsigned long long) * v.size(), hipMemcpyDeviceToHost,
+                           st));
+    k_fill<unsigned long long><<<grid_for(kPairSlots * kPairStride, 256), 256, 0, st>>>(
+        wsp<unsigned long long>(P, P->o_pairs), kPairSlots * kPairStride, 0ull);
+    LAUNCH_CHECK("fill");
+    HIP_TRY(hipStreamSynchronize(st));
+    unsigned long long total = 0;
+    for (int k = 0; k < kPairSlots; ++k) total += v[(size_t)k * kPairStride];
+    *pairs = (int64_t)total;
+    return SPH_OK;
+}
+
+sph_status sph_profile_enable(sph_plan* P, int32_t enable)
+{
+    if (!P) return fail(SPH_ERR_INVALID_ARG, "plan is null");
+    P->prof = enable != 0;
+    return SPH_OK;
+}
+
+sph_status sph_profile_read(sph_plan* P, double* ms, int64_t* launches)
+{
+    if (!P) return fail(SPH_ERR_INVALID_ARG, "plan is null");
+    for (auto& e : P->ev_used) {
+        HIP_TRY(hipEventSynchronize(e.b));
+        float t = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t, e.a, e.b));
+        P->prof_ms[e.kind] += t;
+        P->prof_n[e.kind] += 1;
+        P->ev_pool.push_back({e.a, e.b});
+    }
+    P->ev_used.clear();
+    for (int k = 0; k < SPH_KERN_COUNT; ++k) {
+        if (ms) ms[k] = P->prof_ms[k];
+        if (launches) launches[k] = P->prof_n[k];
+        P->prof_ms[k] = 0.0;
+        P->prof_n[k] = 0;
+    }
     return SPH_OK;
 }
 

@@ -49,8 +49,14 @@ struct SimConst {
     int32_t B;          // cells per block side
     int32_t nb;         // blocks per box side
     int32_t Bd;         // B^dim
-    int32_t pad;
+    int32_t ncu;        // stencil cells per cell, (2 sub + 1)^dim
+    int64_t st0;        // first entry of this simulation's stencil table
 };
+
+// Stencil table entry: global cell id in the low 26 bits, periodic image shift (-1, 0, +1 box
+// lengths, stored + 1) in two bits per axis above it.
+constexpr int kStencilIdBits = 26;
+constexpr int32_t kStencilIdMask = (1 << kStencilIdBits) - 1;
 
 template <typename T, int DIM>
 struct StatePtrs {
@@ -232,6 +238,53 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const I* __restric
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
+// Tile sums, and the workgroup that finishes last (atomic ticket; no waiting on other
+// workgroups) turns them into exclusive tile offsets, part[np] = grand total, and resets the
+// ticket for the next scan.
+template <typename I>
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce_last(const I* __restrict__ in, int64_t n,
+                                                                   I* __restrict__ part,
+                                                                   unsigned int* __restrict__ ticket)
+{
+    __shared__ I smem[8];
+    __shared__ I carry;
+    __shared__ int is_last;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    I sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < n) sum += in[base + k];
+    I tot;
+    block_excl_scan<I>(sum, smem, &tot);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = tot;
+        __threadfence();
+        const unsigned int done = atomicAdd(ticket, 1u);
+        is_last = (done == gridDim.x - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+    const int64_t np = gridDim.x;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t b = 0; b < np; b += blockDim.x) {
+        const int64_t i = b + threadIdx.x;
+        const I v = (i < np) ? __atomic_load_n(&part[i], __ATOMIC_RELAXED) : I(0);
+        I t2;
+        const I ex = block_excl_scan<I>(v, smem, &t2);
+        const I c0 = carry;
+        if (i < np) part[i] = c0 + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry = c0 + t2;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[np] = carry;
+        *ticket = 0u;
+    }
+}
+
 // one workgroup: exclusive scan of part[0..np), part[np] = grand total
 template <typename I>
 __global__ __launch_bounds__(1024) void k_scan_top(I* __restrict__ part, int64_t np)
@@ -252,6 +305,45 @@ __global__ __launch_bounds__(1024) void k_scan_top(I* __restrict__ part, int64_t
         __syncthreads();
     }
     if (threadIdx.x == 0) part[np] = carry;
+}
+
+// One workgroup scans everything (for up to a few tens of thousands of elements this is one
+// launch instead of three): out[i] = exclusive prefix of in, out[n] = total, `in` optionally
+// zeroed.  Each pass covers 1024 threads x 16 consecutive elements.
+template <typename I>
+__global__ __launch_bounds__(1024) void k_scan_single(I* __restrict__ in, int64_t n, I* __restrict__ out, int zero_in)
+{
+    constexpr int kItems = 16;
+    __shared__ I smem[16];
+    __shared__ I carry_s;
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    for (int64_t b = 0; b < n; b += (int64_t)blockDim.x * kItems) {
+        const int64_t base = b + (int64_t)threadIdx.x * kItems;
+        I v[kItems];
+        I sum = 0;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            v[k] = (base + k < n) ? in[base + k] : I(0);
+            sum += v[k];
+        }
+        I tot;
+        I ex = block_excl_scan<I>(sum, smem, &tot);
+        const I carry = carry_s;
+        ex += carry;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            if (base + k < n) {
+                out[base + k] = ex;
+                if (zero_in) in[base + k] = 0;
+            }
+            ex += v[k];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) carry_s = carry + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[n] = carry_s;
 }
 
 // out[i] = exclusive prefix of in; out[n] = total; optionally zero `in` afterwards
@@ -339,7 +431,7 @@ __global__ __launch_bounds__(256) void k_order_gather(int64_t N, const int32_t* 
         b.x = v[0]; b.y = v[1]; b.z = v[2]; b.w = pV;
     } else {
         a.x = u[0]; a.y = u[1]; a.z = V; a.w = pV;
-        b.x = v[0]; b.y = v[1]; b.z = T(0); b.w = T(0);
+        b.x = v[0]; b.y = v[1]; b.z = rho; b.w = T(0);
     }
     jd0[d] = a;
     jd1[d] = b;
@@ -355,218 +447,383 @@ __device__ __forceinline__ void unpack_u(const vec4_t<T>& a, T* u)
 
 // ---------------------------------------------------------------- neighbour lists
 
-constexpr int kBuildTile = 512;  // candidates staged in LDS at a time
+constexpr int kBuildTile = 128;  // candidates staged in LDS at a time
+// The pair counter is spread over kPairSlots words, one per 128-byte line, so that the
+// wavefronts' integer atomics do not serialise on a single address.
+constexpr int kPairSlots = 512;
+constexpr int kPairStride = 16;
 
-// One wavefront per cell block.  The block's particles (a contiguous sorted range) are tested
-// against the union of their stencils, (B + 2 sub)^dim cells visited in lexicographic order of
-// their offset from the block; candidate tiles are staged in LDS and read by all lanes at the
-// same address.  Each lane appends its accepted neighbours to an ELL list (column-major, row
-// stride `ld`), so each particle's list is ordered by stencil offset, then by original index.
+// One wavefront per cell.  The cell's particles are tested against the particles of the
+// (2 sub + 1)^dim stencil cells, visited in lexicographic order of their offset from the cell
+// (the precomputed stencil table lists them in that order) and staged through LDS in tiles
+// read by all lanes at the same address.  When a cell holds n < 64 particles,
+// LPP = 64 / next_pow2(n) lanes share each particle and split its candidate stream; a ballot
+// over each round of LPP candidates gives every accepted candidate its rank, so each
+// particle's list keeps the candidate order (stencil offset, then original index) whatever
+// LPP is.  Lists are row-major: entry k of particle i is nbr[i * width + k], and the writes of
+// one particle's accepted candidates in a round are contiguous.
 template <typename T, int DIM>
-__global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ blk_sim,
-                                                   const int32_t* __restrict__ blk_coord,
-                                                   const int32_t* __restrict__ blk_rank,
+__global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ cell_sim,
+                                                   const int32_t* __restrict__ stencil,
                                                    const SimConst<T>* __restrict__ sims,
                                                    const int32_t* __restrict__ cell_start,
-                                                   const vec4_t<T>* __restrict__ jd0, int64_t ld, int32_t maxnbr,
+                                                   const vec4_t<T>* __restrict__ jd0, int32_t width,
                                                    int32_t* __restrict__ nbr, int32_t* __restrict__ nbr_count,
-                                                   int32_t* __restrict__ status)
+                                                   int32_t* __restrict__ status,
+                                                   unsigned long long* __restrict__ pair_counter)
 {
-    __shared__ T su[DIM][kBuildTile];
-    __shared__ T ssh[DIM][kBuildTile];
-    __shared__ int32_t sj[kBuildTile];
-    __shared__ int32_t uc_first[64];
-    __shared__ int32_t uc_pref[65];
-    __shared__ T uc_shift[DIM][64];
+    __shared__ vec4_t<T> cu[kBuildTile];
+    __shared__ vec4_t<T> csh[kBuildTile];
+    __shared__ int32_t cj[kBuildTile];
+    __shared__ int32_t uc_first[128];
+    __shared__ int32_t uc_pref[129];
+    __shared__ int32_t uc_code[128];
 
-    const int gb = xcd_remap(blockIdx.x, gridDim.x);
-    const int s = blk_sim[gb];
-    const SimConst<T> S = sims[s];
-    const int coord = blk_coord[gb];
-    const int bc[3] = {coord & 1023, (coord >> 10) & 1023, (coord >> 20) & 1023};
-    const int B = S.B, sub = S.sub, nc = S.nc;
-    const int W = B + 2 * sub;
-    const int ncu = (DIM == 3) ? W * W * W : W * W;
-    const int cfirst = S.cell0 + (gb - S.blk0) * S.Bd;
-    const int i0 = cell_start[cfirst], i1 = cell_start[cfirst + S.Bd];
+    const int gc = xcd_remap(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x;
+    const int s = cell_sim[gc];
+    const int i0 = cell_start[gc], i1 = cell_start[gc + 1];
+    const int n = i1 - i0;
+    if (n == 0) return;
+    const SimConst<T> S = sims[s];
+    const int ncu = S.ncu;
+    const int32_t* trow = stencil + S.st0 + (int64_t)(gc - S.cell0) * ncu;
 
-    for (int ib = i0; ib < i1; ib += 64) {
-        const int i = ib + lane;
-        const bool act = i < i1;
+    // stencil cells: particle range and periodic image code, two per lane at most
+    int carry = 0;
+    for (int half = 0; half < 2; ++half) {
+        const int u = lane + 64 * half;
+        int first = 0, count = 0, code = 0;
+        if (u < ncu) {
+            code = trow[u];
+            const int id = code & kStencilIdMask;
+            first = cell_start[id];
+            count = cell_start[id + 1] - first;
+        }
+        const int inc = wave_incl_scan(count);
+        if (u < 128) {
+            uc_first[u] = first;
+            uc_pref[u] = carry + inc - count;
+            uc_code[u] = code;
+        }
+        carry += __shfl(inc, 63, 64);
+    }
+    const int M = carry;
+    if (lane == 0) uc_pref[ncu] = M;
+    __syncthreads();
+
+    int lpp = 1;
+    while (n < 64 && 2 * lpp * n <= 64) lpp *= 2;
+    const int slots = 64 / lpp;
+    const int g = lane / lpp, r = lane - g * lpp;
+    const unsigned long long group_mask = (lpp == 64) ? ~0ull : (((1ull << lpp) - 1ull) << (g * lpp));
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int pairs_acc = 0;
+
+    for (int p0 = 0; p0 < n; p0 += slots) {
+        const bool act = (p0 + g) < n;
+        const int i = i0 + p0 + g;
         T ui[3] = {0, 0, 0};
         if (act) unpack_u<T, DIM>(jd0[i], ui);
         int cnt = 0;
-        for (int cu0 = 0; cu0 < ncu; cu0 += 64) {
-            // lane's union cell: its particle range and periodic image shift
-            const int cu = cu0 + lane;
-            int first = 0, count = 0;
-            T sh[3] = {0, 0, 0};
-            if (cu < ncu) {
-                int o[3] = {cu % W, (cu / W) % W, (DIM == 3) ? cu / (W * W) : 0};
-                int cc[3] = {0, 0, 0};
-#pragma unroll
-                for (int k = 0; k < DIM; ++k) {
-                    int r = bc[k] * B + o[k] - sub;
-                    if (r < 0) {
-                        r += nc;
-                        sh[k] = -S.L;
-                    } else if (r >= nc) {
-                        r -= nc;
-                        sh[k] = S.L;
-                    }
-                    cc[k] = r;
+        for (int t0 = 0; t0 < M; t0 += kBuildTile) {
+            const int mt = (M - t0 < kBuildTile) ? M - t0 : kBuildTile;
+            __syncthreads();
+            for (int m = lane; m < mt; m += 64) {
+                const int gm = t0 + m;
+                int lo = 0, hi = ncu - 1;  // last stencil cell whose prefix is <= gm
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (uc_pref[mid] <= gm) lo = mid;
+                    else hi = mid - 1;
                 }
-                const int gc = global_cell<T, DIM>(S, blk_rank, cc[0], cc[1], cc[2]);
-                first = cell_start[gc];
-                count = cell_start[gc + 1] - first;
+                const int j = uc_first[lo] + (gm - uc_pref[lo]);
+                cu[m] = jd0[j];
+                const int code = uc_code[lo];
+                vec4_t<T> shv;
+                shv.x = T(((code >> kStencilIdBits) & 3) - 1) * S.L;
+                shv.y = T(((code >> (kStencilIdBits + 2)) & 3) - 1) * S.L;
+                shv.z = T(((code >> (kStencilIdBits + 4)) & 3) - 1) * S.L;
+                shv.w = T(0);
+                csh[m] = shv;
+                cj[m] = j;
             }
-            const int inc = wave_incl_scan(count);
-            const int tot = __shfl(inc, 63, 64);
             __syncthreads();
-            uc_first[lane] = first;
-            uc_pref[lane] = inc - count;
-            if (lane == 63) uc_pref[64] = inc;
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) uc_shift[k][lane] = sh[k];
-            __syncthreads();
-            for (int m0 = 0; m0 < tot; m0 += kBuildTile) {
-                const int mt = (tot - m0 < kBuildTile) ? tot - m0 : kBuildTile;
-                for (int m = lane; m < mt; m += 64) {
-                    const int gm = m0 + m;
-                    int lo = 0, hi = 63;  // last union cell whose prefix is <= gm
-                    while (lo < hi) {
-                        int mid = (lo + hi + 1) >> 1;
-                        if (uc_pref[mid] <= gm) lo = mid;
-                        else hi = mid - 1;
-                    }
-                    const int j = uc_first[lo] + (gm - uc_pref[lo]);
-                    T uj[3] = {0, 0, 0};
-                    unpack_u<T, DIM>(jd0[j], uj);
-#pragma unroll
-                    for (int k = 0; k < DIM; ++k) {
-                        su[k][m] = uj[k];
-                        ssh[k][m] = uc_shift[k][lo];
-                    }
-                    sj[m] = j;
+            for (int b = 0; b < mt; b += lpp) {
+                const int m = b + r;
+                bool ok = false;
+                int j = 0;
+                if (act && m < mt) {
+                    T uj[3], sh[3];
+                    unpack_u<T, DIM>(cu[m], uj);
+                    const vec4_t<T> shv = csh[m];
+                    sh[0] = shv.x;
+                    sh[1] = shv.y;
+                    sh[2] = shv.z;
+                    ok = dist2_exact<T, DIM>(ui, uj, sh) < S.H2;
+                    j = cj[m];
                 }
-                __syncthreads();
-                if (act) {
-                    for (int m = 0; m < mt; ++m) {
-                        T uj[3], sh2[3];
-#pragma unroll
-                        for (int k = 0; k < DIM; ++k) {
-                            uj[k] = su[k][m];
-                            sh2[k] = ssh[k][m];
-                        }
-                        const T r2 = dist2_exact<T, DIM>(ui, uj, sh2);
-                        if (r2 < S.H2) {
-                            if (cnt < maxnbr) nbr[(int64_t)cnt * ld + i] = sj[m];
-                            ++cnt;
-                        }
-                    }
-                }
-                __syncthreads();
+                const unsigned long long mask = __ballot(ok);
+                const unsigned long long mine = mask & group_mask;
+                const int pos = cnt + __popcll(mine & below);
+                if (ok && pos < width) nbr[(int64_t)i * width + pos] = j;
+                cnt += __popcll(mine);
             }
         }
-        if (act) {
+        if (act && r == 0) {
             nbr_count[i] = cnt;
-            if (cnt > maxnbr) atomicOr(&status[s], kFlagOverflow);
+            if (cnt > width) atomicOr(&status[s], kFlagOverflow);
+            pairs_acc += cnt - 1;
         }
     }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) pairs_acc += __shfl_xor(pairs_acc, o, 64);
+    if (lane == 0) atomicAdd(&pair_counter[(gc & (kPairSlots - 1)) * kPairStride], (unsigned long long)pairs_acc);
+}
+
+// ---------------------------------------------------------------- canonical pair sums
+//
+// A particle's neighbour sum is split into four partial sums s_q over list positions
+// k = q (mod 4), each accumulated in increasing k, and combined as (s0 + s1) + (s2 + s3).
+// LPP lanes share a particle (LPP in {1, 2, 4}): lane r holds the partial sums with
+// q = r (mod LPP).  The combined value is bitwise the same for every LPP.
+
+template <int LPP, typename T>
+__device__ __forceinline__ T combine4(const T* a /* [4 / LPP] */)
+{
+    if (LPP == 1) return (a[0] + a[1]) + (a[2] + a[3]);
+    if (LPP == 2) {
+        const T s01 = a[0] + __shfl_xor(a[0], 1, 64);
+        const T s23 = a[1] + __shfl_xor(a[1], 1, 64);
+        return s01 + s23;
+    }
+    const T s01 = a[0] + __shfl_xor(a[0], 1, 64);
+    return s01 + __shfl_xor(s01, 2, 64);
+}
+
+// ---------------------------------------------------------------- gathers and fast arithmetic
+
+// Element `idx` of an array whose byte size fits 32 bits: a 32-bit byte offset from the
+// array base, so the load uses a scalar base plus a vector offset.
+template <typename V>
+__device__ __forceinline__ V ldo(const V* __restrict__ base, uint32_t idx)
+{
+    return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(V));
+}
+
+// FP32 sweeps use the hardware reciprocal and square root (about 1 ulp); FP64 keeps IEEE
+// division and square root.
+template <typename T> __device__ __forceinline__ T fast_rcp(T x) { return T(1) / x; }
+template <> __device__ __forceinline__ float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <typename T> __device__ __forceinline__ T fast_sqrt(T x) { return sqrt(x); }
+template <> __device__ __forceinline__ float fast_sqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// Per-simulation constants the pair loops use, held in registers.
+template <typename T>
+struct PairConst {
+    T L, invL, invH, kG, kH, epsH2, cA, cD;
+};
+
+template <typename T>
+__device__ __forceinline__ PairConst<T> pair_const(const SimConst<T>& S)
+{
+    PairConst<T> c;
+    c.L = S.L;
+    c.invL = S.invL;
+    c.invH = S.invH;
+    c.kG = S.kG;
+    c.kH = S.kH;
+    c.epsH2 = S.epsH2;
+    c.cA = S.cA;
+    c.cD = S.cD;
+    return c;
 }
 
 // ---------------------------------------------------------------- forward sweep
 
 constexpr int kModeStep = 0;  // integrate into dst (sorted order)
 constexpr int kModeRhs = 1;   // write drho, a, rho_sum to caller arrays (original order)
+constexpr int kPairsInFlight = 4;  // list positions each lane loads before computing them
 
-template <typename T, int DIM, int MODE>
-__global__ __launch_bounds__(256) void k_sweep(int64_t N, int64_t ld, int32_t maxnbr, const int32_t* __restrict__ nbr,
+template <typename T, int DIM>
+struct FwdAcc {
+    T ax[3];
+    T rdv, rdd, rs;
+};
+
+// Per-particle sweep record of a neighbour (jd0, jd1, and rho in 3D).
+template <typename T, int DIM>
+struct FwdNbr {
+    vec4_t<T> a, b;
+    T rho;
+};
+
+// Forward pair terms of (i, j), added to acc:
+//   a_i    += ((alpha H c0 rho0 pi_ij - p_i) V_j - p_j V_j) gW
+//   drho_i += V_j (v_i - v_j).gW     (times rho_i later)   and   V_j (rho_i - rho_j) x_ij.gW / (r^2 + eps H^2)
+//   rho_i  += W shape (times m C_d / H^d later)
+// In 3D jd0 = (u, V), jd1 = (v, p V) and rho comes separately; in 2D jd0 = (u, V, p V) and
+// jd1 = (v, rho, 0).
+template <typename T, int DIM, bool RHOSUM>
+__device__ __forceinline__ void fwd_pair(const PairConst<T>& c, const T* ui, const T* vi, T rhoi, T pi,
+                                         const FwdNbr<T, DIM>& nb, FwdAcc<T, DIM>& acc)
+{
+    T uj[3], vj[3], d[3];
+    T Vj, pVj, rhoj;
+    if (DIM == 3) {
+        uj[0] = nb.a.x; uj[1] = nb.a.y; uj[2] = nb.a.z; Vj = nb.a.w;
+        vj[0] = nb.b.x; vj[1] = nb.b.y; vj[2] = nb.b.z; pVj = nb.b.w;
+        rhoj = nb.rho;
+    } else {
+        uj[0] = nb.a.x; uj[1] = nb.a.y; Vj = nb.a.z; pVj = nb.a.w;
+        vj[0] = nb.b.x; vj[1] = nb.b.y; rhoj = nb.b.z;
+    }
+    T r2 = 0, ue = 0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        T dd = ui[k] - uj[k];
+        dd -= c.L * rint(dd * c.invL);
+        d[k] = dd;
+        r2 += dd * dd;
+        ue += (vi[k] - vj[k]) * dd;
+    }
+    const T q = fast_sqrt(r2) * c.invH;
+    const T t = T(1) - q;
+    const T t2 = t * t;
+    const T t4 = t2 * t2;
+    const T t5 = t4 * t;
+    const T gF = c.kG * (T(-56.0 / 3.0) * t5 * (T(1) + T(5) * q));  // grad W = gF x_ij
+    const T inv = fast_rcp(r2 + c.epsH2);
+    const T pij = ue * inv;
+    const T cg = ((c.cA * pij - pi) * Vj - pVj) * gF;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) acc.ax[k] += cg * d[k];
+    acc.rdv += Vj * (gF * ue);
+    acc.rdd += Vj * (rhoi - rhoj) * (gF * r2 * inv);
+    if (RHOSUM) acc.rs += t4 * t2 * (T(1) + q * (T(6) + q * T(35.0 / 3.0)));
+}
+
+// Cell assignment of the next step's sort, done by the sweep that produced the positions
+// (same arithmetic as k_assign).  Null cell_count: no sort follows.
+struct NextCells {
+    const int32_t* blk_rank;
+    int32_t* cell_count;
+    int32_t* cell_of;
+    int32_t* slot_of;
+};
+
+// The neighbour list positions of lane r among the LPP lanes of a particle are
+// k = r + LPP m (m = 0, 1, ...); position k belongs to partial sum k mod 4, which is
+// accumulator m mod (4 / LPP) of the lane.  Lanes load kPairsInFlight positions before
+// computing them, in increasing m.
+template <typename T, int DIM, int MODE, int LPP>
+__global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const int32_t* __restrict__ nbr,
                                                const int32_t* __restrict__ nbr_count,
                                                const vec4_t<T>* __restrict__ jd0, const vec4_t<T>* __restrict__ jd1,
                                                StatePtrs<T, DIM> cur, StatePtrs<T, DIM> dst,
                                                const int32_t* __restrict__ orig, T* __restrict__ drho_out,
                                                T* __restrict__ acc_out, T* __restrict__ rhosum_out,
                                                const int32_t* __restrict__ psim,
-                                               const SimConst<T>* __restrict__ sims, int32_t* __restrict__ status)
+                                               const SimConst<T>* __restrict__ sims, int32_t* __restrict__ status,
+                                               NextCells next)
 {
-    const int64_t i = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    constexpr int NQ = 4 / LPP;
+    constexpr int U = kPairsInFlight;
+    const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int64_t i = t / LPP;
+    const int r = (int)(t - i * LPP);
     if (i >= N) return;
     const int s = psim[i];
     const SimConst<T>& S = sims[s];
+    const PairConst<T> c = pair_const(S);
     T ui[3] = {0, 0, 0}, vi[3] = {0, 0, 0};
     unpack_u<T, DIM>(jd0[i], ui);
 #pragma unroll
     for (int k = 0; k < DIM; ++k) vi[k] = cur.v[k][i];
     const T rhoi = cur.rho[i];
     const T pi = tait(S, rhoi);
-    const T L = S.L, invL = S.invL, invH = S.invH, kG = S.kG, epsH2 = S.epsH2, cA = S.cA;
     int n = nbr_count[i];
-    n = n < maxnbr ? n : maxnbr;
-    T ax[3] = {0, 0, 0};
-    T rdv = 0, rdd = 0, rs = 0;
-    for (int k = 0; k < n; ++k) {
-        const int j = nbr[(int64_t)k * ld + i];
-        const vec4_t<T> a = jd0[j];
-        const vec4_t<T> b = jd1[j];
-        const T rhoj = cur.rho[j];
-        T uj[3], vj[3], d[3];
-        T Vj, pVj;
-        if (DIM == 3) {
-            uj[0] = a.x; uj[1] = a.y; uj[2] = a.z; Vj = a.w;
-            vj[0] = b.x; vj[1] = b.y; vj[2] = b.z; pVj = b.w;
-        } else {
-            uj[0] = a.x; uj[1] = a.y; Vj = a.z; pVj = a.w;
-            vj[0] = b.x; vj[1] = b.y;
-        }
-        T r2 = 0, ue = 0;
+    n = n < width ? n : width;
+    const int mcount = (n - r + LPP - 1) / LPP;
+    const int32_t* row = nbr + i * (int64_t)width;
+    FwdAcc<T, DIM> acc[NQ];
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-            T dd = ui[c] - uj[c];
-            dd -= L * rint(dd * invL);
-            d[c] = dd;
-            r2 += dd * dd;
-            ue += (vi[c] - vj[c]) * dd;
-        }
-        const T q = sqrt(r2) * invH;
-        const T t = T(1) - q;
-        const T t2 = t * t;
-        const T t4 = t2 * t2;
-        const T t5 = t4 * t;
-        const T gF = kG * (T(-56.0 / 3.0) * t5 * (T(1) + T(5) * q));  // grad W = gF x_ij
-        const T inv = T(1) / (r2 + epsH2);
-        const T pij = ue * inv;                                        // pi_ij
-        const T cg = ((cA * pij - pi) * Vj - pVj) * gF;
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) ax[c] += cg * d[c];
-        rdv += Vj * (gF * ue);                                         // V_j (v_i - v_j).gW
-        rdd += Vj * (rhoi - rhoj) * (gF * r2 * inv);                   // V_j (rho_i - rho_j) x_ij.gW / (r^2+eps H^2)
-        if (MODE == kModeRhs) rs += t4 * t2 * (T(1) + q * (T(6) + q * T(35.0 / 3.0)));
+    for (int q = 0; q < NQ; ++q) {
+        acc[q].ax[0] = acc[q].ax[1] = acc[q].ax[2] = T(0);
+        acc[q].rdv = acc[q].rdd = acc[q].rs = T(0);
     }
-    const T invrho = T(1) / rhoi;
-    T acc[3];
+    for (int m0 = 0; m0 < mcount; m0 += U) {
+        int jj[U];
+        if (LPP == 1) {
+            const int4 v4 = *reinterpret_cast<const int4*>(row + m0);
+            jj[0] = v4.x; jj[1] = v4.y; jj[2] = v4.z; jj[3] = v4.w;
+        } else {
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) acc[c] = ax[c] * invrho;
+            for (int u = 0; u < U; ++u) jj[u] = (m0 + u < mcount) ? row[r + LPP * (m0 + u)] : 0;
+        }
+        FwdNbr<T, DIM> nb[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t j = (m0 + u < mcount) ? (uint32_t)jj[u] : (uint32_t)i;
+            nb[u].a = ldo(jd0, j);
+            nb[u].b = ldo(jd1, j);
+            nb[u].rho = (DIM == 3) ? ldo(cur.rho, j) : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (m0 + u < mcount) fwd_pair<T, DIM, MODE == kModeRhs>(c, ui, vi, rhoi, pi, nb[u], acc[u % NQ]);
+    }
+    T ax[3] = {0, 0, 0};
+    T tmp[NQ];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) tmp[q] = acc[q].ax[k];
+        ax[k] = combine4<LPP>(tmp);
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) tmp[q] = acc[q].rdv;
+    const T rdv = combine4<LPP>(tmp);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) tmp[q] = acc[q].rdd;
+    const T rdd = combine4<LPP>(tmp);
+    T rs = 0;
+    if (MODE == kModeRhs) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) tmp[q] = acc[q].rs;
+        rs = combine4<LPP>(tmp);
+    }
+    if (r != 0) return;
+    const T invrho = T(1) / rhoi;
+    T a[3];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) a[k] = ax[k] * invrho;
     const T drho = rhoi * rdv + S.cD * rdd;
     if (MODE == kModeStep) {
         bool bad = !isfinite(drho);
         const T dt = S.dt;
+        int cc[3] = {0, 0, 0};
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-            const T vn = vi[c] + dt * acc[c];
-            const T xn = cur.x[c][i] + dt * vn;
-            dst.v[c][i] = vn;
-            dst.x[c][i] = xn;
+        for (int k = 0; k < DIM; ++k) {
+            const T vn = vi[k] + dt * a[k];
+            const T xn = cur.x[k][i] + dt * vn;
+            dst.v[k][i] = vn;
+            dst.x[k][i] = xn;
             bad = bad || !isfinite(vn) || !isfinite(xn);
+            cc[k] = cell_coord(wrap_pos(isfinite(xn) ? xn : T(0), S.L, S.invL), S.cinv, S.nc);
         }
         dst.rho[i] = rhoi + dt * drho;
         if (bad) atomicOr(&status[s], kFlagNonfinite);
+        if (next.cell_count) {
+            const int gcell = global_cell<T, DIM>(S, next.blk_rank, cc[0], cc[1], cc[2]);
+            next.cell_of[i] = gcell;
+            next.slot_of[i] = atomicAdd(&next.cell_count[gcell], 1);
+        }
     } else {
         const int o = orig[i];
         drho_out[o] = drho;
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) acc_out[(int64_t)c * N + o] = acc[c];
+        for (int k = 0; k < DIM; ++k) acc_out[(int64_t)k * N + o] = a[k];
         if (rhosum_out) rhosum_out[o] = S.m * S.kW * rs;
     }
 }
@@ -623,14 +880,91 @@ __global__ __launch_bounds__(256) void k_adj_prologue(int64_t N, const int32_t* 
     jdB[q] = b;
 }
 
-// Adjoint sweep, gather form.  For particle k and each neighbour j != k it adds the partial
+template <typename T, int DIM>
+struct AdjAcc {
+    T gx[3], gv[3];
+    T gr;
+};
+
+// Per-particle adjoint record of a neighbour: jd0 = (u, V), jd1 = (v, p V), jdA = (abar, rbar)
+// (2D: (u, V, p V), (v, rho, 0), (abar, rbar, 0)), jdB = (rho, p, 1/rho, dp/drho).
+template <typename T>
+struct AdjNbr {
+    vec4_t<T> a, b, A, B;
+};
+
+// Adjoint pair terms, gather form.  For particle k and a neighbour j != k: the partial
 // derivatives, with respect to k's position, velocity and density, of the two directed pair
 // terms (k,j) and (j,k) contracted with their particles' cotangents (abar, rbar).  With
 // e = x_kj, G = gF e, the kernel Hessian Jg = gF I + hF e e^T, pi = (v_k - v_j).e / (r^2+eps H^2),
-// s = e.G / (r^2+eps H^2), these partials reduce to the closed forms below.
+// s = e.G / (r^2+eps H^2), these partials reduce to the closed forms below.  The self pair
+// contributes exactly zero.
 template <typename T, int DIM>
-__global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int64_t ld, int32_t maxnbr,
-                                                   const int32_t* __restrict__ nbr,
+__device__ __forceinline__ void adj_pair(const PairConst<T>& c, const T* uk, const T* vk, const T* ak, T rbk, T Vk,
+                                         T rhok, T pk, T irk, T dpk, const AdjNbr<T>& nb, AdjAcc<T, DIM>& acc)
+{
+    T uj[3], vj[3], aj[3];
+    T Vj, rbj;
+    if (DIM == 3) {
+        uj[0] = nb.a.x; uj[1] = nb.a.y; uj[2] = nb.a.z; Vj = nb.a.w;
+        vj[0] = nb.b.x; vj[1] = nb.b.y; vj[2] = nb.b.z;
+        aj[0] = nb.A.x; aj[1] = nb.A.y; aj[2] = nb.A.z; rbj = nb.A.w;
+    } else {
+        uj[0] = nb.a.x; uj[1] = nb.a.y; Vj = nb.a.z;
+        vj[0] = nb.b.x; vj[1] = nb.b.y;
+        aj[0] = nb.A.x; aj[1] = nb.A.y; rbj = nb.A.z;
+    }
+    const T rhoj = nb.B.x, pj = nb.B.y, irj = nb.B.z;
+    const T cA = c.cA, cD = c.cD;
+    T e[3], u[3];
+    T r2 = 0, ue = 0, ake = 0, aje = 0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        T dd = uk[k] - uj[k];
+        dd -= c.L * rint(dd * c.invL);
+        e[k] = dd;
+        u[k] = vk[k] - vj[k];
+        r2 += dd * dd;
+        ue += u[k] * dd;
+        ake += ak[k] * dd;
+        aje += aj[k] * dd;
+    }
+    const T q = fast_sqrt(r2) * c.invH;
+    const T t = T(1) - q;
+    const T t2 = t * t;
+    const T t4 = t2 * t2;
+    const T gF = c.kG * (T(-56.0 / 3.0) * t4 * t * (T(1) + T(5) * q));  // grad W = gF e
+    const T hF = c.kH * t4;                                              // Hessian: gF I + hF e e^T
+    const T inv = fast_rcp(r2 + c.epsH2);
+    const T pij = ue * inv;
+    const T sij = gF * r2 * inv;
+    const T sig = inv * (T(2) * gF + hF * r2 - T(2) * sij);              // d s / d e = sig e
+    const T aGk = gF * ake, aGj = gF * aje, uG = gF * ue;
+    const T Qk = (cA * pij - pk - pj) * irk;
+    const T Qj = (cA * pij - pj - pk) * irj;
+    const T beta = cA * inv * (Vj * aGk * irk - Vk * aGj * irj);
+    const T gam = Vj * rbk * rhok + Vk * rbj * rhoj;
+    const T cdr = cD * sig * (rhok - rhoj) * (Vj * rbk - Vk * rbj);
+    T w[3];
+    T ew = 0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        w[k] = Vj * Qk * ak[k] - Vk * Qj * aj[k] + gam * u[k];
+        ew += e[k] * w[k];
+    }
+    const T ce = cdr - T(2) * beta * pij + hF * ew;  // coefficient of e in the position cotangent
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        acc.gx[k] += beta * u[k] + ce * e[k] + gF * w[k];
+        acc.gv[k] += (beta + gam * gF) * e[k];
+    }
+    const T phi2 = Vk * (-Qj * aGj + rbj * rhoj * uG + rbj * cD * (rhoj - rhok) * sij);
+    acc.gr += Vj * (aGk * (-dpk - Qk) * irk + rbk * uG + rbk * cD * sij) - phi2 * irk +
+              Vk * (aGj * dpk * irj - rbj * cD * sij);
+}
+
+template <typename T, int DIM, int LPP>
+__global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, const int32_t* __restrict__ nbr,
                                                    const int32_t* __restrict__ nbr_count,
                                                    const vec4_t<T>* __restrict__ jd0,
                                                    const vec4_t<T>* __restrict__ jd1,
@@ -640,11 +974,15 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int64_t ld, int32_
                                                    const int32_t* __restrict__ psim,
                                                    const SimConst<T>* __restrict__ sims, int32_t* __restrict__ status)
 {
-    const int64_t k = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    constexpr int NQ = 4 / LPP;
+    constexpr int U = kPairsInFlight;
+    const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int64_t k = t / LPP;
+    const int r = (int)(t - k * LPP);
     if (k >= N) return;
     const int s = psim[k];
     const SimConst<T>& S = sims[s];
-    const T L = S.L, invL = S.invL, invH = S.invH, kG = S.kG, kH = S.kH, epsH2 = S.epsH2, cA = S.cA, cD = S.cD;
+    const PairConst<T> c = pair_const(S);
     T uk[3] = {0, 0, 0}, vk[3] = {0, 0, 0}, ak[3] = {0, 0, 0};
     T Vk, rbk;
     {
@@ -661,82 +999,64 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int64_t ld, int32_
     }
     const vec4_t<T> Bk = jdB[k];
     const T rhok = Bk.x, pk = Bk.y, irk = Bk.z, dpk = Bk.w;
-    T gx[3] = {0, 0, 0}, gv[3] = {0, 0, 0};
-    T gr = 0;
     int n = nbr_count[k];
-    n = n < maxnbr ? n : maxnbr;
-    for (int m = 0; m < n; ++m) {
-        const int j = nbr[(int64_t)m * ld + k];
-        const vec4_t<T> a = jd0[j], b = jd1[j], A = jdA[j], Bj = jdB[j];
-        T uj[3], vj[3], aj[3];
-        T Vj, rbj;
-        if (DIM == 3) {
-            uj[0] = a.x; uj[1] = a.y; uj[2] = a.z; Vj = a.w;
-            vj[0] = b.x; vj[1] = b.y; vj[2] = b.z;
-            aj[0] = A.x; aj[1] = A.y; aj[2] = A.z; rbj = A.w;
-        } else {
-            uj[0] = a.x; uj[1] = a.y; Vj = a.z;
-            vj[0] = b.x; vj[1] = b.y;
-            aj[0] = A.x; aj[1] = A.y; rbj = A.z;
-        }
-        const T rhoj = Bj.x, pj = Bj.y, irj = Bj.z;
-        T e[3], u[3];
-        T r2 = 0, ue = 0, ake = 0, aje = 0;
+    n = n < width ? n : width;
+    const int mcount = (n - r + LPP - 1) / LPP;
+    const int32_t* row = nbr + k * (int64_t)width;
+    AdjAcc<T, DIM> acc[NQ];
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-            T dd = uk[c] - uj[c];
-            dd -= L * rint(dd * invL);
-            e[c] = dd;
-            u[c] = vk[c] - vj[c];
-            r2 += dd * dd;
-            ue += u[c] * dd;
-            ake += ak[c] * dd;
-            aje += aj[c] * dd;
-        }
-        const T q = sqrt(r2) * invH;
-        const T t = T(1) - q;
-        const T t2 = t * t;
-        const T t4 = t2 * t2;
-        const T gF = kG * (T(-56.0 / 3.0) * t4 * t * (T(1) + T(5) * q));  // grad W = gF e
-        const T hF = kH * t4;                                              // Hessian: gF I + hF e e^T
-        const T inv = T(1) / (r2 + epsH2);
-        const T pij = ue * inv;
-        const T sij = gF * r2 * inv;
-        const T sig = inv * (T(2) * gF + hF * r2 - T(2) * sij);            // d s / d e = sig e
-        const T aGk = gF * ake, aGj = gF * aje, uG = gF * ue;
-        const T Qk = (cA * pij - pk - pj) * irk;
-        const T Qj = (cA * pij - pj - pk) * irj;
-        const T beta = cA * inv * (Vj * aGk * irk - Vk * aGj * irj);
-        const T gam = Vj * rbk * rhok + Vk * rbj * rhoj;
-        const T cdr = cD * sig * (rhok - rhoj) * (Vj * rbk - Vk * rbj);
-        T w[3];
-        T ew = 0;
+    for (int q = 0; q < NQ; ++q) {
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-            w[c] = Vj * Qk * ak[c] - Vk * Qj * aj[c] + gam * u[c];
-            ew += e[c] * w[c];
-        }
-        const T hew = hF * ew;
-        const T ce = cdr - T(2) * beta * pij + hew;   // coefficient of e in the position cotangent
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-            gx[c] += beta * u[c] + ce * e[c] + gF * w[c];
-            gv[c] += (beta + gam * gF) * e[c];
-        }
-        const T phi2 = Vk * (-Qj * aGj + rbj * rhoj * uG + rbj * cD * (rhoj - rhok) * sij);
-        gr += Vj * (aGk * (-dpk - Qk) * irk + rbk * uG + rbk * cD * sij) - phi2 * irk +
-              Vk * (aGj * dpk * irj - rbj * cD * sij);
+        for (int d = 0; d < 3; ++d) acc[q].gx[d] = acc[q].gv[d] = T(0);
+        acc[q].gr = T(0);
     }
+    for (int m0 = 0; m0 < mcount; m0 += U) {
+        int jj[U];
+        if (LPP == 1) {
+            const int4 v4 = *reinterpret_cast<const int4*>(row + m0);
+            jj[0] = v4.x; jj[1] = v4.y; jj[2] = v4.z; jj[3] = v4.w;
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) jj[u] = (m0 + u < mcount) ? row[r + LPP * (m0 + u)] : 0;
+        }
+        AdjNbr<T> nb[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t j = (m0 + u < mcount) ? (uint32_t)jj[u] : (uint32_t)k;
+            nb[u].a = ldo(jd0, j);
+            nb[u].b = ldo(jd1, j);
+            nb[u].A = ldo(jdA, j);
+            nb[u].B = ldo(jdB, j);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (m0 + u < mcount) adj_pair<T, DIM>(c, uk, vk, ak, rbk, Vk, rhok, pk, irk, dpk, nb[u], acc[u % NQ]);
+    }
+    T gx[3] = {0, 0, 0}, gv[3] = {0, 0, 0};
+    T tmp[NQ];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) tmp[q] = acc[q].gx[d];
+        gx[d] = combine4<LPP>(tmp);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) tmp[q] = acc[q].gv[d];
+        gv[d] = combine4<LPP>(tmp);
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) tmp[q] = acc[q].gr;
+    const T gr = combine4<LPP>(tmp);
+    if (r != 0) return;
     const int o = orig[k];
     const T dt = S.dt;
     bool bad = !isfinite(gr);
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) {
-        const T xb = cot.x[c][o];
-        const T vb = cot.v[c][o];
-        cot.x[c][o] = xb + gx[c];
-        cot.v[c][o] = vb + dt * xb + gv[c];
-        bad = bad || !isfinite(gx[c]) || !isfinite(gv[c]);
+    for (int d = 0; d < DIM; ++d) {
+        const T xb = cot.x[d][o];
+        const T vb = cot.v[d][o];
+        cot.x[d][o] = xb + gx[d];
+        cot.v[d][o] = vb + dt * xb + gv[d];
+        bad = bad || !isfinite(gx[d]) || !isfinite(gv[d]);
     }
     cot.rho[o] = cot.rho[o] + gr;
     if (bad) atomicOr(&status[s], kFlagNonfinite);
@@ -745,38 +1065,39 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int64_t ld, int32_
 // ---------------------------------------------------------------- neighbour export (CSR, original indices)
 
 __global__ __launch_bounds__(256) void k_export_counts(int64_t N, const int32_t* __restrict__ orig,
-                                                       const int32_t* __restrict__ nbr_count, int32_t maxnbr,
+                                                       const int32_t* __restrict__ nbr_count, int32_t width,
                                                        int64_t* __restrict__ rowcnt)
 {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= N) return;
     int c = nbr_count[q];
-    rowcnt[orig[q]] = c < maxnbr ? c : maxnbr;
+    rowcnt[orig[q]] = c < width ? c : width;
 }
 
 // one wavefront per row: entries mapped to original indices and written in ascending order
 // (each entry's rank in its row by comparison with every other entry of the row)
-__global__ __launch_bounds__(64) void k_export_rows(int64_t N, int64_t ld, const int32_t* __restrict__ orig,
+__global__ __launch_bounds__(64) void k_export_rows(int64_t N, int32_t width, const int32_t* __restrict__ orig,
                                                     const int32_t* __restrict__ nbr,
-                                                    const int32_t* __restrict__ nbr_count, int32_t maxnbr,
+                                                    const int32_t* __restrict__ nbr_count,
                                                     const int64_t* __restrict__ offsets, int32_t* __restrict__ out)
 {
     __shared__ int32_t row[1024];
     const int64_t q = (int64_t)xcd_remap(blockIdx.x, gridDim.x);
     if (q >= N) return;
     int c = nbr_count[q];
-    c = c < maxnbr ? c : maxnbr;
+    c = c < width ? c : width;
+    const int32_t* src = nbr + q * (int64_t)width;
     const int64_t base = offsets[orig[q]];
     for (int m0 = 0; m0 < c; m0 += 1024) {
         // rows longer than 1024 are handled by ranking each chunk against the full row
         const int mc = (c - m0 < 1024) ? c - m0 : 1024;
-        for (int m = threadIdx.x; m < mc; m += 64) row[m] = orig[nbr[(int64_t)(m0 + m) * ld + q]];
+        for (int m = threadIdx.x; m < mc; m += 64) row[m] = orig[src[m0 + m]];
         __syncthreads();
         for (int m = threadIdx.x; m < mc; m += 64) {
             const int v = row[m];
             int rank = 0;
-            for (int r = 0; r < c; ++r) {
-                const int w = (r >= m0 && r < m0 + mc) ? row[r - m0] : orig[nbr[(int64_t)r * ld + q]];
+            for (int r2 = 0; r2 < c; ++r2) {
+                const int w = (r2 >= m0 && r2 < m0 + mc) ? row[r2 - m0] : orig[src[r2]];
                 rank += (w < v) ? 1 : 0;
             }
             out[base + rank] = v;

@@ -57,7 +57,14 @@ def lib():
         st = ctypes.c_int32
         L.sph_plan_create.restype = st
         L.sph_plan_create.argtypes = [ctypes.POINTER(SphParams), ctypes.c_int32, ctypes.POINTER(ctypes.c_int64),
-                                      ctypes.c_int32, ctypes.POINTER(_VP)]
+                                      ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_VP)]
+        L.sph_set_tuning.restype = st
+        L.sph_set_tuning.argtypes = [_VP, ctypes.c_int32, ctypes.c_int32]
+        L.sph_get_tuning.restype = st
+        L.sph_get_tuning.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+        L.sph_rollout_backward.restype = st
+        L.sph_rollout_backward.argtypes = [_VP, ctypes.POINTER(SphState), ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.POINTER(SphState), _VP]
         L.sph_plan_destroy.restype = None
         L.sph_plan_destroy.argtypes = [_VP]
         L.sph_workspace_size.restype = st
@@ -81,6 +88,12 @@ def lib():
         L.sph_step_adjoint.argtypes = [_VP, ctypes.POINTER(SphState), ctypes.POINTER(SphState), _VP]
         L.sph_poll.restype = st
         L.sph_poll.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32), _VP]
+        L.sph_pair_count.restype = st
+        L.sph_pair_count.argtypes = [_VP, ctypes.POINTER(ctypes.c_int64), _VP]
+        L.sph_profile_enable.restype = st
+        L.sph_profile_enable.argtypes = [_VP, ctypes.c_int32]
+        L.sph_profile_read.restype = st
+        L.sph_profile_read.argtypes = [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.sph_last_error.restype = ctypes.c_char_p
         L.sph_last_error.argtypes = []
         _lib = L
@@ -96,7 +109,11 @@ def exported_symbols() -> List[str]:
     """Names the binding expects libsph.so to export."""
     return ["sph_plan_create", "sph_plan_destroy", "sph_workspace_size", "sph_plan_info", "sph_bind",
             "sph_build_cells", "sph_neighbors", "sph_rhs", "sph_step", "sph_step_adjoint", "sph_poll",
-            "sph_last_error"]
+            "sph_pair_count", "sph_profile_enable", "sph_profile_read", "sph_last_error", "sph_set_tuning",
+            "sph_get_tuning", "sph_rollout_backward"]
+
+
+KERNEL_CLASSES = ["sort", "build", "sweep", "adjoint", "other"]
 
 
 def _stream_ptr(stream=None) -> int:
@@ -115,7 +132,8 @@ class Plan:
     """A bound plan: host plan + device workspace for a batch of simulations."""
 
     def __init__(self, sims: Sequence[dict], counts: Sequence[int], dtype: str = "f32",
-                 max_neighbors: int = 0, device: Optional[torch.device] = None, stream=None):
+                 max_neighbors: int = 0, tape_depth: int = 8, device: Optional[torch.device] = None,
+                 stream=None):
         L = lib()
         self.dtype = dtype
         self.torch_dtype = torch.float64 if dtype == "f64" else torch.float32
@@ -124,7 +142,8 @@ class Plan:
         arr = (SphParams * n)(*[make_params(p, dtype) for p in sims])
         cnt = (ctypes.c_int64 * n)(*[int(c) for c in counts])
         h = _VP()
-        _check(L.sph_plan_create(arr, n, cnt, int(max_neighbors), ctypes.byref(h)))
+        _check(L.sph_plan_create(arr, n, cnt, int(max_neighbors), int(tape_depth), ctypes.byref(h)))
+        self.tape_depth = int(tape_depth)
         self._h = h
         self.counts = [int(c) for c in counts]
         self.offsets = np.concatenate([[0], np.cumsum(self.counts)]).astype(np.int64)
@@ -212,6 +231,41 @@ class Plan:
         s = self.state(x, v, rho)
         c = self.state(gx, gv, grho)
         _check(lib().sph_step_adjoint(self._h, ctypes.byref(s), ctypes.byref(c), _stream_ptr(stream)))
+
+    def rollout_backward(self, ckpt: List[tuple], nsteps: int, ckpt_every: int, gx, gv, grho, stream=None):
+        """Cotangents (gx, gv, grho) of the state after nsteps steps -> those of the initial state, in place,
+        from the checkpoints sph_step wrote."""
+        need = (nsteps + ckpt_every - 1) // ckpt_every if nsteps > 0 else 0
+        if len(ckpt) < need:
+            raise ValueError("need %d checkpoint slots" % need)
+        cp = (SphState * max(need, 1))(*[self.state(*c) for c in ckpt[:need]])
+        c = self.state(gx, gv, grho)
+        _check(lib().sph_rollout_backward(self._h, cp, int(nsteps), int(ckpt_every), ctypes.byref(c),
+                                          _stream_ptr(stream)))
+
+    def set_tuning(self, lanes_fwd: int, lanes_adj: int):
+        _check(lib().sph_set_tuning(self._h, int(lanes_fwd), int(lanes_adj)))
+
+    def get_tuning(self) -> Tuple[int, int]:
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().sph_get_tuning(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return int(a.value), int(b.value)
+
+    def pair_count(self, stream=None) -> int:
+        """Directed neighbour pairs (j != i) found by list builds since the last call."""
+        v = ctypes.c_int64()
+        _check(lib().sph_pair_count(self._h, ctypes.byref(v), _stream_ptr(stream)))
+        return int(v.value)
+
+    def profile(self, enable: bool = True):
+        _check(lib().sph_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        """{class: (milliseconds, launches)} accumulated since the last read."""
+        ms = (ctypes.c_double * len(KERNEL_CLASSES))()
+        n = (ctypes.c_int64 * len(KERNEL_CLASSES))()
+        _check(lib().sph_profile_read(self._h, ms, n))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_CLASSES)}
 
     def poll(self, stream=None) -> np.ndarray:
         out = (ctypes.c_int32 * self.nsims)()

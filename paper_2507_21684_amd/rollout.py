@@ -2,9 +2,11 @@
 
 The forward pass advances the state with `sph_step`, keeping only a checkpoint of the state
 every K steps (the paper's gradient checkpointing, Sec. 3: only particle data are retained,
-intermediate pair quantities are recomputed).  The backward pass walks the segments in
-reverse: it recomputes the segment's states from its checkpoint with `sph_step` and applies
-`sph_step_adjoint` step by step, which returns (dP/du)^T a for one step (Sec. 2.2).
+intermediate pair quantities are recomputed).  The backward pass is `sph_rollout_backward`:
+segment by segment in reverse, it recomputes the segment from its checkpoint (keeping each
+step's sorted state and neighbour lists in the plan's tape) and applies the one-step
+vector-Jacobian product (Sec. 2.2) to every step in reverse.  The plan's tape_depth must be
+at least K.
 """
 from __future__ import annotations
 
@@ -42,17 +44,8 @@ class SPHRollout(torch.autograd.Function):
         cx = gx.detach().clone().contiguous() if gx is not None else torch.zeros_like(ref[0])
         cv = gv.detach().clone().contiguous() if gv is not None else torch.zeros_like(ref[1])
         cr = grho.detach().clone().contiguous() if grho is not None else torch.zeros_like(ref[2])
-        T, K = ctx.nsteps, ctx.K
-        for seg in reversed(range(ctx.nseg)):
-            start = seg * K
-            length = min(K, T - start)
-            states = [ckpts[seg]]
-            for _ in range(1, length):
-                s = tuple(t.clone() for t in states[-1])
-                plan.step(*s, 1)
-                states.append(s)
-            for i in reversed(range(length)):
-                plan.step_adjoint(*states[i], cx, cv, cr)
+        if ctx.nsteps > 0:
+            plan.rollout_backward(ckpts, ctx.nsteps, ctx.K, cx, cv, cr)
         return cx, cv, cr, None, None, None
 
 

@@ -27,11 +27,11 @@ def test_exports_every_declared_symbol():
     assert sorted(L.exported_symbols()) == declared
 
 
-def _plan(params, counts, maxn=0):
+def _plan(params, counts, maxn=0, tape=0):
     arr = (L.SphParams * len(params))(*params)
     cnt = (ctypes.c_int64 * len(counts))(*counts)
     h = ctypes.c_void_p()
-    rc = L.lib().sph_plan_create(arr, len(params), cnt, maxn, ctypes.byref(h))
+    rc = L.lib().sph_plan_create(arr, len(params), cnt, maxn, tape, ctypes.byref(h))
     return rc, h
 
 
@@ -52,9 +52,21 @@ def test_plan_create_and_sizes():
     assert tot.value == 65536 and ns.value == 1
     # automatic width: 1.6 x (pi H^2 / dx^2) rounded up to 8
     assert mn.value == 88
-    # the neighbour list dominates: width x padded N x 4 bytes, plus O(N) arrays
-    assert mn.value * 65536 * 4 < size.value < mn.value * 65536 * 4 + 400 * 65536
+    # two neighbour-list slots dominate: 2 x width x N x 4 bytes, plus O(N) arrays
+    lists = 2 * mn.value * 65536 * 4
+    assert lists < size.value < lists + 600 * 65536
     L.lib().sph_plan_destroy(h)
+    # a tape of 8 steps holds 8 slots
+    rc, h8 = _plan([_p(spec)], [spec.n], 0, 8)
+    size8 = ctypes.c_size_t()
+    L.lib().sph_workspace_size(h8, ctypes.byref(size8))
+    assert 8 * mn.value * 65536 * 4 < size8.value < 8 * (mn.value * 65536 * 4 + 100 * 65536) + 300 * 65536
+    lf, la = ctypes.c_int32(), ctypes.c_int32()
+    assert L.lib().sph_get_tuning(h8, ctypes.byref(lf), ctypes.byref(la)) == 0
+    assert (lf.value, la.value) == (4, 4)
+    assert L.lib().sph_set_tuning(h8, 2, 1) == 0
+    assert L.lib().sph_set_tuning(h8, 3, 1) == -1
+    L.lib().sph_plan_destroy(h8)
 
 
 @pytest.mark.parametrize("kw,code", [
@@ -101,4 +113,11 @@ def test_calls_need_bound_plan():
     rc, h = _plan([_p(spec)], [spec.n])
     st = L.SphState()
     assert L.lib().sph_build_cells(h, ctypes.byref(st), None) == -7
+    assert L.lib().sph_rollout_backward(h, None, 4, 2, ctypes.byref(st), None) == -7
     L.lib().sph_plan_destroy(h)
+
+
+def test_tape_depth_validation():
+    spec = SimSpec(2, 16)
+    rc, _ = _plan([_p(spec)], [spec.n], 0, -1)
+    assert rc == -1

@@ -47,6 +47,7 @@ def _plan(specs, dtype, **kw):
     return Plan([s.params() for s in specs], [s.n for s in specs], dtype, **kw)
 
 
+
 def _oparams(orc, spec):
     return orc.Params(**spec.params())
 
@@ -227,3 +228,50 @@ def test_full_size_rhs_sampled(orc, dim, side):
     assert _max_norm_err(acc, a_r) <= 1e-4
     assert _max_norm_err(drho, d_r) <= 1e-4
     assert np.all(plan.poll() == 0)
+
+
+@pytest.mark.parametrize("dim,side", [(2, 40), (3, 14)])
+def test_lanes_per_particle_bitwise(dim, side):
+    """The sweeps give bitwise identical results for 1, 2 and 4 lanes per particle."""
+    spec = SimSpec(dim, side, jitter=0.2)
+    st = _inputs(spec, 21, "f32", rho_noise=0.01, v_noise=0.2)
+    rng = np.random.default_rng(22)
+    cot = [rng.normal(size=a.shape).astype(np.float32) for a in st]
+    outs = []
+    for lanes in (1, 2, 4):
+        plan = _plan([spec], "f32")
+        plan.set_tuning(lanes, lanes)
+        g = _to_gpu(st, "f32")
+        rhs = [t.cpu().numpy() for t in plan.rhs(*g)]
+        plan.step(*g, 3)
+        c = _to_gpu(cot, "f32")
+        plan.step_adjoint(*g, *c)
+        outs.append(rhs + [t.cpu().numpy() for t in g] + [t.cpu().numpy() for t in c])
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            np.testing.assert_array_equal(a, b)
+
+
+def test_taped_backward_equals_per_step_adjoints():
+    """sph_rollout_backward (tape) equals recomputing each state and calling sph_step_adjoint."""
+    spec = SimSpec(2, 32)
+    st = _inputs(spec, 4, "f32")
+    T, K = 7, 3
+    plan = _plan([spec], "f32", tape_depth=K)
+    g = _to_gpu(st, "f32")
+    ck = [plan.empty_state() for _ in range(3)]
+    plan.step(*g, T, ck, K)
+    rng = np.random.default_rng(5)
+    cot = [rng.normal(size=a.shape).astype(np.float32) for a in st]
+    c1 = _to_gpu(cot, "f32")
+    plan.rollout_backward(ck, T, K, *c1)
+    states = [_to_gpu(st, "f32")]
+    for _ in range(T - 1):
+        s2 = [t.clone() for t in states[-1]]
+        plan.step(*s2, 1)
+        states.append(s2)
+    c2 = _to_gpu(cot, "f32")
+    for n in reversed(range(T)):
+        plan.step_adjoint(*states[n], *c2)
+    for a, b in zip(c1, c2):
+        assert torch.equal(a, b)
