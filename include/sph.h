@@ -121,11 +121,10 @@ sph_status sph_plan_info(const sph_plan* plan, int64_t* total_particles, int32_t
                          int32_t* max_neighbors);
 
 /* Lanes that share one particle in the forward sweep and in the adjoint sweep
- * (1, 2 or 4).  A particle's pair sums are always formed as four partial sums
- * over list positions k mod 4 combined as (s0 + s1) + (s2 + s3), so results
- * are bitwise the same for every setting; only speed changes.  The default
- * gives every SIMD several wavefronts (4 up to 2^18 particles, 2 up to 2^20,
- * else 1). */
+ * (2, 4 or 8; default 4).  A particle's pair sums are always formed as eight
+ * partial sums over list positions k mod 8 combined by the balanced tree
+ * ((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7)), so results are bitwise
+ * the same for every setting; only speed changes.  INVALID_ARG otherwise. */
 sph_status sph_set_tuning(sph_plan* plan, int32_t lanes_fwd, int32_t lanes_adj);
 sph_status sph_get_tuning(const sph_plan* plan, int32_t* lanes_fwd, int32_t* lanes_adj);
 

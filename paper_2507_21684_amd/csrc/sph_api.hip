@@ -323,8 +323,8 @@ sph_status sweep(sph_plan* P, int slot, T* drho, T* acc, T* rhosum, hipStream_t 
     if (assign_next) next.cell_count = wsp<int32_t>(P, P->o_cell_count);
     ProfScope prof(P, st, SPH_KERN_SWEEP);
     switch (P->lpp_fwd) {
-    case 1: launch_sweep<T, D, MODE, 1>(P, L, drho, acc, rhosum, next, st); break;
     case 2: launch_sweep<T, D, MODE, 2>(P, L, drho, acc, rhosum, next, st); break;
+    case 8: launch_sweep<T, D, MODE, 8>(P, L, drho, acc, rhosum, next, st); break;
     default: launch_sweep<T, D, MODE, 4>(P, L, drho, acc, rhosum, next, st); break;
     }
     LAUNCH_CHECK("sweep");
@@ -367,8 +367,8 @@ sph_status adjoint(sph_plan* P, int slot, StatePtrs<T, D> cot, hipStream_t st)
     }
     ProfScope prof(P, st, SPH_KERN_ADJOINT);
     switch (P->lpp_adj) {
-    case 1: launch_adj<T, D, 1>(P, L, cot, st); break;
     case 2: launch_adj<T, D, 2>(P, L, cot, st); break;
+    case 8: launch_adj<T, D, 8>(P, L, cot, st); break;
     default: launch_adj<T, D, 4>(P, L, cot, st); break;
     }
     LAUNCH_CHECK("adj_sweep");
@@ -630,8 +630,8 @@ sph_status sph_plan_create(const sph_params* sims, int32_t nsims, const int64_t*
     if (P->width < 8) P->width = 8;
     P->tape_depth = tape_depth;
     P->nslots = std::max(2, tape_depth);
-    // lanes per particle of the sweeps: enough lanes to give every SIMD several wavefronts
-    P->lpp_fwd = P->lpp_adj = (P->N <= (1 << 18)) ? 4 : (P->N <= (1 << 20) ? 2 : 1);
+    // lanes per particle of the sweeps (the autotuner may change it; results do not depend on it)
+    P->lpp_fwd = P->lpp_adj = 4;
 
     // host tables: particle -> simulation, cell -> simulation, block tables in Morton order
     P->h_psim.resize((size_t)P->N);
@@ -766,8 +766,8 @@ sph_status sph_plan_info(const sph_plan* plan, int64_t* total_particles, int32_t
 sph_status sph_set_tuning(sph_plan* plan, int32_t lanes_fwd, int32_t lanes_adj)
 {
     if (!plan) return fail(SPH_ERR_INVALID_ARG, "plan is null");
-    auto ok = [](int32_t v) { return v == 1 || v == 2 || v == 4; };
-    if (!ok(lanes_fwd) || !ok(lanes_adj)) return fail(SPH_ERR_INVALID_ARG, "lanes per particle must be 1, 2 or 4");
+    auto ok = [](int32_t v) { return v == 2 || v == 4 || v == 8; };
+    if (!ok(lanes_fwd) || !ok(lanes_adj)) return fail(SPH_ERR_INVALID_ARG, "lanes per particle must be 2, 4 or 8");
     plan->lpp_fwd = lanes_fwd;
     plan->lpp_adj = lanes_adj;
     return SPH_OK;

@@ -583,22 +583,27 @@ __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ c
 
 // ---------------------------------------------------------------- canonical pair sums
 //
-// A particle's neighbour sum is split into four partial sums s_q over list positions
-// k = q (mod 4), each accumulated in increasing k, and combined as (s0 + s1) + (s2 + s3).
-// LPP lanes share a particle (LPP in {1, 2, 4}): lane r holds the partial sums with
-// q = r (mod LPP).  The combined value is bitwise the same for every LPP.
+// A particle's neighbour sum is split into eight partial sums s_q over list positions
+// k = q (mod 8), each accumulated in increasing k, and combined by the balanced tree
+// ((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7)).  LPP lanes share a particle
+// (LPP in {2, 4, 8}): lane r holds the 8 / LPP partial sums with q = r (mod LPP).  The
+// first log2(LPP) levels of the tree combine lanes (xor shuffles; every lane of the group ends
+// with the same value because floating-point addition commutes), the remaining levels combine
+// a lane's own partial sums.  The result is bitwise the same for every LPP.
+constexpr int kLeaves = 8;
 
 template <int LPP, typename T>
-__device__ __forceinline__ T combine4(const T* a /* [4 / LPP] */)
+__device__ __forceinline__ T combine_leaves(T* a /* [kLeaves / LPP] */)
 {
-    if (LPP == 1) return (a[0] + a[1]) + (a[2] + a[3]);
-    if (LPP == 2) {
-        const T s01 = a[0] + __shfl_xor(a[0], 1, 64);
-        const T s23 = a[1] + __shfl_xor(a[1], 1, 64);
-        return s01 + s23;
+    constexpr int NQ = kLeaves / LPP;
+#pragma unroll
+    for (int o = 1; o < LPP; o <<= 1) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) a[q] = a[q] + __shfl_xor(a[q], o, 64);
     }
-    const T s01 = a[0] + __shfl_xor(a[0], 1, 64);
-    return s01 + __shfl_xor(s01, 2, 64);
+    if (NQ == 1) return a[0];
+    if (NQ == 2) return a[0] + a[1];
+    return (a[0] + a[1]) + (a[2] + a[3]);
 }
 
 // ---------------------------------------------------------------- gathers and fast arithmetic
@@ -713,8 +718,8 @@ struct NextCells {
 };
 
 // The neighbour list positions of lane r among the LPP lanes of a particle are
-// k = r + LPP m (m = 0, 1, ...); position k belongs to partial sum k mod 4, which is
-// accumulator m mod (4 / LPP) of the lane.  Lanes load kPairsInFlight positions before
+// k = r + LPP m (m = 0, 1, ...); position k belongs to partial sum k mod 8, which is
+// accumulator m mod (8 / LPP) of the lane.  Lanes load kPairsInFlight positions before
 // computing them, in increasing m.
 template <typename T, int DIM, int MODE, int LPP>
 __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const int32_t* __restrict__ nbr,
@@ -727,8 +732,9 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
                                                const SimConst<T>* __restrict__ sims, int32_t* __restrict__ status,
                                                NextCells next)
 {
-    constexpr int NQ = 4 / LPP;
+    constexpr int NQ = kLeaves / LPP;
     constexpr int U = kPairsInFlight;
+    static_assert(LPP >= 2 && LPP <= 8 && U % NQ == 0, "lanes per particle must be 2, 4 or 8");
     const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int64_t i = t / LPP;
     const int r = (int)(t - i * LPP);
@@ -754,13 +760,8 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
     }
     for (int m0 = 0; m0 < mcount; m0 += U) {
         int jj[U];
-        if (LPP == 1) {
-            const int4 v4 = *reinterpret_cast<const int4*>(row + m0);
-            jj[0] = v4.x; jj[1] = v4.y; jj[2] = v4.z; jj[3] = v4.w;
-        } else {
 #pragma unroll
-            for (int u = 0; u < U; ++u) jj[u] = (m0 + u < mcount) ? row[r + LPP * (m0 + u)] : 0;
-        }
+        for (int u = 0; u < U; ++u) jj[u] = (m0 + u < mcount) ? row[r + LPP * (m0 + u)] : 0;
         FwdNbr<T, DIM> nb[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -779,19 +780,19 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
     for (int k = 0; k < DIM; ++k) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) tmp[q] = acc[q].ax[k];
-        ax[k] = combine4<LPP>(tmp);
+        ax[k] = combine_leaves<LPP>(tmp);
     }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) tmp[q] = acc[q].rdv;
-    const T rdv = combine4<LPP>(tmp);
+    const T rdv = combine_leaves<LPP>(tmp);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) tmp[q] = acc[q].rdd;
-    const T rdd = combine4<LPP>(tmp);
+    const T rdd = combine_leaves<LPP>(tmp);
     T rs = 0;
     if (MODE == kModeRhs) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) tmp[q] = acc[q].rs;
-        rs = combine4<LPP>(tmp);
+        rs = combine_leaves<LPP>(tmp);
     }
     if (r != 0) return;
     const T invrho = T(1) / rhoi;
@@ -974,8 +975,9 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
                                                    const int32_t* __restrict__ psim,
                                                    const SimConst<T>* __restrict__ sims, int32_t* __restrict__ status)
 {
-    constexpr int NQ = 4 / LPP;
+    constexpr int NQ = kLeaves / LPP;
     constexpr int U = kPairsInFlight;
+    static_assert(LPP >= 2 && LPP <= 8 && U % NQ == 0, "lanes per particle must be 2, 4 or 8");
     const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int64_t k = t / LPP;
     const int r = (int)(t - k * LPP);
@@ -1012,13 +1014,8 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
     }
     for (int m0 = 0; m0 < mcount; m0 += U) {
         int jj[U];
-        if (LPP == 1) {
-            const int4 v4 = *reinterpret_cast<const int4*>(row + m0);
-            jj[0] = v4.x; jj[1] = v4.y; jj[2] = v4.z; jj[3] = v4.w;
-        } else {
 #pragma unroll
-            for (int u = 0; u < U; ++u) jj[u] = (m0 + u < mcount) ? row[r + LPP * (m0 + u)] : 0;
-        }
+        for (int u = 0; u < U; ++u) jj[u] = (m0 + u < mcount) ? row[r + LPP * (m0 + u)] : 0;
         AdjNbr<T> nb[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1038,14 +1035,14 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
     for (int d = 0; d < DIM; ++d) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) tmp[q] = acc[q].gx[d];
-        gx[d] = combine4<LPP>(tmp);
+        gx[d] = combine_leaves<LPP>(tmp);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) tmp[q] = acc[q].gv[d];
-        gv[d] = combine4<LPP>(tmp);
+        gv[d] = combine_leaves<LPP>(tmp);
     }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) tmp[q] = acc[q].gr;
-    const T gr = combine4<LPP>(tmp);
+    const T gr = combine_leaves<LPP>(tmp);
     if (r != 0) return;
     const int o = orig[k];
     const T dt = S.dt;

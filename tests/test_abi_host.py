@@ -64,8 +64,8 @@ def test_plan_create_and_sizes():
     lf, la = ctypes.c_int32(), ctypes.c_int32()
     assert L.lib().sph_get_tuning(h8, ctypes.byref(lf), ctypes.byref(la)) == 0
     assert (lf.value, la.value) == (4, 4)
-    assert L.lib().sph_set_tuning(h8, 2, 1) == 0
-    assert L.lib().sph_set_tuning(h8, 3, 1) == -1
+    assert L.lib().sph_set_tuning(h8, 2, 8) == 0
+    assert L.lib().sph_set_tuning(h8, 1, 4) == -1
     L.lib().sph_plan_destroy(h8)
 
 

@@ -232,13 +232,13 @@ def test_full_size_rhs_sampled(orc, dim, side):
 
 @pytest.mark.parametrize("dim,side", [(2, 40), (3, 14)])
 def test_lanes_per_particle_bitwise(dim, side):
-    """The sweeps give bitwise identical results for 1, 2 and 4 lanes per particle."""
+    """The sweeps give bitwise identical results for 2, 4 and 8 lanes per particle."""
     spec = SimSpec(dim, side, jitter=0.2)
     st = _inputs(spec, 21, "f32", rho_noise=0.01, v_noise=0.2)
     rng = np.random.default_rng(22)
     cot = [rng.normal(size=a.shape).astype(np.float32) for a in st]
     outs = []
-    for lanes in (1, 2, 4):
+    for lanes in (2, 4, 8):
         plan = _plan([spec], "f32")
         plan.set_tuning(lanes, lanes)
         g = _to_gpu(st, "f32")
