@@ -13,9 +13,11 @@ respect to the initial state.  Inputs are synthetic (seeded jittered lattice).
 
 The JSON line also carries the roofline of the dominant pair kernel (device time from HIP
 events the library records on its launch stream during the timed region), the CPU oracle
-on the host's cores, and the batched workload (512 uneven 2D simulations in one plan)
+on the host's cores, the batched workload (512 uneven 2D simulations in one plan)
 against the plain path (one plan per simulation, run one after the other), with the
-per-simulation completion latency p50/p99 of both.
+per-simulation completion latency p50/p99 of both, and the served workload (Poisson
+arrivals of uneven 2D/3D solve-plus-gradient requests under continuous batching) against
+the plain first-come first-served path on the same arrival trace.
 """
 from __future__ import annotations
 
@@ -111,11 +113,12 @@ def cpu_baseline(wl, host):
     return time.perf_counter() - t0, threads
 
 
-def timed_jobs(plan, x0, v0, r0, wl, reps):
-    """Wall time of `reps` jobs with library-side kernel timing; returns (seconds, profile)."""
+def timed_jobs(plan, x0, v0, r0, wl, reps, classes=None):
+    """Wall time of `reps` jobs with library-side HIP-event timing of the kernel classes named
+    (all when None); returns (seconds, profile)."""
     import torch
     plan.profile_read()
-    plan.profile(True)
+    plan.profile(True, classes)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
@@ -126,26 +129,41 @@ def timed_jobs(plan, x0, v0, r0, wl, reps):
     return t1 - t0, plan.profile_read()
 
 
-def roofline(prof, wl, per_state, reps, dim):
-    """Roofline of the dominant pair kernel: algorithmic flops per launch / mean launch time."""
+def roofline(prof, dom, wl, per_state, reps, dim, n_particles):
+    """Roofline of the dominant kernel from its HIP-event launch times in the timed region.
+
+    k_sweep / k_adj_sweep: ALU-bound; algorithmic flops per launch = flops per directed pair x
+    pairs per launch.  k_build_list: bound by its HBM output; algorithmic bytes per launch =
+    4 B per list entry (pairs plus the self entry) + 4 B per count + the 16 B record read per
+    particle."""
     K = wl.ckpt_every
-    recompute_swept = [n for n in range(wl.steps) if wl.adjoint and (n + 1) % K != 0 and n != wl.steps - 1]
+    recompute = [n for n in range(wl.steps) if wl.adjoint and (n + 1) % K != 0 and n != wl.steps - 1]
     p_fwd = sum(per_state)
-    cand = ("sweep", "adjoint") if wl.adjoint else ("sweep",)
-    dom = max(cand, key=lambda k: prof[k][0])
     ms_dom, n_dom = prof[dom]
+    mean_launch_s = ms_dom / n_dom * 1e-3
+    kernel = {"sweep": "k_sweep", "adjoint": "k_adj_sweep", "build": "k_build_list"}[dom]
+    if dom == "build":
+        # one build per forward state; the backward pass rebuilds every state of each segment
+        states = list(range(wl.steps)) * (2 if wl.adjoint else 1)
+        entries = sum(per_state[n] + n_particles for n in states) * reps
+        launches = len(states) * reps
+        bytes_per_launch = (4 * entries + launches * n_particles * (4 + (16 if wl.dtype == "f32" else 32))) / launches
+        achieved = bytes_per_launch / mean_launch_s / 1e9
+        peak = 8000.0
+        return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": peak, "unit": "GB/s",
+                "frac": round(achieved / peak, 4), "traffic": None,
+                "mean_launch_us": round(mean_launch_s * 1e6, 2), "launches": n_dom,
+                "algorithmic_bytes_per_launch": int(bytes_per_launch)}
     if dom == "sweep":
-        pairs = (p_fwd + sum(per_state[n] for n in recompute_swept)) * reps
+        pairs = (p_fwd + sum(per_state[n] for n in recompute)) * reps
     else:
         pairs = p_fwd * reps
     flops_per_launch = FLOPS_PER_PAIR[(dom, dim)] * pairs / n_dom
-    mean_launch_s = ms_dom / n_dom * 1e-3
     achieved = flops_per_launch / mean_launch_s / 1e12
     peak = PEAK_TFLOPS[wl.dtype]
-    return {"bound": "alu", "kernel": {"sweep": "k_sweep", "adjoint": "k_adj_sweep"}[dom],
-            "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-            "traffic": None, "mean_launch_us": round(mean_launch_s * 1e6, 2),
-            "pairs_per_launch": int(pairs / n_dom)}
+    return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None, "mean_launch_us": round(mean_launch_s * 1e6, 2),
+            "launches": n_dom, "pairs_per_launch": int(pairs / n_dom)}
 
 
 def bench_batched(dev, reps):
@@ -163,7 +181,7 @@ def bench_batched(dev, reps):
     run_job(plan, x0, v0, r0, wl)
     per_state = count_pairs(plan, x0, v0, r0, wl)
     work = 2 * sum(per_state)
-    t_batched, _ = timed_jobs(plan, x0, v0, r0, wl, reps)
+    t_batched, _ = timed_jobs(plan, x0, v0, r0, wl, reps, ())
     t_batched /= reps
     assert np.all(plan.poll() == 0)
     del plan
@@ -203,6 +221,60 @@ def bench_batched(dev, reps):
             "speedup": round(t_plain / t_batched, 2)}
 
 
+def log(msg):
+    """Progress line on stderr (the JSON result is the only line on stdout)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def bench_serving(dev, count, warmup, load=0.75, budget_gib=96):
+    """Poisson arrivals of uneven 2D/3D solve-plus-gradient requests: continuous batching vs plain FIFO.
+
+    The request mix is fixed by the trace seed; the arrival rate is `load` times the plain path's
+    saturation throughput (1 / mean plain service time, measured on the same requests), so the
+    same trace is offered to both servers.  Latency percentiles skip the first `warmup` requests."""
+    import numpy as np
+    import torch
+    from paper_2507_21684_amd import serving as S
+    from paper_2507_21684_amd.inputs import Request, serving_trace
+    base = serving_trace(seed=2026, count=count, rate=1.0)
+    # warm the allocator, the kernels and the plan tables on a few requests of each dimension
+    for r in [r for r in base if r.spec.dim == 2][:2] + [r for r in base if r.spec.dim == 3][:1]:
+        S.plain_request(Request(r.rid, 0.0, r.spec, r.seed, 16), "f32", 8, dev)
+    service = []
+    t_last = time.perf_counter()
+    for k, r in enumerate(base):
+        service.append(S.plain_request(r, "f32", 8, dev)[0])
+        if time.perf_counter() - t_last > 10:
+            t_last = time.perf_counter()
+            log("serving, plain path: %d of %d requests, %.1f s of service" % (k + 1, count, sum(service)))
+    service = np.array(service)
+    log("serving, plain path done: mean service %.1f ms" % (service.mean() * 1e3))
+    rate = load / service.mean()
+    trace = [Request(r.rid, r.arrival / rate, r.spec, r.seed, r.steps) for r in base]
+    arrivals = np.array([r.arrival for r in trace])
+    lat_plain = S.fifo_latencies(arrivals, service)
+    makespan_plain = float(np.max(arrivals + lat_plain) - arrivals[0])
+    torch.cuda.empty_cache()
+    sch, eng, done = S.serve(trace, "f32", 8, int(budget_gib * (1 << 30)), dev, progress=log)
+    log("serving, batched path done: %d ticks, %.1f s creating plans" % (sch.ticks, eng.plan_seconds))
+    lat_served = np.array([j.finished - j.req.arrival for j in sorted(done, key=lambda j: j.req.rid)])
+    makespan_served = float(max(j.finished for j in done) - arrivals[0])
+    work = 2 * eng.pairs
+    keep = slice(warmup, None)
+    pp, ps = S.percentiles(lat_plain[keep]), S.percentiles(lat_served[keep])
+    return {"workload": "poisson_%d_mixed_2d3d_f32" % count, "requests": count, "warmup_requests": warmup,
+            "rate_per_s": round(rate, 3), "load_vs_plain_saturation": load,
+            "mean_plain_service_ms": round(float(service.mean() * 1e3), 3), "pair_interactions": work,
+            "hbm_budget_gib": budget_gib, "peak_admitted_gib": round(sch.peak_used / (1 << 30), 2),
+            "mean_batch": round(float(np.mean(sch.batch_sizes)), 2), "ticks": sch.ticks,
+            "plan_creation_s": round(eng.plan_seconds, 3),
+            "served": {"value": round(work / makespan_served, 1), "p50_ms": round(ps["p50_ms"], 3),
+                       "p99_ms": round(ps["p99_ms"], 3), "makespan_s": round(makespan_served, 3)},
+            "plain": {"value": round(work / makespan_plain, 1), "p50_ms": round(pp["p50_ms"], 3),
+                      "p99_ms": round(pp["p99_ms"], 3), "makespan_s": round(makespan_plain, 3)},
+            "unit": "pair interactions/s"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -211,6 +283,10 @@ def main():
     ap.add_argument("--workload", default="tgv2d_64k_f32", choices=sorted(workloads()))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--serving", type=int, default=200, help="requests of the served workload (0 skips it)")
+    ap.add_argument("--counter-pass", action="store_true",
+                    help="for hardware-counter runs: warm-up and one job of the workload, then a plain "
+                         "device copy of 256 MiB (the calibration kernel for byte counters); prints nothing")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -234,6 +310,13 @@ def main():
     for _ in range(args.warmup):
         run_job(plan, x0, v0, r0, wl)
     torch.cuda.synchronize()
+    if args.counter_pass:
+        run_job(plan, x0, v0, r0, wl)
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        return
     per_state = count_pairs(plan, x0, v0, r0, wl)
     K = wl.ckpt_every
     p_fwd = sum(per_state)
@@ -242,14 +325,20 @@ def main():
     p_rec = sum(per_state[n] for n in recompute_swept)
     plan.poll()
 
-    elapsed, prof = timed_jobs(plan, x0, v0, r0, wl, args.steps)
+    log("workload %s: %d particles, pairs per job %d" % (wl.name, int(sum(s.n for s in wl.sims)), p_fwd + p_adj))
+    # untimed pass with every kernel class timed: the per-class breakdown and the dominant kernel
+    _, prof_all = timed_jobs(plan, x0, v0, r0, wl, 1)
+    breakdown = {k: round(v[0], 3) for k, v in prof_all.items()}
+    dom = max(("build", "sweep", "adjoint") if wl.adjoint else ("build", "sweep"), key=lambda k: prof_all[k][0])
+    # timed region: only the dominant kernel's launches carry events (each event pair costs ~1 us)
+    elapsed, prof = timed_jobs(plan, x0, v0, r0, wl, args.steps, [dom])
     status = plan.poll()
     assert np.all(status == 0), "device reported non-finite values or neighbour overflow: %s" % status
     value = (p_fwd + p_adj) * args.steps / elapsed
     dim = wl.sims[0].dim
-    roof = roofline(prof, wl, per_state, args.steps, dim)
-    breakdown = {k: round(v[0] / args.steps, 3) for k, v in prof.items()}
+    roof = roofline(prof, dom, wl, per_state, args.steps, dim, int(sum(s.n for s in wl.sims)))
 
+    log("timed %d jobs: %.3f ms per job" % (args.steps, 1e3 * elapsed / args.steps))
     cpu = None
     if not args.no_cpu_baseline and len(wl.sims) == 1:
         cdt, threads = cpu_baseline(wl, host)
@@ -262,7 +351,14 @@ def main():
     if not args.no_batched and args.workload != "batched_512_tgv2d_f32":
         del plan
         torch.cuda.empty_cache()
+        log("batched workload")
         batched = bench_batched(dev, max(1, min(args.steps, 3)))
+
+    served = None
+    if args.serving > 0 and args.workload != "batched_512_tgv2d_f32":
+        torch.cuda.empty_cache()
+        log("served workload")
+        served = bench_serving(dev, args.serving, max(1, args.serving // 10))
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "pair interactions/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
@@ -273,7 +369,7 @@ def main():
                       "ckpt_every": wl.ckpt_every, "adjoint": wl.adjoint, "loss": wl.loss,
                       "pairs_fwd": p_fwd, "pairs_adj": p_adj, "pairs_recompute": p_rec,
                       "lanes_per_particle": list(lanes)},
-           "roofline": roof, "kernel_ms_per_step": breakdown, "cpu_baseline": cpu, "batched": batched}
+           "roofline": roof, "kernel_ms_per_job": breakdown, "cpu_baseline": cpu, "batched": batched, "serving": served}
     print(json.dumps(out), flush=True)
 
 

@@ -128,6 +128,21 @@ sph_status sph_plan_info(const sph_plan* plan, int64_t* total_particles, int32_t
 sph_status sph_set_tuning(sph_plan* plan, int32_t lanes_fwd, int32_t lanes_adj);
 sph_status sph_get_tuning(const sph_plan* plan, int32_t* lanes_fwd, int32_t* lanes_adj);
 
+/* Graph mode (default off; host-side switch, no device work).  When on, every
+ * sph_step and sph_rollout_backward call is issued as one executable HIP graph
+ * holding all of the call's launches (the fixed-step loop of Sec. 3.3 has no
+ * data-dependent control flow, so a call's launch sequence depends only on its
+ * arguments).  A graph is captured on the plan's private stream the first time
+ * a given argument set is seen (nsteps, ckpt_every, every state, checkpoint
+ * and cotangent pointer, the lanes settings), kept in a cache of 8 entries per
+ * plan (least recently used evicted), and launched on the caller's stream;
+ * later calls with the same arguments only launch it.  Results are bitwise
+ * those of the direct path.  Calls made while profiling is enabled run
+ * directly.  Turning the mode off, or sph_bind, drops the cached graphs.  The
+ * graphs contain kernel and device-to-device copy nodes only (no memset nodes).
+ * DEVICE if capture or instantiation fails. */
+sph_status sph_set_graphs(sph_plan* plan, int32_t enable);
+
 /* Bind a device workspace of at least sph_workspace_size() bytes, 256-byte
  * aligned, and upload the plan's tables into it (asynchronous on stream).
  * The workspace must stay valid until the plan is destroyed or rebound. */
@@ -221,9 +236,13 @@ sph_status sph_pair_count(sph_plan* plan, int64_t* pairs, void* stream);
 #define SPH_KERN_OTHER 4     /* unsort, adjoint prologue */
 #define SPH_KERN_COUNT 5
 
-/* Enable (1) or disable (0) per-launch HIP-event timing of the plan's kernels; events are
- * recorded on the stream each kernel is launched on. */
-sph_status sph_profile_enable(sph_plan* plan, int32_t enable);
+/* Per-launch HIP-event timing of the plan's kernels: `classes` is a bit mask, bit k
+ * selecting kernel class k (SPH_PROFILE_ALL for every class, 0 to stop).  A pair of
+ * events is recorded around each selected launch group, on the stream it is launched
+ * on; each pair costs about a microsecond of device time, so time only the classes of
+ * interest in a timed run. */
+#define SPH_PROFILE_ALL ((1 << SPH_KERN_COUNT) - 1)
+sph_status sph_profile_enable(sph_plan* plan, int32_t classes);
 
 /* Accumulated device time in milliseconds (host double[SPH_KERN_COUNT]) and launch counts
  * (host int64[SPH_KERN_COUNT]) per kernel class since the last read, then reset.

@@ -70,7 +70,7 @@ def measure(plan: Plan, x, v, rho, steps: int = 4, reps: int = 2) -> Dict[int, T
             xs, vs, rs = x.clone(), v.clone(), rho.clone()
             ck = [plan.empty_state()]
             plan.profile_read()
-            plan.profile(True)
+            plan.profile(True, ["sweep", "adjoint"])
             plan.step(xs, vs, rs, K, ck, K)
             gx, gv, gr = torch.zeros_like(x), torch.ones_like(v), torch.zeros_like(rho)
             plan.rollout_backward(ck, K, K, gx, gv, gr)
@@ -98,5 +98,15 @@ def tune(plan: Plan, x, v, rho, use_cache: bool = True) -> Tuple[int, int]:
         if use_cache:
             table[key] = [lf, la, {str(k): list(t) for k, t in times.items()}]
             _store(table)
+    plan.set_tuning(lf, la)
+    return lf, la
+
+
+def apply_cached(plan: Plan) -> Optional[Tuple[int, int]]:
+    """Set the cached setting for this plan's bucket if there is one (never measures)."""
+    entry = _load().get(cache_key(plan))
+    if entry is None:
+        return None
+    lf, la = int(entry[0]), int(entry[1])
     plan.set_tuning(lf, la)
     return lf, la

@@ -95,7 +95,7 @@ struct sph_plan {
     char* ws = nullptr;
     bool bound = false;
     // per-launch timing (sph_profile_enable)
-    bool prof = false;
+    int32_t prof = 0;   // bit k: time launches of kernel class k
     struct Ev {
         hipEvent_t a, b;
         int kind;
@@ -104,8 +104,30 @@ struct sph_plan {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
     double prof_ms[SPH_KERN_COUNT] = {0, 0, 0, 0, 0};
     int64_t prof_n[SPH_KERN_COUNT] = {0, 0, 0, 0, 0};
+    // executable graphs of whole sph_step / sph_rollout_backward calls (sph_set_graphs),
+    // keyed by the call's arguments, least recently used evicted first
+    struct GraphEntry {
+        std::vector<uintptr_t> key;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+        uint64_t used;
+    };
+    bool graphs = false;
+    std::vector<GraphEntry> gcache;
+    uint64_t gclock = 0;
+    hipStream_t capture_stream = nullptr;
+    void clear_graphs()
+    {
+        for (auto& g : gcache) {
+            (void)hipGraphExecDestroy(g.exec);
+            (void)hipGraphDestroy(g.graph);
+        }
+        gcache.clear();
+    }
     ~sph_plan()
     {
+        clear_graphs();
+        if (capture_stream) (void)hipStreamDestroy(capture_stream);
         for (auto& e : ev_used) {
             (void)hipEventDestroy(e.a);
             (void)hipEventDestroy(e.b);
@@ -133,7 +155,7 @@ struct ProfScope {
     hipEvent_t a = nullptr, b = nullptr;
     ProfScope(sph_plan* P_, hipStream_t st_, int kind_) : P(P_), st(st_), kind(kind_)
     {
-        if (!P->prof) return;
+        if (!((P->prof >> kind_) & 1)) return;
         if (P->ev_pool.empty()) {
             hipEvent_t e1, e2;
             if (hipEventCreate(&e1) != hipSuccess) return;
@@ -488,6 +510,63 @@ sph_status do_rollout_backward(sph_plan* P, const sph_state* ckpt, int32_t nstep
     return SPH_OK;
 }
 
+constexpr size_t kGraphCache = 8;
+
+// Runs `issue(stream)` directly, or, with graphs enabled (and profiling off), as an executable
+// graph: captured once per distinct key on a private stream (capture records the launches
+// without running them), instantiated, kept, and launched on the caller's stream.
+template <typename F>
+sph_status run_graphed(sph_plan* P, std::vector<uintptr_t> key, hipStream_t st, F&& issue)
+{
+    if (!P->graphs || P->prof) return issue(st);
+    key.push_back((uintptr_t)P->lpp_fwd);
+    key.push_back((uintptr_t)P->lpp_adj);
+    for (auto& g : P->gcache) {
+        if (g.key == key) {
+            g.used = ++P->gclock;
+            HIP_TRY(hipGraphLaunch(g.exec, st));
+            return SPH_OK;
+        }
+    }
+    if (!P->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&P->capture_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(P->capture_stream, hipStreamCaptureModeThreadLocal));
+    const sph_status rc = issue(P->capture_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(P->capture_stream, &graph);
+    if (rc != SPH_OK || ec != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        if (rc != SPH_OK) return rc;
+        return fail(SPH_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(SPH_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+    }
+    if (P->gcache.size() >= kGraphCache) {
+        auto lru = std::min_element(P->gcache.begin(), P->gcache.end(),
+                                    [](const sph_plan::GraphEntry& a, const sph_plan::GraphEntry& b) {
+                                        return a.used < b.used;
+                                    });
+        (void)hipGraphExecDestroy(lru->exec);
+        (void)hipGraphDestroy(lru->graph);
+        P->gcache.erase(lru);
+    }
+    P->gcache.push_back({std::move(key), graph, exec, ++P->gclock});
+    HIP_TRY(hipGraphLaunch(exec, st));
+    return SPH_OK;
+}
+
+void key_state(std::vector<uintptr_t>& key, const sph_state* s)
+{
+    for (int k = 0; k < 3; ++k) {
+        key.push_back((uintptr_t)s->x[k]);
+        key.push_back((uintptr_t)s->v[k]);
+    }
+    key.push_back((uintptr_t)s->rho);
+}
+
 template <typename T, int D>
 sph_status do_neighbors(sph_plan* P, const sph_state* s, int64_t* offsets, int32_t* nbr, int64_t capacity,
                         int64_t* total, hipStream_t st)
@@ -773,6 +852,14 @@ sph_status sph_set_tuning(sph_plan* plan, int32_t lanes_fwd, int32_t lanes_adj)
     return SPH_OK;
 }
 
+sph_status sph_set_graphs(sph_plan* plan, int32_t enable)
+{
+    if (!plan) return fail(SPH_ERR_INVALID_ARG, "plan is null");
+    plan->graphs = enable != 0;
+    if (!plan->graphs) plan->clear_graphs();
+    return SPH_OK;
+}
+
 sph_status sph_get_tuning(const sph_plan* plan, int32_t* lanes_fwd, int32_t* lanes_adj)
 {
     if (!plan) return fail(SPH_ERR_INVALID_ARG, "plan is null");
@@ -788,6 +875,7 @@ sph_status sph_bind(sph_plan* P, void* workspace, size_t bytes, void* stream)
     if (bytes < P->bytes) return fail(SPH_ERR_CAPACITY, "workspace smaller than sph_workspace_size()");
     if (((uintptr_t)workspace) % 256 != 0) return fail(SPH_ERR_INVALID_ARG, "workspace not 256-byte aligned");
     hipStream_t st = (hipStream_t)stream;
+    P->clear_graphs();          // captured graphs hold addresses inside the old workspace
     P->ws = (char*)workspace;
     HIP_TRY(hipMemcpyAsync(P->ws + P->o_simc, P->h_simc.data(), P->h_simc.size(), hipMemcpyHostToDevice, st));
     if (P->N > 0)
@@ -854,7 +942,13 @@ sph_status sph_step(sph_plan* P, sph_state* s, int32_t nsteps, const sph_state* 
         const int32_t nslots = (nsteps + ckpt_every - 1) / ckpt_every;
         for (int32_t k = 0; k < nslots; ++k) RC_TRY(check_state(P, &ckpt[k], "checkpoint slot"));
     }
-    return DISPATCH(P, do_step, P, s, nsteps, ckpt, ckpt_every, (hipStream_t)stream);
+    std::vector<uintptr_t> key = {1u, (uintptr_t)nsteps, (uintptr_t)(ckpt ? ckpt_every : 0)};
+    key_state(key, s);
+    if (ckpt)
+        for (int32_t k = 0; k < (nsteps + ckpt_every - 1) / ckpt_every; ++k) key_state(key, &ckpt[k]);
+    return run_graphed(P, std::move(key), (hipStream_t)stream, [&](hipStream_t st) {
+        return DISPATCH(P, do_step, P, s, nsteps, ckpt, ckpt_every, st);
+    });
 }
 
 sph_status sph_step_adjoint(sph_plan* P, const sph_state* s_n, sph_state* cot, void* stream)
@@ -876,7 +970,12 @@ sph_status sph_rollout_backward(sph_plan* P, const sph_state* ckpt, int32_t nste
         return fail(SPH_ERR_CAPACITY, "plan tape_depth is smaller than the checkpoint interval");
     const int32_t nseg = nsteps > 0 ? (nsteps + ckpt_every - 1) / ckpt_every : 0;
     for (int32_t k = 0; k < nseg; ++k) RC_TRY(check_state(P, &ckpt[k], "checkpoint slot"));
-    return DISPATCH(P, do_rollout_backward, P, ckpt, nsteps, ckpt_every, cot, (hipStream_t)stream);
+    std::vector<uintptr_t> key = {2u, (uintptr_t)nsteps, (uintptr_t)ckpt_every};
+    key_state(key, cot);
+    for (int32_t k = 0; k < nseg; ++k) key_state(key, &ckpt[k]);
+    return run_graphed(P, std::move(key), (hipStream_t)stream, [&](hipStream_t st) {
+        return DISPATCH(P, do_rollout_backward, P, ckpt, nsteps, ckpt_every, cot, st);
+    });
 }
 
 sph_status sph_poll(sph_plan* P, int32_t* per_sim_status, void* stream)
@@ -912,7 +1011,7 @@ sph_status sph_pair_count(sph_plan* P, int64_t* pairs, void* stream)
 sph_status sph_profile_enable(sph_plan* P, int32_t enable)
 {
     if (!P) return fail(SPH_ERR_INVALID_ARG, "plan is null");
-    P->prof = enable != 0;
+    P->prof = enable & ((1 << SPH_KERN_COUNT) - 1);
     return SPH_OK;
 }
 

@@ -447,21 +447,22 @@ __device__ __forceinline__ void unpack_u(const vec4_t<T>& a, T* u)
 
 // ---------------------------------------------------------------- neighbour lists
 
-constexpr int kBuildTile = 128;  // candidates staged in LDS at a time
 // The pair counter is spread over kPairSlots words, one per 128-byte line, so that the
 // wavefronts' integer atomics do not serialise on a single address.
 constexpr int kPairSlots = 512;
 constexpr int kPairStride = 16;
 
-// One wavefront per cell.  The cell's particles are tested against the particles of the
-// (2 sub + 1)^dim stencil cells, visited in lexicographic order of their offset from the cell
-// (the precomputed stencil table lists them in that order) and staged through LDS in tiles
-// read by all lanes at the same address.  When a cell holds n < 64 particles,
-// LPP = 64 / next_pow2(n) lanes share each particle and split its candidate stream; a ballot
-// over each round of LPP candidates gives every accepted candidate its rank, so each
-// particle's list keeps the candidate order (stencil offset, then original index) whatever
-// LPP is.  Lists are row-major: entry k of particle i is nbr[i * width + k], and the writes of
-// one particle's accepted candidates in a round are contiguous.
+// One wavefront per cell.  The candidates of the cell's particles are the particles of the
+// (2 sub + 1)^dim stencil cells, taken in lexicographic order of the cell offset (the
+// precomputed stencil table lists them in that order), each cell's particles in sorted order
+// (= original index inside a cell), which is the canonical list order.  The candidate stream
+// is cut into chunks of 64; lane l holds candidate 64 c + l of chunk c in registers (the next
+// chunk's gather is issued before the current chunk is tested), and the cell's particles,
+// staged in LDS, are taken one after the other with the same address in every lane.  For
+// particle p one round tests all 64 candidates of the chunk; the ballot of the accepted ones
+// gives each its rank, so the round appends a contiguous run to p's row, in candidate order.
+// Lane p keeps p's running count.  Lists are row-major: entry k of particle i is
+// nbr[i * width + k].
 template <typename T, int DIM>
 __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ cell_sim,
                                                    const int32_t* __restrict__ stencil,
@@ -472,9 +473,7 @@ __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ c
                                                    int32_t* __restrict__ status,
                                                    unsigned long long* __restrict__ pair_counter)
 {
-    __shared__ vec4_t<T> cu[kBuildTile];
-    __shared__ vec4_t<T> csh[kBuildTile];
-    __shared__ int32_t cj[kBuildTile];
+    __shared__ vec4_t<T> pu[64];
     __shared__ int32_t uc_first[128];
     __shared__ int32_t uc_pref[129];
     __shared__ int32_t uc_code[128];
@@ -512,65 +511,53 @@ __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ c
     if (lane == 0) uc_pref[ncu] = M;
     __syncthreads();
 
-    int lpp = 1;
-    while (n < 64 && 2 * lpp * n <= 64) lpp *= 2;
-    const int slots = 64 / lpp;
-    const int g = lane / lpp, r = lane - g * lpp;
-    const unsigned long long group_mask = (lpp == 64) ? ~0ull : (((1ull << lpp) - 1ull) << (g * lpp));
+    // candidate m of the stream: sorted index, position and periodic shift
+    auto fetch = [&](int m, int& j, vec4_t<T>& u, int& code) {
+        int lo = 0, hi = ncu - 1;  // last stencil cell whose prefix is <= m
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (uc_pref[mid] <= m) lo = mid;
+            else hi = mid - 1;
+        }
+        j = uc_first[lo] + (m - uc_pref[lo]);
+        code = uc_code[lo];
+        u = jd0[j];
+    };
+
     const unsigned long long below = (1ull << lane) - 1ull;
     int pairs_acc = 0;
-
-    for (int p0 = 0; p0 < n; p0 += slots) {
-        const bool act = (p0 + g) < n;
-        const int i = i0 + p0 + g;
-        T ui[3] = {0, 0, 0};
-        if (act) unpack_u<T, DIM>(jd0[i], ui);
-        int cnt = 0;
-        for (int t0 = 0; t0 < M; t0 += kBuildTile) {
-            const int mt = (M - t0 < kBuildTile) ? M - t0 : kBuildTile;
-            __syncthreads();
-            for (int m = lane; m < mt; m += 64) {
-                const int gm = t0 + m;
-                int lo = 0, hi = ncu - 1;  // last stencil cell whose prefix is <= gm
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (uc_pref[mid] <= gm) lo = mid;
-                    else hi = mid - 1;
-                }
-                const int j = uc_first[lo] + (gm - uc_pref[lo]);
-                cu[m] = jd0[j];
-                const int code = uc_code[lo];
-                vec4_t<T> shv;
-                shv.x = T(((code >> kStencilIdBits) & 3) - 1) * S.L;
-                shv.y = T(((code >> (kStencilIdBits + 2)) & 3) - 1) * S.L;
-                shv.z = T(((code >> (kStencilIdBits + 4)) & 3) - 1) * S.L;
-                shv.w = T(0);
-                csh[m] = shv;
-                cj[m] = j;
-            }
-            __syncthreads();
-            for (int b = 0; b < mt; b += lpp) {
-                const int m = b + r;
-                bool ok = false;
-                int j = 0;
-                if (act && m < mt) {
-                    T uj[3], sh[3];
-                    unpack_u<T, DIM>(cu[m], uj);
-                    const vec4_t<T> shv = csh[m];
-                    sh[0] = shv.x;
-                    sh[1] = shv.y;
-                    sh[2] = shv.z;
-                    ok = dist2_exact<T, DIM>(ui, uj, sh) < S.H2;
-                    j = cj[m];
-                }
+    for (int pb = 0; pb < n; pb += 64) {
+        const int nb = (n - pb < 64) ? n - pb : 64;
+        __syncthreads();
+        if (lane < nb) pu[lane] = jd0[i0 + pb + lane];
+        __syncthreads();
+        int cnt = 0;  // lane p: entries of particle i0 + pb + p so far
+        int jn = 0, coden = 0;
+        vec4_t<T> un;
+        un.x = un.y = un.z = un.w = T(0);
+        if (lane < M) fetch(lane, jn, un, coden);
+        for (int c0 = 0; c0 < M; c0 += 64) {
+            const bool valid = c0 + lane < M;
+            const int jc = jn;
+            T uj[3] = {T(0), T(0), T(0)}, sh[3];
+            unpack_u<T, DIM>(un, uj);
+            sh[0] = T(((coden >> kStencilIdBits) & 3) - 1) * S.L;
+            sh[1] = T(((coden >> (kStencilIdBits + 2)) & 3) - 1) * S.L;
+            sh[2] = T(((coden >> (kStencilIdBits + 4)) & 3) - 1) * S.L;
+            if (c0 + 64 + lane < M) fetch(c0 + 64 + lane, jn, un, coden);  // next chunk in flight
+            for (int p = 0; p < nb; ++p) {
+                T ui[3] = {T(0), T(0), T(0)};
+                unpack_u<T, DIM>(pu[p], ui);
+                const bool ok = valid && dist2_exact<T, DIM>(ui, uj, sh) < S.H2;
                 const unsigned long long mask = __ballot(ok);
-                const unsigned long long mine = mask & group_mask;
-                const int pos = cnt + __popcll(mine & below);
-                if (ok && pos < width) nbr[(int64_t)i * width + pos] = j;
-                cnt += __popcll(mine);
+                const int base = __builtin_amdgcn_readlane(cnt, p);
+                const int pos = base + __popcll(mask & below);
+                if (ok && pos < width) nbr[(int64_t)(i0 + pb + p) * width + pos] = jc;
+                if (lane == p) cnt = base + __popcll(mask);
             }
         }
-        if (act && r == 0) {
+        if (lane < nb) {
+            const int i = i0 + pb + lane;
             nbr_count[i] = cnt;
             if (cnt > width) atomicOr(&status[s], kFlagOverflow);
             pairs_acc += cnt - 1;

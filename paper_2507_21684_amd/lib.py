@@ -61,6 +61,8 @@ def lib():
         L.sph_set_tuning.restype = st
         L.sph_set_tuning.argtypes = [_VP, ctypes.c_int32, ctypes.c_int32]
         L.sph_get_tuning.restype = st
+        L.sph_set_graphs.argtypes = [_VP, ctypes.c_int32]
+        L.sph_set_graphs.restype = ctypes.c_int32
         L.sph_get_tuning.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         L.sph_rollout_backward.restype = st
         L.sph_rollout_backward.argtypes = [_VP, ctypes.POINTER(SphState), ctypes.c_int32, ctypes.c_int32,
@@ -110,10 +112,27 @@ def exported_symbols() -> List[str]:
     return ["sph_plan_create", "sph_plan_destroy", "sph_workspace_size", "sph_plan_info", "sph_bind",
             "sph_build_cells", "sph_neighbors", "sph_rhs", "sph_step", "sph_step_adjoint", "sph_poll",
             "sph_pair_count", "sph_profile_enable", "sph_profile_read", "sph_last_error", "sph_set_tuning",
-            "sph_get_tuning", "sph_rollout_backward"]
+            "sph_get_tuning", "sph_rollout_backward", "sph_set_graphs"]
 
 
 KERNEL_CLASSES = ["sort", "build", "sweep", "adjoint", "other"]
+
+
+def workspace_bytes(sims: Sequence[dict], counts: Sequence[int], dtype: str = "f32", tape_depth: int = 8,
+                    max_neighbors: int = 0) -> int:
+    """Workspace bytes a plan for this batch needs (host-only query; allocates no device memory)."""
+    L = lib()
+    n = len(sims)
+    arr = (SphParams * n)(*[make_params(p, dtype) for p in sims])
+    cnt = (ctypes.c_int64 * n)(*[int(c) for c in counts])
+    h = _VP()
+    _check(L.sph_plan_create(arr, n, cnt, int(max_neighbors), int(tape_depth), ctypes.byref(h)))
+    try:
+        size = ctypes.c_size_t()
+        _check(L.sph_workspace_size(h, ctypes.byref(size)))
+        return int(size.value)
+    finally:
+        L.sph_plan_destroy(h)
 
 
 def _stream_ptr(stream=None) -> int:
@@ -246,6 +265,10 @@ class Plan:
     def set_tuning(self, lanes_fwd: int, lanes_adj: int):
         _check(lib().sph_set_tuning(self._h, int(lanes_fwd), int(lanes_adj)))
 
+    def set_graphs(self, enable: bool = True):
+        """Issue step / rollout_backward calls as cached executable HIP graphs."""
+        _check(lib().sph_set_graphs(self._h, 1 if enable else 0))
+
     def get_tuning(self) -> Tuple[int, int]:
         a, b = ctypes.c_int32(), ctypes.c_int32()
         _check(lib().sph_get_tuning(self._h, ctypes.byref(a), ctypes.byref(b)))
@@ -257,8 +280,14 @@ class Plan:
         _check(lib().sph_pair_count(self._h, ctypes.byref(v), _stream_ptr(stream)))
         return int(v.value)
 
-    def profile(self, enable: bool = True):
-        _check(lib().sph_profile_enable(self._h, 1 if enable else 0))
+    def profile(self, enable: bool = True, classes: Optional[Sequence[str]] = None):
+        """Time launches with HIP events: every kernel class, or only those named in `classes`."""
+        mask = 0
+        if enable:
+            names = KERNEL_CLASSES if classes is None else classes
+            for c in names:
+                mask |= 1 << KERNEL_CLASSES.index(c)
+        _check(lib().sph_profile_enable(self._h, mask))
 
     def profile_read(self) -> dict:
         """{class: (milliseconds, launches)} accumulated since the last read."""

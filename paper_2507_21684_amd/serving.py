@@ -1,0 +1,332 @@
+"""Serving loop: many independent solve-plus-gradient requests on one GPU.
+
+A request is one simulation (its own size, amplitude, step count T) that has to be rolled
+out for T fixed steps with a checkpoint every K steps and then differentiated: the loss is
+sum_i |v_i(T)|^2 and the answer is the cotangent of the initial state (x0, v0, rho0), as in
+the checkpointed scheme of Sec. 3.3 (store every K-th state, recompute the rest).
+
+The scheduler works in ticks.  Within a tick every admitted request advances by one
+checkpoint segment: requests in their forward phase step to their next checkpoint
+boundary, requests in their backward phase run the adjoint of one segment (recompute it
+from its checkpoint, then its adjoint steps in reverse).  Requests in the same phase, of the
+same dimension and with the same segment length are packed back to back into one batched
+plan (one library call per group), so the batch changes at every segment boundary:
+requests join as soon as they are admitted and leave as soon as their gradient is done
+(continuous batching).  Admission is first-come first-served under an HBM budget: a request
+is admitted when its footprint (its states, checkpoints and cotangent plus the workspace of
+a plan of its size) fits beside the requests already running; the head of the queue is
+always admitted into an empty server so that every request makes progress.
+
+The segment boundaries of a request are the same (every K steps from its step 0, the last
+segment possibly shorter) whether it runs alone or in a mix, and the library's results do
+not depend on the batch composition, so a served request returns bitwise the gradient that
+the plain path (one plan per request, sph_step with checkpoints then sph_rollout_backward)
+returns.
+
+Time is kept on a clock that advances by the measured wall time of each tick and jumps to
+the next arrival when the server is idle; latency of a request is its completion time minus
+its arrival time on that clock.  The plain path is timed per request (service time) and its
+first-come first-served latencies follow from the same arrival times.
+"""
+from __future__ import annotations
+
+import math
+import time
+from collections import deque
+from dataclasses import dataclass, field
+from typing import Callable, Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from .inputs import Request
+
+
+@dataclass
+class Job:
+    req: Request
+    footprint: int
+    state: object = None                       # engine-owned current state (forward phase)
+    ckpts: List[object] = field(default_factory=list)
+    cot: object = None                         # engine-owned cotangent (backward phase)
+    pos: int = 0                               # forward steps done
+    seg: int = -1                              # next backward segment
+    phase: str = "fwd"
+    admitted: float = math.nan
+    finished: float = math.nan
+
+    @property
+    def dim(self) -> int:
+        return self.req.spec.dim
+
+    def seg_len(self, K: int) -> int:
+        """Length of the segment this job works on next."""
+        T = self.req.steps
+        if self.phase == "fwd":
+            return min(K, T - self.pos)
+        return min(K, T - self.seg * K)
+
+
+class Scheduler:
+    """First-come first-served admission under a byte budget, continuous batching by segment.
+
+    The engine supplies footprint(req), admit(job), forward(jobs, n), backward(jobs, n) and
+    finish(jobs) (the latter three after a tick's work is issued), plus sync(); the scheduler
+    owns the clock and the queues and never touches device memory itself.
+    """
+
+    def __init__(self, engine, ckpt_every: int = 8, budget_bytes: int = 64 << 30,
+                 clock: Optional[Callable[[], float]] = None,
+                 progress: Optional[Callable[[str], None]] = None, progress_every: float = 10.0):
+        if ckpt_every < 1:
+            raise ValueError("ckpt_every must be >= 1")
+        self.engine = engine
+        self.K = int(ckpt_every)
+        self.budget = int(budget_bytes)
+        self.clock_fn = clock if clock is not None else time.perf_counter
+        self.now = 0.0
+        self.used = 0
+        self.peak_used = 0
+        self.ticks = 0
+        self.batch_sizes: List[int] = []
+        self.progress = progress
+        self.progress_every = progress_every
+
+    def _groups(self, active: Sequence[Job]) -> Dict[Tuple[str, int, int], List[Job]]:
+        groups: Dict[Tuple[str, int, int], List[Job]] = {}
+        for j in active:
+            groups.setdefault((j.phase, j.dim, j.seg_len(self.K)), []).append(j)
+        return groups
+
+    def run(self, trace: Sequence[Request]) -> List[Job]:
+        pending = deque(sorted(trace, key=lambda r: (r.arrival, r.rid)))
+        queue: deque = deque()
+        active: List[Job] = []
+        done: List[Job] = []
+        K = self.K
+        last_report = time.perf_counter()
+        while pending or queue or active:
+            if self.progress is not None and time.perf_counter() - last_report > self.progress_every:
+                last_report = time.perf_counter()
+                self.progress("serving: tick %d, clock %.2f s, done %d, active %d, queued %d, pending %d"
+                              % (self.ticks, self.now, len(done), len(active), len(queue), len(pending)))
+            while pending and pending[0].arrival <= self.now:
+                r = pending.popleft()
+                queue.append(Job(r, int(self.engine.footprint(r))))
+            if not queue and not active:
+                self.now = max(self.now, pending[0].arrival)
+                continue
+            while queue and (self.used + queue[0].footprint <= self.budget or not active):
+                j = queue.popleft()
+                self.used += j.footprint
+                self.peak_used = max(self.peak_used, self.used)
+                j.admitted = self.now
+                active.append(j)
+            t0 = self.clock_fn()
+            for j in [j for j in active if j.state is None and j.phase == "fwd" and j.pos == 0]:
+                self.engine.admit(j)
+            groups = self._groups(active)
+            for (phase, _, n), jobs in sorted(groups.items(), key=lambda kv: kv[0]):
+                if phase == "fwd":
+                    self.engine.forward(jobs, n)
+                    for j in jobs:
+                        j.pos += n
+                        if j.pos == j.req.steps:
+                            j.phase = "bwd"
+                            j.seg = (j.req.steps + K - 1) // K - 1
+                else:
+                    self.engine.backward(jobs, n)
+                    for j in jobs:
+                        j.seg -= 1
+                        if j.seg < 0:
+                            j.phase = "done"
+            self.engine.sync()
+            self.now += self.clock_fn() - t0
+            self.ticks += 1
+            self.batch_sizes.append(len(active))
+            finished = [j for j in active if j.phase == "done"]
+            if finished:
+                self.engine.finish(finished)
+            for j in finished:
+                j.finished = self.now
+                self.used -= j.footprint
+                done.append(j)
+            active = [j for j in active if j.phase != "done"]
+        return done
+
+
+def fifo_latencies(arrivals: Sequence[float], service: Sequence[float]) -> np.ndarray:
+    """Latencies of a single first-come first-served server with the given service times."""
+    free = 0.0
+    out = np.empty(len(arrivals))
+    for k, (a, s) in enumerate(zip(arrivals, service)):
+        start = max(a, free)
+        free = start + s
+        out[k] = free - a
+    return out
+
+
+def percentiles(lat_s: Sequence[float]) -> Dict[str, float]:
+    a = np.asarray(lat_s, dtype=np.float64)
+    if a.size == 0:
+        return {"p50_ms": math.nan, "p99_ms": math.nan, "mean_ms": math.nan}
+    return {"p50_ms": float(np.percentile(a, 50) * 1e3), "p99_ms": float(np.percentile(a, 99) * 1e3),
+            "mean_ms": float(a.mean() * 1e3)}
+
+
+# ---------------------------------------------------------------- GPU engine
+
+class GpuEngine:
+    """Runs the scheduler's groups through batched plans of the HIP library."""
+
+    def __init__(self, dtype: str = "f32", ckpt_every: int = 8, device=None, tuned: bool = True):
+        import torch
+        self.torch = torch
+        self.dtype = dtype
+        self.tdt = torch.float32 if dtype == "f32" else torch.float64
+        self.K = int(ckpt_every)
+        self.device = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.tuned = tuned
+        self._plans: Dict[tuple, object] = {}
+        self._used_plans: Dict[tuple, object] = {}
+        self._ws_cache: Dict[tuple, int] = {}
+        self.pairs = 0
+        self.results: Dict[int, tuple] = {}
+        self._host: Dict[int, list] = {}
+        self.plan_seconds = 0.0         # host time spent creating and binding plans
+
+    # -- accounting
+    def workspace_bytes(self, spec) -> int:
+        from .lib import workspace_bytes
+        key = (spec.dim, spec.side)
+        if key not in self._ws_cache:
+            self._ws_cache[key] = workspace_bytes([spec.params()], [spec.n], self.dtype, self.K)
+        return self._ws_cache[key]
+
+    def footprint(self, req: Request) -> int:
+        """Bytes the request holds while admitted.  Called when the request arrives, which is
+        also when its initial state (the request's payload) is generated on the host."""
+        from .inputs import make_state
+        npdt = np.float32 if self.dtype == "f32" else np.float64
+        self._host[req.rid] = [a.astype(npdt) for a in make_state(req.spec, req.seed)]
+        spec = req.spec
+        esz = 4 if self.dtype == "f32" else 8
+        state = (2 * spec.dim + 1) * spec.n * esz
+        nseg = (req.steps + self.K - 1) // self.K
+        # checkpoints, current state, cotangent, and packed copies of both for a group call
+        return (nseg + 4) * state + self.workspace_bytes(spec)
+
+    # -- plans
+    def _plan(self, key, jobs: Sequence[Job], tape: int):
+        from .lib import Plan
+        p = self._plans.get(key)
+        if p is None:
+            t0 = time.perf_counter()
+            p = Plan([j.req.spec.params() for j in jobs], [j.req.spec.n for j in jobs], dtype=self.dtype,
+                     tape_depth=tape, device=self.device)
+            if self.tuned:
+                from .autotune import apply_cached
+                apply_cached(p)
+            self._plans[key] = p
+            self.plan_seconds += time.perf_counter() - t0
+        self._used_plans[key] = p
+        return p
+
+    def _pack(self, parts: Sequence[tuple]):
+        torch = self.torch
+        if len(parts) == 1:
+            return tuple(t.clone() for t in parts[0])
+        return (torch.cat([p[0] for p in parts], 1), torch.cat([p[1] for p in parts], 1),
+                torch.cat([p[2] for p in parts], 0))
+
+    @staticmethod
+    def _unpack(packed: tuple, jobs: Sequence[Job]) -> List[tuple]:
+        out, a = [], 0
+        for j in jobs:
+            b = a + j.req.spec.n
+            out.append((packed[0][:, a:b].contiguous(), packed[1][:, a:b].contiguous(),
+                        packed[2][a:b].contiguous()))
+            a = b
+        return out
+
+    # -- scheduler hooks
+    def admit(self, job: Job):
+        host = self._host.pop(job.req.rid)
+        job.state = tuple(self.torch.tensor(a, device=self.device) for a in host)
+
+    def forward(self, jobs: Sequence[Job], n: int):
+        key = ("fwd", jobs[0].dim) + tuple(j.req.rid for j in jobs)
+        plan = self._plan(key, jobs, 0)
+        for j in jobs:
+            j.ckpts.append(j.state)                     # the state at the start of this segment
+        xs, vs, rs = self._pack([j.state for j in jobs])
+        plan.step(xs, vs, rs, n)
+        for j, st in zip(jobs, self._unpack((xs, vs, rs), jobs)):
+            j.state = st
+            if j.pos + n == j.req.steps:
+                # loss sum_i |v_i(T)|^2: seed v-bar = 2 v(T), x-bar = rho-bar = 0
+                j.cot = (self.torch.zeros_like(st[0]), 2.0 * st[1], self.torch.zeros_like(st[2]))
+                j.state = None
+
+    def backward(self, jobs: Sequence[Job], n: int):
+        key = ("bwd", jobs[0].dim) + tuple(j.req.rid for j in jobs)
+        plan = self._plan(key, jobs, self.K)
+        ck = self._pack([j.ckpts[j.seg] for j in jobs])
+        gx, gv, gr = self._pack([j.cot for j in jobs])
+        plan.rollout_backward([ck], n, n, gx, gv, gr)
+        for j, c in zip(jobs, self._unpack((gx, gv, gr), jobs)):
+            j.cot = c
+            j.ckpts[j.seg] = None
+
+    def finish(self, jobs: Sequence[Job]):
+        for j in jobs:
+            self.results[j.req.rid] = j.cot
+            j.cot = None
+            j.ckpts = []
+
+    def sync(self):
+        # work is counted on the forward states only (each is also the start of one adjoint
+        # step); the recompute builds of the backward plans are not work and are discarded
+        for key, p in self._used_plans.items():
+            n = p.pair_count()
+            if key[0] == "fwd":
+                self.pairs += n
+        self.torch.cuda.synchronize()
+        # plans not used in this tick belong to compositions that no longer exist
+        self._plans = dict(self._used_plans)
+        self._used_plans = {}
+
+
+def serve(trace: Sequence[Request], dtype: str = "f32", ckpt_every: int = 8, budget_bytes: int = 64 << 30,
+          device=None, tuned: bool = True, progress: Optional[Callable[[str], None]] = None):
+    """Serve `trace` with continuous batching; returns (scheduler, engine, finished jobs)."""
+    eng = GpuEngine(dtype, ckpt_every, device, tuned)
+    sch = Scheduler(eng, ckpt_every, budget_bytes, progress=progress)
+    done = sch.run(trace)
+    return sch, eng, done
+
+
+def plain_request(req: Request, dtype: str = "f32", ckpt_every: int = 8, device=None, tuned: bool = True):
+    """The plain path for one request: its own plan, sph_step with checkpoints, sph_rollout_backward.
+
+    Returns (service seconds, gradient tuple)."""
+    import torch
+    from .inputs import make_state
+    from .lib import Plan
+    spec = req.spec
+    npdt = np.float32 if dtype == "f32" else np.float64
+    host = [a.astype(npdt) for a in make_state(spec, req.seed)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+    x, v, r = (torch.tensor(a, device=dev) for a in host)
+    plan = Plan([spec.params()], [spec.n], dtype=dtype, tape_depth=ckpt_every, device=dev)
+    if tuned:
+        from .autotune import apply_cached
+        apply_cached(plan)
+    T, K = req.steps, ckpt_every
+    ck = [plan.empty_state() for _ in range((T + K - 1) // K)]
+    plan.step(x, v, r, T, ck, K)
+    gx, gv, gr = torch.zeros_like(x), 2.0 * v, torch.zeros_like(r)
+    plan.rollout_backward(ck, T, K, gx, gv, gr)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, (gx, gv, gr)

@@ -1,0 +1,166 @@
+"""Host logic of the serving loop: admission, continuous batching by segment, FIFO latencies.
+
+The scheduler runs against a recording engine on a simulated clock (no GPU); the GPU engine
+and its bitwise agreement with the plain path are covered by the GPU tests.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2507_21684_amd.inputs import Request, SimSpec, serving_trace
+from paper_2507_21684_amd.serving import Scheduler, fifo_latencies, percentiles
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+
+class RecordingEngine:
+    """Footprint = particle count; every group call costs 1 ms + 1 us per particle-step."""
+
+    def __init__(self, clock):
+        self.clock = clock
+        self.calls = []
+        self.admitted = []
+        self.finished = []
+
+    def footprint(self, req):
+        return req.spec.n
+
+    def admit(self, job):
+        self.admitted.append(job.req.rid)
+        job.state = "x0"
+
+    def forward(self, jobs, n):
+        self.calls.append(("fwd", [j.req.rid for j in jobs], n, [j.pos for j in jobs], [j.dim for j in jobs]))
+        self.clock.t += 1e-3 + 1e-6 * n * sum(j.req.spec.n for j in jobs)
+
+    def backward(self, jobs, n):
+        self.calls.append(("bwd", [j.req.rid for j in jobs], n, [j.seg for j in jobs], [j.dim for j in jobs]))
+        self.clock.t += 1e-3 + 2e-6 * n * sum(j.req.spec.n for j in jobs)
+
+    def finish(self, jobs):
+        self.finished.extend(j.req.rid for j in jobs)
+
+    def sync(self):
+        pass
+
+
+def small_trace(seed=7, count=40, rate=200.0):
+    rng = np.random.default_rng(seed)
+    t, out = 0.0, []
+    for k in range(count):
+        t += rng.exponential(1.0 / rate)
+        dim = 2 if rng.uniform() < 0.7 else 3
+        side = int(rng.integers(16, 40)) if dim == 2 else int(rng.integers(16, 24))
+        out.append(Request(k, t, SimSpec(dim, side), k, int(rng.integers(3, 30))))
+    return out
+
+
+def run(trace, K=8, budget=1 << 40):
+    clock = FakeClock()
+    eng = RecordingEngine(clock)
+    sch = Scheduler(eng, K, budget, clock=clock)
+    done = sch.run(trace)
+    return sch, eng, done
+
+
+@pytest.mark.parametrize("K", [1, 3, 8])
+def test_every_request_runs_its_segments_in_order(K):
+    trace = small_trace()
+    sch, eng, done = run(trace, K)
+    assert sorted(j.req.rid for j in done) == list(range(len(trace)))
+    assert sorted(eng.finished) == list(range(len(trace)))
+    for r in trace:
+        fwd = [(n, c[3][c[1].index(r.rid)]) for c in eng.calls if c[0] == "fwd" and r.rid in c[1] for n in [c[2]]]
+        bwd = [(n, c[3][c[1].index(r.rid)]) for c in eng.calls if c[0] == "bwd" and r.rid in c[1] for n in [c[2]]]
+        # forward: segments of K from step 0, the last one shorter, positions increasing
+        pos = 0
+        for n, p in fwd:
+            assert p == pos and n == min(K, r.steps - pos)
+            pos += n
+        assert pos == r.steps
+        # backward: the same segments in reverse
+        nseg = (r.steps + K - 1) // K
+        assert [s for _, s in bwd] == list(range(nseg - 1, -1, -1))
+        assert [n for n, _ in bwd] == [min(K, r.steps - s * K) for s in range(nseg - 1, -1, -1)]
+        # the backward starts after the last forward segment
+        first_b = min(i for i, c in enumerate(eng.calls) if c[0] == "bwd" and r.rid in c[1])
+        last_f = max(i for i, c in enumerate(eng.calls) if c[0] == "fwd" and r.rid in c[1])
+        assert first_b > last_f
+
+
+def test_groups_are_homogeneous_and_batched():
+    trace = small_trace(count=60, rate=2000.0)
+    sch, eng, done = run(trace)
+    for phase, rids, n, _, dims in eng.calls:
+        assert len(set(dims)) == 1
+        assert len(set(rids)) == len(rids)
+    # with a dense arrival trace the batches hold several requests
+    assert max(len(c[1]) for c in eng.calls) >= 5
+    assert max(sch.batch_sizes) >= 5
+
+
+def test_budget_and_fifo_admission():
+    trace = small_trace(count=50, rate=5000.0)
+    budget = 30000      # above every single footprint, below the sum of a few
+    sch, eng, done = run(trace, 8, budget)
+    assert max(r.spec.n for r in trace) <= budget
+    assert sch.peak_used <= budget
+    assert sch.peak_used > budget // 2
+    # admitted in arrival order
+    by_rid = {j.req.rid: j for j in done}
+    adm = [by_rid[r.rid].admitted for r in sorted(trace, key=lambda r: r.arrival)]
+    assert all(a <= b for a, b in zip(adm, adm[1:]))
+    assert eng.admitted == sorted(eng.admitted, key=lambda rid: trace[rid].arrival)
+    for j in done:
+        assert j.admitted >= j.req.arrival - 1e-12
+        assert j.finished > j.admitted
+
+
+def test_oversized_request_runs_alone():
+    trace = [Request(0, 0.0, SimSpec(2, 64), 0, 8), Request(1, 0.0, SimSpec(2, 16), 1, 8)]
+    sch, eng, done = run(trace, 8, budget=100)
+    assert len(done) == 2
+    for c in eng.calls:
+        assert len(c[1]) == 1
+
+
+def test_idle_server_jumps_to_next_arrival():
+    trace = [Request(0, 0.0, SimSpec(2, 16), 0, 4), Request(1, 10.0, SimSpec(2, 16), 1, 4)]
+    sch, eng, done = run(trace)
+    j1 = [j for j in done if j.req.rid == 1][0]
+    assert j1.admitted == pytest.approx(10.0)
+    assert j1.finished - 10.0 < 0.1
+
+
+def test_fifo_latencies_closed_form():
+    # arrivals every 1 s, service 2 s: the k-th request waits k seconds in the queue
+    lat = fifo_latencies([0, 1, 2, 3], [2, 2, 2, 2])
+    assert np.allclose(lat, [2, 3, 4, 5])
+    # idle gaps do not accumulate
+    assert np.allclose(fifo_latencies([0, 10], [1, 1]), [1, 1])
+    p = percentiles([0.001, 0.002, 0.003])
+    assert p["p50_ms"] == pytest.approx(2.0) and p["mean_ms"] == pytest.approx(2.0)
+    assert math.isnan(percentiles([])["p50_ms"])
+
+
+def test_serving_trace_recipe():
+    tr = serving_trace(seed=2026, count=400, rate=10.0)
+    assert [r.rid for r in tr] == list(range(400))
+    arr = np.array([r.arrival for r in tr])
+    assert np.all(np.diff(arr) > 0)
+    assert abs(np.mean(np.diff(arr)) - 0.1) < 0.02
+    dims = np.array([r.spec.dim for r in tr])
+    assert 0.24 < np.mean(dims == 3) < 0.36
+    for r in tr:
+        assert 16 <= r.steps <= 128 and 0.5 <= r.spec.amplitude <= 2.0
+        if r.spec.dim == 2:
+            assert 32 <= r.spec.side <= 256
+        else:
+            assert 20 <= r.spec.side <= 100
