@@ -8,7 +8,7 @@ counted as work.  One benchmark "step" is one pass of the whole job: the forward
 with checkpoints, the loss seed and the checkpointed backward rollout.
 
 Default workload (tgv2d_64k_f32): 2D periodic Taylor-Green, 256^2 = 65536 particles,
-FP32, 64 steps of dt = 0.25 H / c0, checkpoint every 8, loss sum |v_T|^2, gradient with
+FP32, 64 steps of dt = 0.125 H / c0, checkpoint every 8, loss sum |v_T|^2, gradient with
 respect to the initial state.  Inputs are synthetic (seeded jittered lattice).
 
 The JSON line also carries the roofline of the dominant pair kernel (device time from HIP

@@ -38,7 +38,7 @@ class SimSpec:
     alpha: float = 0.01
     eps: float = 0.01
     support_factor: float = 4.0   # H = support_factor * dx
-    cfl: float = 0.25             # dt = cfl * H / c0
+    cfl: float = 0.125            # dt = cfl * H / c0 = 0.25 h / c0 with smoothing length h = H / 2
     jitter: float = 0.1           # uniform jitter, fraction of dx
     box: float = 1.0
 

@@ -95,7 +95,7 @@ def test_rhs_parity(orc, dim, side, dtype):
 
 
 def test_c1_forward_fp64(orc):
-    """2D 32x32 Taylor-Green, FP64, 10 steps of dt = 0.25 H / c0 (seed 0)."""
+    """2D 32x32 Taylor-Green, FP64, 10 steps of dt = 0.125 H / c0 (seed 0)."""
     spec = SimSpec(2, 32)
     x, v, rho = _inputs(spec, 0, "f64")
     plan = _plan([spec], "f64")

@@ -159,11 +159,13 @@ def test_rhs_sample_matches_full(orc):
     np.testing.assert_allclose(ss, s[idx], rtol=1e-13)
 
 
-@pytest.mark.parametrize("dim,side,steps", [(2, 64, 64), (3, 16, 32)])
-def test_taylor_green_stays_bounded_and_decays(orc, dim, side, steps):
-    # sanity check of the dt = 0.25 H / c0 reading: the TGV kinetic energy stays
-    # bounded and decays (artificial viscosity) over the configured step counts
-    spec = SimSpec(dim, side)
+@pytest.mark.parametrize("dim,side,steps,amp", [(2, 64, 64, 1.0), (2, 32, 512, 2.0), (2, 32, 512, 0.5),
+                                                 (3, 16, 32, 1.0), (3, 12, 96, 2.0)])
+def test_taylor_green_stays_bounded_and_decays(orc, dim, side, steps, amp):
+    # the time step dt = 0.25 h / c0 with h = H / 2: the TGV kinetic energy stays bounded
+    # (never above its start, up to acoustic noise) and decays, also over rollouts several
+    # times longer than the configured ones and at the largest amplitude of the batches
+    spec = SimSpec(dim, side, amplitude=amp)
     x, v, rho = make_state(spec, 0)
     p = _params(orc, spec)
     ke0 = 0.5 * spec.mass * (v ** 2).sum()
@@ -173,4 +175,21 @@ def test_taylor_green_stays_bounded_and_decays(orc, dim, side, steps):
         kes.append(0.5 * spec.mass * (v ** 2).sum())
     assert np.all(np.isfinite(kes))
     assert kes[-1] < ke0 and max(kes) < 1.01 * ke0
-    assert np.abs(rho - spec.rho0).max() < 0.05
+    assert np.abs(rho - spec.rho0).max() < 0.15
+
+
+def test_time_step_with_h_equal_to_support_is_unstable(orc):
+    # the rejected reading h = H in dt = 0.25 h / c0 (dt = dx / c0): the same flow blows up
+    # within a few hundred steps, while the adopted step above stays bounded for 512
+    spec = SimSpec(2, 32, amplitude=1.0, cfl=0.25)
+    x, v, rho = make_state(spec, 0)
+    p = _params(orc, spec)
+    ke0 = (v ** 2).sum()
+    grew = False
+    for _ in range(256 // 8):
+        x, v, rho = orc.step(p, x, v, rho, 8)
+        ke = (v ** 2).sum()
+        if not np.isfinite(ke) or ke > 10 * ke0:
+            grew = True
+            break
+    assert grew
