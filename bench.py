@@ -266,6 +266,7 @@ def bench_serving(dev, count, warmup, load=0.75, budget_gib=96):
             "rate_per_s": round(rate, 3), "load_vs_plain_saturation": load,
             "mean_plain_service_ms": round(float(service.mean() * 1e3), 3), "pair_interactions": work,
             "hbm_budget_gib": budget_gib, "peak_admitted_gib": round(sch.peak_used / (1 << 30), 2),
+            "failed_requests": int(sum(1 for j in done if j.error)),
             "mean_batch": round(float(np.mean(sch.batch_sizes)), 2), "ticks": sch.ticks,
             "plan_creation_s": round(eng.plan_seconds, 3),
             "served": {"value": round(work / makespan_served, 1), "p50_ms": round(ps["p50_ms"], 3),

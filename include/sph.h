@@ -144,8 +144,13 @@ sph_status sph_get_tuning(const sph_plan* plan, int32_t* lanes_fwd, int32_t* lan
 sph_status sph_set_graphs(sph_plan* plan, int32_t enable);
 
 /* Bind a device workspace of at least sph_workspace_size() bytes, 256-byte
- * aligned, and upload the plan's tables into it (asynchronous on stream).
- * The workspace must stay valid until the plan is destroyed or rebound. */
+ * aligned: copies the per-simulation constants and the cell-block tables into
+ * it and fills the particle -> simulation and cell -> simulation tables on the
+ * device (asynchronous on stream; host work is O(simulations + cell blocks)).
+ * The workspace must stay valid until the plan is destroyed or rebound.  A
+ * plan may be rebound at any time, e.g. several plans taking turns on one
+ * workspace on one stream; rebinding drops cached graphs and clears the
+ * plan's status words and pair counter. */
 sph_status sph_bind(sph_plan* plan, void* workspace, size_t bytes, void* stream);
 
 /* Cell list of the state s (App. B, steps 1-2): every particle is mapped into

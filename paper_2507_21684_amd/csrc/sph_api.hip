@@ -63,7 +63,7 @@ uint64_t morton(int bx, int by, int bz, int dim)
 }
 
 struct SimHost {
-    int64_t p0, n, st0;
+    int64_t p0, n;
     int32_t cell0, blk0, nc, sub, B, nb, Bd, nblk, ncu;
 };
 
@@ -82,11 +82,10 @@ struct sph_plan {
     int64_t ncell = 0, nblk = 0;
     std::vector<sph_params> prm;
     std::vector<SimHost> sim;
-    std::vector<int32_t> h_psim, h_cell_sim, h_blk_coord, h_blk_rank, h_stencil;
-    int64_t nstencil = 0;
+    std::vector<int32_t> h_blk_coord, h_blk_rank;
     std::vector<unsigned char> h_simc;
     // workspace layout (byte offsets)
-    size_t o_simc = 0, o_psim = 0, o_cell_sim = 0, o_blk_coord = 0, o_blk_rank = 0, o_stencil = 0;
+    size_t o_simc = 0, o_psim = 0, o_cell_sim = 0, o_blk_coord = 0, o_blk_rank = 0;
     size_t o_cell_count = 0, o_cell_start = 0, o_part = 0, o_cell_of = 0, o_slot_of = 0, o_tmp = 0;
     size_t o_SB = 0, o_jdA = 0, o_jdB = 0, o_status = 0, o_part64 = 0, o_pairs = 0, o_ticket = 0;
     std::vector<SlotLayout> slot;
@@ -218,7 +217,6 @@ void fill_simconst(const sph_plan* P, std::vector<unsigned char>& out)
         c.nb = h.nb;
         c.Bd = h.Bd;
         c.ncu = h.ncu;
-        c.st0 = h.st0;
         sc[s] = c;
     }
 }
@@ -314,7 +312,8 @@ sph_status build_lists(sph_plan* P, int slot, hipStream_t st)
     const SlotLayout& L = P->slot[slot];
     ProfScope prof(P, st, SPH_KERN_BUILD);
     k_build_list<T, D><<<(unsigned)P->ncell, 64, 0, st>>>(
-        wsp<int32_t>(P, P->o_cell_sim), wsp<int32_t>(P, P->o_stencil), wsp<SimConst<T>>(P, P->o_simc),
+        wsp<int32_t>(P, P->o_cell_sim), wsp<int32_t>(P, P->o_blk_coord), wsp<int32_t>(P, P->o_blk_rank),
+        wsp<SimConst<T>>(P, P->o_simc),
         wsp<int32_t>(P, P->o_cell_start), wsp<vec4_t<T>>(P, L.jd0), P->width,
         wsp<int32_t>(P, L.nbr), wsp<int32_t>(P, L.cnt), wsp<int32_t>(P, P->o_status),
         wsp<unsigned long long>(P, P->o_pairs));
@@ -681,8 +680,6 @@ sph_status sph_plan_create(const sph_params* sims, int32_t nsims, const int64_t*
         h.blk0 = (int32_t)blk0;
         const int sw = 2 * h.sub + 1;
         h.ncu = (d == 3) ? sw * sw * sw : sw * sw;
-        h.st0 = P->nstencil;
-        P->nstencil += (int64_t)h.nblk * h.Bd * h.ncu;
         cell0 += (int64_t)h.nblk * h.Bd;
         blk0 += h.nblk;
         if (cell0 >= ((int64_t)1 << kStencilIdBits) - 1) {
@@ -712,15 +709,13 @@ sph_status sph_plan_create(const sph_params* sims, int32_t nsims, const int64_t*
     // lanes per particle of the sweeps (the autotuner may change it; results do not depend on it)
     P->lpp_fwd = P->lpp_adj = 4;
 
-    // host tables: particle -> simulation, cell -> simulation, block tables in Morton order
-    P->h_psim.resize((size_t)P->N);
-    P->h_cell_sim.resize((size_t)P->ncell);
+    // host tables: block coordinates in Morton order of each simulation and the rank of every
+    // row-major block index (the particle -> simulation and cell -> simulation tables are
+    // filled on the device at bind time)
     P->h_blk_coord.resize((size_t)P->nblk);
     P->h_blk_rank.resize((size_t)P->nblk);
     for (int s = 0; s < nsims; ++s) {
         const SimHost& h = P->sim[s];
-        for (int64_t i = 0; i < h.n; ++i) P->h_psim[(size_t)(h.p0 + i)] = s;
-        for (int64_t c = 0; c < (int64_t)h.nblk * h.Bd; ++c) P->h_cell_sim[(size_t)(h.cell0 + c)] = s;
         std::vector<std::pair<uint64_t, int32_t>> blocks;
         blocks.reserve((size_t)h.nblk);
         for (int lin = 0; lin < h.nblk; ++lin) {
@@ -733,47 +728,6 @@ sph_status sph_plan_create(const sph_params* sims, int32_t nsims, const int64_t*
             int bx = lin % h.nb, by = (lin / h.nb) % h.nb, bz = (d == 3) ? lin / (h.nb * h.nb) : 0;
             P->h_blk_coord[(size_t)(h.blk0 + r)] = bx | (by << 10) | (bz << 20);
             P->h_blk_rank[(size_t)(h.blk0 + lin)] = r;
-        }
-    }
-    // stencil table: for every cell slot, its stencil cells in lexicographic order of the offset
-    // (z, then y, then x), each with the periodic image it is seen through
-    P->h_stencil.assign((size_t)P->nstencil, 0);
-    for (int s = 0; s < nsims; ++s) {
-        const SimHost& h = P->sim[s];
-        const int sw = 2 * h.sub + 1;
-        for (int rank = 0; rank < h.nblk; ++rank) {
-            const int coord = P->h_blk_coord[(size_t)(h.blk0 + rank)];
-            const int bc[3] = {coord & 1023, (coord >> 10) & 1023, (coord >> 20) & 1023};
-            for (int w = 0; w < h.Bd; ++w) {
-                const int cc[3] = {bc[0] * h.B + w % h.B, bc[1] * h.B + (w / h.B) % h.B,
-                                   (d == 3) ? bc[2] * h.B + w / (h.B * h.B) : 0};
-                const int64_t row = h.st0 + ((int64_t)rank * h.Bd + w) * h.ncu;
-                if (cc[0] >= h.nc || cc[1] >= h.nc || cc[2] >= ((d == 3) ? h.nc : 1)) continue;  // empty slot
-                for (int u = 0; u < h.ncu; ++u) {
-                    const int o[3] = {u % sw - h.sub, (u / sw) % sw - h.sub, (d == 3) ? u / (sw * sw) - h.sub : 0};
-                    int c[3] = {0, 0, 0}, sh[3] = {0, 0, 0};
-                    for (int k = 0; k < d; ++k) {
-                        int rr = cc[k] + o[k];
-                        if (rr < 0) {
-                            rr += h.nc;
-                            sh[k] = -1;
-                        } else if (rr >= h.nc) {
-                            rr -= h.nc;
-                            sh[k] = 1;
-                        }
-                        c[k] = rr;
-                    }
-                    const int bx = c[0] / h.B, by = c[1] / h.B, bz = (d == 3) ? c[2] / h.B : 0;
-                    const int lin = (d == 3) ? (bz * h.nb + by) * h.nb + bx : by * h.nb + bx;
-                    const int rk = P->h_blk_rank[(size_t)(h.blk0 + lin)];
-                    const int wl = (d == 3) ? ((c[2] - bz * h.B) * h.B + (c[1] - by * h.B)) * h.B + (c[0] - bx * h.B)
-                                            : (c[1] - by * h.B) * h.B + (c[0] - bx * h.B);
-                    const int id = h.cell0 + rk * h.Bd + wl;
-                    P->h_stencil[(size_t)(row + u)] = id | ((sh[0] + 1) << kStencilIdBits) |
-                                                     ((sh[1] + 1) << (kStencilIdBits + 2)) |
-                                                     ((sh[2] + 1) << (kStencilIdBits + 4));
-                }
-            }
         }
     }
     if (P->dtype == SPH_F32) fill_simconst<float>(P, P->h_simc);
@@ -795,7 +749,6 @@ sph_status sph_plan_create(const sph_params* sims, int32_t nsims, const int64_t*
     P->o_cell_sim = take(4 * (size_t)P->ncell);
     P->o_blk_coord = take(4 * (size_t)P->nblk);
     P->o_blk_rank = take(4 * (size_t)P->nblk);
-    P->o_stencil = take(4 * (size_t)P->nstencil);
     P->o_cell_count = take(4 * (size_t)P->ncell);
     P->o_cell_start = take(4 * ((size_t)P->ncell + 1));
     P->o_part = take(4 * ((size_t)P->nparts + 1));
@@ -878,17 +831,22 @@ sph_status sph_bind(sph_plan* P, void* workspace, size_t bytes, void* stream)
     P->clear_graphs();          // captured graphs hold addresses inside the old workspace
     P->ws = (char*)workspace;
     HIP_TRY(hipMemcpyAsync(P->ws + P->o_simc, P->h_simc.data(), P->h_simc.size(), hipMemcpyHostToDevice, st));
-    if (P->N > 0)
-        HIP_TRY(hipMemcpyAsync(P->ws + P->o_psim, P->h_psim.data(), 4 * (size_t)P->N, hipMemcpyHostToDevice, st));
-    if (P->ncell > 0)
-        HIP_TRY(hipMemcpyAsync(P->ws + P->o_cell_sim, P->h_cell_sim.data(), 4 * (size_t)P->ncell, hipMemcpyHostToDevice, st));
     if (P->nblk > 0) {
         HIP_TRY(hipMemcpyAsync(P->ws + P->o_blk_coord, P->h_blk_coord.data(), 4 * (size_t)P->nblk, hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(P->ws + P->o_blk_rank, P->h_blk_rank.data(), 4 * (size_t)P->nblk, hipMemcpyHostToDevice, st));
     }
-    if (P->nstencil > 0)
-        HIP_TRY(hipMemcpyAsync(P->ws + P->o_stencil, P->h_stencil.data(), 4 * (size_t)P->nstencil,
-                               hipMemcpyHostToDevice, st));
+    if (P->N > 0 || P->ncell > 0) {
+        const int64_t n = std::max<int64_t>(P->N, P->ncell);
+        if (P->dtype == SPH_F32)
+            k_sim_index<float><<<grid_for(n, 256), 256, 0, st>>>(P->N, P->ncell, P->nsims,
+                                                                 wsp<SimConst<float>>(P, P->o_simc),
+                                                                 wsp<int32_t>(P, P->o_psim), wsp<int32_t>(P, P->o_cell_sim));
+        else
+            k_sim_index<double><<<grid_for(n, 256), 256, 0, st>>>(P->N, P->ncell, P->nsims,
+                                                                  wsp<SimConst<double>>(P, P->o_simc),
+                                                                  wsp<int32_t>(P, P->o_psim), wsp<int32_t>(P, P->o_cell_sim));
+        LAUNCH_CHECK("sim_index");
+    }
     if (P->ncell > 0) {
         k_fill<int32_t><<<grid_for(P->ncell, 256), 256, 0, st>>>(wsp<int32_t>(P, P->o_cell_count), P->ncell, 0);
         LAUNCH_CHECK("fill");
@@ -900,8 +858,8 @@ sph_status sph_bind(sph_plan* P, void* workspace, size_t bytes, void* stream)
     k_fill<unsigned long long><<<grid_for(kPairSlots * kPairStride, 256), 256, 0, st>>>(
         wsp<unsigned long long>(P, P->o_pairs), kPairSlots * kPairStride, 0ull);
     LAUNCH_CHECK("fill");
-    // the host tables must outlive the asynchronous copies
-    HIP_TRY(hipStreamSynchronize(st));
+    // the tables are copied from pageable host memory, which the runtime stages before the
+    // copy call returns, so nothing here waits for the device
     P->bound = true;
     return SPH_OK;
 }

@@ -50,13 +50,74 @@ struct SimConst {
     int32_t nb;         // blocks per box side
     int32_t Bd;         // B^dim
     int32_t ncu;        // stencil cells per cell, (2 sub + 1)^dim
-    int64_t st0;        // first entry of this simulation's stencil table
 };
 
-// Stencil table entry: global cell id in the low 26 bits, periodic image shift (-1, 0, +1 box
+// Stencil entry: global cell id in the low 26 bits, periodic image shift (-1, 0, +1 box
 // lengths, stored + 1) in two bits per axis above it.
 constexpr int kStencilIdBits = 26;
 constexpr int32_t kStencilIdMask = (1 << kStencilIdBits) - 1;
+
+// Stencil cell u (u = 0 .. (2 sub + 1)^dim - 1, offsets in lexicographic order z, y, x) of the
+// cell at coordinates cc of simulation S, as a stencil entry.  Cells are numbered block-major:
+// blocks of B^dim cells in Morton order (blk_rank maps a row-major block index to its rank),
+// cells row-major inside a block.
+template <int DIM, typename T>
+__device__ __forceinline__ int32_t stencil_entry(const SimConst<T>& S, const int32_t* __restrict__ blk_rank,
+                                                 const int* cc, int u)
+{
+    const int sw = 2 * S.sub + 1;
+    const int o[3] = {u % sw - S.sub, (u / sw) % sw - S.sub, (DIM == 3) ? u / (sw * sw) - S.sub : 0};
+    int c[3] = {0, 0, 0}, sh[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        int r = cc[k] + o[k];
+        if (r < 0) {
+            r += S.nc;
+            sh[k] = -1;
+        } else if (r >= S.nc) {
+            r -= S.nc;
+            sh[k] = 1;
+        }
+        c[k] = r;
+    }
+    const int B = S.B;
+    const int bx = c[0] / B, by = c[1] / B, bz = (DIM == 3) ? c[2] / B : 0;
+    const int lin = (DIM == 3) ? (bz * S.nb + by) * S.nb + bx : by * S.nb + bx;
+    const int rk = blk_rank[S.blk0 + lin];
+    const int wl = (DIM == 3) ? ((c[2] - bz * B) * B + (c[1] - by * B)) * B + (c[0] - bx * B)
+                              : (c[1] - by * B) * B + (c[0] - bx * B);
+    const int id = S.cell0 + rk * S.Bd + wl;
+    return id | ((sh[0] + 1) << kStencilIdBits) | ((sh[1] + 1) << (kStencilIdBits + 2)) |
+           ((sh[2] + 1) << (kStencilIdBits + 4));
+}
+
+// Simulation index of every particle and every cell slot: the last simulation whose first
+// particle (cell slot) is at or before it.  Empty simulations share their first index with the
+// next one, so the last such simulation is the one that owns the index.
+template <typename T>
+__global__ void k_sim_index(int64_t N, int64_t ncell, int32_t nsims, const SimConst<T>* __restrict__ sims,
+                            int32_t* __restrict__ psim, int32_t* __restrict__ cell_sim)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < N) {
+        int lo = 0, hi = nsims - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (sims[mid].p0 <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        psim[t] = lo;
+    }
+    if (t < ncell) {
+        int lo = 0, hi = nsims - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (sims[mid].cell0 <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        cell_sim[t] = lo;
+    }
+}
 
 template <typename T, int DIM>
 struct StatePtrs {
@@ -465,7 +526,8 @@ constexpr int kPairStride = 16;
 // nbr[i * width + k].
 template <typename T, int DIM>
 __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ cell_sim,
-                                                   const int32_t* __restrict__ stencil,
+                                                   const int32_t* __restrict__ blk_coord,
+                                                   const int32_t* __restrict__ blk_rank,
                                                    const SimConst<T>* __restrict__ sims,
                                                    const int32_t* __restrict__ cell_start,
                                                    const vec4_t<T>* __restrict__ jd0, int32_t width,
@@ -486,7 +548,16 @@ __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ c
     if (n == 0) return;
     const SimConst<T> S = sims[s];
     const int ncu = S.ncu;
-    const int32_t* trow = stencil + S.st0 + (int64_t)(gc - S.cell0) * ncu;
+    // the cell's coordinates from its block and its place inside the block
+    int cc[3];
+    {
+        const int local = gc - S.cell0;
+        const int rank = local / S.Bd, w = local - rank * S.Bd;
+        const int coord = blk_coord[S.blk0 + rank];
+        cc[0] = (coord & 1023) * S.B + w % S.B;
+        cc[1] = ((coord >> 10) & 1023) * S.B + (w / S.B) % S.B;
+        cc[2] = (DIM == 3) ? ((coord >> 20) & 1023) * S.B + w / (S.B * S.B) : 0;
+    }
 
     // stencil cells: particle range and periodic image code, two per lane at most
     int carry = 0;
@@ -494,7 +565,7 @@ __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ c
         const int u = lane + 64 * half;
         int first = 0, count = 0, code = 0;
         if (u < ncu) {
-            code = trow[u];
+            code = stencil_entry<DIM>(S, blk_rank, cc, u);
             const int id = code & kStencilIdMask;
             first = cell_start[id];
             count = cell_start[id + 1] - first;

@@ -5,14 +5,14 @@ out for T fixed steps with a checkpoint every K steps and then differentiated: t
 sum_i |v_i(T)|^2 and the answer is the cotangent of the initial state (x0, v0, rho0), as in
 the checkpointed scheme of Sec. 3.3 (store every K-th state, recompute the rest).
 
-The scheduler works in ticks.  Within a tick every admitted request advances by one
-checkpoint segment: requests in their forward phase step to their next checkpoint
-boundary, requests in their backward phase run the adjoint of one segment (recompute it
-from its checkpoint, then its adjoint steps in reverse).  Requests in the same phase, of the
-same dimension and with the same segment length are packed back to back into one batched
-plan (one library call per group), so the batch changes at every segment boundary:
-requests join as soon as they are admitted and leave as soon as their gradient is done
-(continuous batching).  Admission is first-come first-served under an HBM budget: a request
+The scheduler works in ticks.  Within a tick a request advances by one checkpoint segment:
+in its forward phase it steps to its next checkpoint boundary, in its backward phase it runs
+the adjoint of one segment (recompute it from its checkpoint, then its adjoint steps in
+reverse).  Requests in the same phase, of the same dimension and with the same segment
+length are packed back to back into one batched plan (one library call per group), so the
+batch changes at every segment boundary: requests join as soon as they are admitted and
+leave as soon as their gradient is done (continuous batching).  Which requests take part in
+a tick is decided by cost-fair sharing (see Scheduler).  Admission is first-come first-served under an HBM budget: a request
 is admitted when its footprint (its states, checkpoints and cotangent plus the workspace of
 a plan of its size) fits beside the requests already running; the head of the queue is
 always admitted into an empty server so that every request makes progress.
@@ -53,6 +53,8 @@ class Job:
     phase: str = "fwd"
     admitted: float = math.nan
     finished: float = math.nan
+    error: int = 0                             # device status word if the request failed
+    vtime: float = 0.0                         # estimated device time received so far
 
     @property
     def dim(self) -> int:
@@ -67,15 +69,26 @@ class Job:
 
 
 class Scheduler:
-    """First-come first-served admission under a byte budget, continuous batching by segment.
+    """First-come first-served admission under a byte budget; continuous batching by segment
+    with cost-fair sharing of the device.
 
-    The engine supplies footprint(req), admit(job), forward(jobs, n), backward(jobs, n) and
-    finish(jobs) (the latter three after a tick's work is issued), plus sync(); the scheduler
-    owns the clock and the queues and never touches device memory itself.
+    Every admitted request carries a virtual time: the estimated device time of the segments it
+    has run so far (engine.segment_cost).  Each tick runs one segment of every request whose
+    virtual time is within `quantum` seconds of the smallest one, grouped into batched calls by
+    (phase, dimension, segment length).  A request that has just run an expensive segment (a
+    large 3D simulation) therefore sits out while cheaper ones catch up, so small requests are
+    not held at the pace of the largest one, and the largest one still gets its share.  A request
+    admitted mid-way starts at the current smallest virtual time.
+
+    The engine supplies footprint(req), segment_cost(job, n), admit(job), forward(jobs, n),
+    backward(jobs, n), finish(jobs) and sync(); sync() ends a tick and may return {rid: status}
+    for requests whose device status reports a failure (non-finite values, list overflow):
+    those leave the server at once with job.error set.  The scheduler owns the clock and the
+    queues and never touches device memory itself.
     """
 
     def __init__(self, engine, ckpt_every: int = 8, budget_bytes: int = 64 << 30,
-                 clock: Optional[Callable[[], float]] = None,
+                 clock: Optional[Callable[[], float]] = None, quantum: float = 2e-3,
                  progress: Optional[Callable[[str], None]] = None, progress_every: float = 10.0):
         if ckpt_every < 1:
             raise ValueError("ckpt_every must be >= 1")
@@ -83,6 +96,7 @@ class Scheduler:
         self.K = int(ckpt_every)
         self.budget = int(budget_bytes)
         self.clock_fn = clock if clock is not None else time.perf_counter
+        self.quantum = float(quantum)
         self.now = 0.0
         self.used = 0
         self.peak_used = 0
@@ -91,9 +105,9 @@ class Scheduler:
         self.progress = progress
         self.progress_every = progress_every
 
-    def _groups(self, active: Sequence[Job]) -> Dict[Tuple[str, int, int], List[Job]]:
+    def _groups(self, jobs: Sequence[Job]) -> Dict[Tuple[str, int, int], List[Job]]:
         groups: Dict[Tuple[str, int, int], List[Job]] = {}
-        for j in active:
+        for j in jobs:
             groups.setdefault((j.phase, j.dim, j.seg_len(self.K)), []).append(j)
         return groups
 
@@ -115,17 +129,23 @@ class Scheduler:
             if not queue and not active:
                 self.now = max(self.now, pending[0].arrival)
                 continue
+            vmin = min((j.vtime for j in active), default=0.0)
             while queue and (self.used + queue[0].footprint <= self.budget or not active):
                 j = queue.popleft()
                 self.used += j.footprint
                 self.peak_used = max(self.peak_used, self.used)
                 j.admitted = self.now
+                j.vtime = vmin
                 active.append(j)
+            vmin = min(j.vtime for j in active)
+            runnable = [j for j in active if j.vtime <= vmin + self.quantum]
             t0 = self.clock_fn()
-            for j in [j for j in active if j.state is None and j.phase == "fwd" and j.pos == 0]:
+            for j in [j for j in runnable if j.state is None and j.phase == "fwd" and j.pos == 0]:
                 self.engine.admit(j)
-            groups = self._groups(active)
+            groups = self._groups(runnable)
             for (phase, _, n), jobs in sorted(groups.items(), key=lambda kv: kv[0]):
+                for j in jobs:
+                    j.vtime += self.engine.segment_cost(j, n)
                 if phase == "fwd":
                     self.engine.forward(jobs, n)
                     for j in jobs:
@@ -139,10 +159,14 @@ class Scheduler:
                         j.seg -= 1
                         if j.seg < 0:
                             j.phase = "done"
-            self.engine.sync()
+            failed = self.engine.sync() or {}
+            for j in active:
+                if j.req.rid in failed:
+                    j.error = int(failed[j.req.rid])
+                    j.phase = "done"
             self.now += self.clock_fn() - t0
             self.ticks += 1
-            self.batch_sizes.append(len(active))
+            self.batch_sizes.append(len(runnable))
             finished = [j for j in active if j.phase == "done"]
             if finished:
                 self.engine.finish(finished)
@@ -192,6 +216,7 @@ class GpuEngine:
         self.pairs = 0
         self.results: Dict[int, tuple] = {}
         self._host: Dict[int, list] = {}
+        self._members: Dict[tuple, List[int]] = {}
         self.plan_seconds = 0.0         # host time spent creating and binding plans
 
     # -- accounting
@@ -215,6 +240,17 @@ class GpuEngine:
         # checkpoints, current state, cotangent, and packed copies of both for a group call
         return (nseg + 4) * state + self.workspace_bytes(spec)
 
+    # neighbours per particle (self excluded) on the jittered lattices, and the cost model of
+    # one simulation step used for fair sharing: a fixed launch cost per step plus the pair
+    # interactions at a nominal rate; a backward step (recompute + adjoint) costs 2.5 forward
+    NEIGHBOURS = {2: 47.0, 3: 256.0}
+    STEP_LAUNCH_S = 60e-6
+    PAIRS_PER_S = 100e9
+
+    def segment_cost(self, job: Job, n: int) -> float:
+        per_step = self.STEP_LAUNCH_S + job.req.spec.n * self.NEIGHBOURS[job.dim] / self.PAIRS_PER_S
+        return n * per_step * (1.0 if job.phase == "fwd" else 2.5)
+
     # -- plans
     def _plan(self, key, jobs: Sequence[Job], tape: int):
         from .lib import Plan
@@ -229,6 +265,7 @@ class GpuEngine:
             self._plans[key] = p
             self.plan_seconds += time.perf_counter() - t0
         self._used_plans[key] = p
+        self._members[key] = [j.req.rid for j in jobs]
         return p
 
     def _pack(self, parts: Sequence[tuple]):
@@ -279,28 +316,38 @@ class GpuEngine:
 
     def finish(self, jobs: Sequence[Job]):
         for j in jobs:
-            self.results[j.req.rid] = j.cot
+            self.results[j.req.rid] = None if j.error else j.cot
             j.cot = None
             j.ckpts = []
 
     def sync(self):
         # work is counted on the forward states only (each is also the start of one adjoint
         # step); the recompute builds of the backward plans are not work and are discarded
+        failed = {}
         for key, p in self._used_plans.items():
             n = p.pair_count()
             if key[0] == "fwd":
                 self.pairs += n
+            st = p.poll()
+            for rid, word in zip(self._members[key], st):
+                if word:
+                    failed[rid] = int(word)
         self.torch.cuda.synchronize()
         # plans not used in this tick belong to compositions that no longer exist
         self._plans = dict(self._used_plans)
+        self._members = {k: self._members[k] for k in self._plans}
         self._used_plans = {}
+        for rid in failed:
+            self.results[rid] = None
+        return failed
 
 
 def serve(trace: Sequence[Request], dtype: str = "f32", ckpt_every: int = 8, budget_bytes: int = 64 << 30,
-          device=None, tuned: bool = True, progress: Optional[Callable[[str], None]] = None):
+          device=None, tuned: bool = True, progress: Optional[Callable[[str], None]] = None,
+          quantum: float = 2e-3):
     """Serve `trace` with continuous batching; returns (scheduler, engine, finished jobs)."""
     eng = GpuEngine(dtype, ckpt_every, device, tuned)
-    sch = Scheduler(eng, ckpt_every, budget_bytes, progress=progress)
+    sch = Scheduler(eng, ckpt_every, budget_bytes, quantum=quantum, progress=progress)
     done = sch.run(trace)
     return sch, eng, done
 

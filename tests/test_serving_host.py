@@ -28,9 +28,13 @@ class RecordingEngine:
         self.calls = []
         self.admitted = []
         self.finished = []
+        self.fail = set()
 
     def footprint(self, req):
         return req.spec.n
+
+    def segment_cost(self, job, n):
+        return 1e-6 * n * job.req.spec.n * (1.0 if job.phase == "fwd" else 2.0)
 
     def admit(self, job):
         self.admitted.append(job.req.rid)
@@ -48,7 +52,7 @@ class RecordingEngine:
         self.finished.extend(j.req.rid for j in jobs)
 
     def sync(self):
-        pass
+        return {rid: 1 for rid in self.fail if any(rid in c[1] for c in self.calls)}
 
 
 def small_trace(seed=7, count=40, rate=200.0):
@@ -164,3 +168,33 @@ def test_serving_trace_recipe():
             assert 32 <= r.spec.side <= 256
         else:
             assert 20 <= r.spec.side <= 100
+
+
+def test_failed_request_leaves_at_once():
+    trace = [Request(0, 0.0, SimSpec(2, 16), 0, 64), Request(1, 0.0, SimSpec(2, 16), 1, 64)]
+    clock = FakeClock()
+    eng = RecordingEngine(clock)
+    eng.fail = {0}
+    sch = Scheduler(eng, 8, 1 << 40, clock=clock)
+    done = {j.req.rid: j for j in sch.run(trace)}
+    assert done[0].error == 1 and done[1].error == 0
+    assert sum(1 for c in eng.calls if 0 in c[1]) == 1        # dropped after its first tick
+    assert sum(1 for c in eng.calls if 1 in c[1]) == 16       # 8 forward + 8 backward segments
+
+
+def test_small_request_is_not_held_at_the_pace_of_a_large_one():
+    # a large request is running when a small one arrives: with cost-fair sharing the small
+    # one finishes long before the large one, and in far fewer ticks than the large one needs
+    trace = [Request(0, 0.0, SimSpec(3, 40), 0, 128), Request(1, 1e-9, SimSpec(2, 16), 1, 128)]
+    clock = FakeClock()
+    eng = RecordingEngine(clock)
+    sch = Scheduler(eng, 8, 1 << 40, clock=clock, quantum=1e-3)
+    done = {j.req.rid: j for j in sch.run(trace)}
+    small, large = done[1], done[0]
+    assert small.finished < 0.2 * large.finished
+    ticks_with_large = sum(1 for c in eng.calls if 0 in c[1])
+    assert ticks_with_large == 32
+    # in plain segment-per-tick sharing the small request would have taken 32 ticks of the large one
+    ticks_before_small_done = sum(1 for c in eng.calls[:max(i for i, c in enumerate(eng.calls) if 1 in c[1]) + 1]
+                                  if 0 in c[1])
+    assert ticks_before_small_done <= 3
