@@ -129,7 +129,33 @@ def timed_jobs(plan, x0, v0, r0, wl, reps, classes=None):
     return t1 - t0, plan.profile_read()
 
 
-def roofline(prof, dom, wl, per_state, reps, dim, n_particles):
+def source_hash():
+    """sha256 prefix of the kernel sources, the key of the committed counter tables."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("paper_2507_21684_amd/csrc/sph_device.hpp", "paper_2507_21684_amd/csrc/sph_api.hip"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel_symbol):
+    """HBM bytes per dispatch of a kernel from the committed rocprofv3 counter summary, or None when
+    the summary has no line for it or the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_and_counters.md")
+    try:
+        lines = open(path).read().splitlines()
+    except OSError:
+        return None
+    h = source_hash()
+    for ln in lines:
+        f = ln.split()
+        if len(f) == 5 and f[0] == "traffic" and f[1] == workload and f[2] == kernel_symbol and f[3] == h:
+            return int(f[4])
+    return None
+
+
+def roofline(prof, dom, wl, per_state, reps, dim, n_particles, lanes=(4, 4)):
     """Roofline of the dominant kernel from its HIP-event launch times in the timed region.
 
     k_sweep / k_adj_sweep: ALU-bound; algorithmic flops per launch = flops per directed pair x
@@ -150,8 +176,10 @@ def roofline(prof, dom, wl, per_state, reps, dim, n_particles):
         bytes_per_launch = (4 * entries + launches * n_particles * (4 + (16 if wl.dtype == "f32" else 32))) / launches
         achieved = bytes_per_launch / mean_launch_s / 1e9
         peak = 8000.0
+        tdt = "float" if wl.dtype == "f32" else "double"
+        traffic = measured_traffic(wl.name, "sph::k_build_list<%s,%d>" % (tdt, dim))
         return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": peak, "unit": "GB/s",
-                "frac": round(achieved / peak, 4), "traffic": None,
+                "frac": round(achieved / peak, 4), "traffic": traffic,
                 "mean_launch_us": round(mean_launch_s * 1e6, 2), "launches": n_dom,
                 "algorithmic_bytes_per_launch": int(bytes_per_launch)}
     if dom == "sweep":
@@ -161,8 +189,11 @@ def roofline(prof, dom, wl, per_state, reps, dim, n_particles):
     flops_per_launch = FLOPS_PER_PAIR[(dom, dim)] * pairs / n_dom
     achieved = flops_per_launch / mean_launch_s / 1e12
     peak = PEAK_TFLOPS[wl.dtype]
+    tdt = "float" if wl.dtype == "f32" else "double"
+    sym = ("sph::k_sweep<%s,%d,0,%d>" % (tdt, dim, lanes[0]) if dom == "sweep"
+           else "sph::k_adj_sweep<%s,%d,%d>" % (tdt, dim, lanes[1]))
     return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": None, "mean_launch_us": round(mean_launch_s * 1e6, 2),
+            "frac": round(achieved / peak, 4), "traffic": measured_traffic(wl.name, sym), "mean_launch_us": round(mean_launch_s * 1e6, 2),
             "launches": n_dom, "pairs_per_launch": int(pairs / n_dom)}
 
 
@@ -337,7 +368,7 @@ def main():
     assert np.all(status == 0), "device reported non-finite values or neighbour overflow: %s" % status
     value = (p_fwd + p_adj) * args.steps / elapsed
     dim = wl.sims[0].dim
-    roof = roofline(prof, dom, wl, per_state, args.steps, dim, int(sum(s.n for s in wl.sims)))
+    roof = roofline(prof, dom, wl, per_state, args.steps, dim, int(sum(s.n for s in wl.sims)), lanes)
 
     log("timed %d jobs: %.3f ms per job" % (args.steps, 1e3 * elapsed / args.steps))
     cpu = None
