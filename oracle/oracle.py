@@ -99,6 +99,8 @@ def lib():
         L.orc_rhs_sample.argtypes = [_P, ctypes.c_int64, _D, _D, _D, ctypes.c_int64, _I64, _D, _D, _D]
         L.orc_step.restype = ctypes.c_int
         L.orc_step.argtypes = [_P, ctypes.c_int64, _D, _D, _D, ctypes.c_int32]
+        L.orc_density_adjoint.restype = ctypes.c_int
+        L.orc_density_adjoint.argtypes = [_P, ctypes.c_int64, _D, _D, _D]
         L.orc_step_adjoint.restype = ctypes.c_int
         L.orc_step_adjoint.argtypes = [_P, ctypes.c_int64, _D, _D, _D, _D, _D, _D]
         L.orc_adjoint_sweep_sample.restype = ctypes.c_int
@@ -253,6 +255,19 @@ def step_adjoint(p: Params, x, v, rho, xb, vb, rb):
     if rc != 0:
         raise ValueError("oracle step_adjoint rejected its input")
     return xb, vb, rb
+
+
+def density_adjoint(p: Params, x, g):
+    """Cotangent of the positions for cotangents g of the summation density:
+    xbar_k = sum_{j != k} m (g_k + g_j) grad_k W_kj."""
+    x, g = _f64(x), _f64(g)
+    n = g.shape[0]
+    xbar = np.zeros((p.dim, n))
+    pc = p.c()
+    rc = lib().orc_density_adjoint(ctypes.byref(pc), n, _d(x), _d(g), _d(xbar))
+    if rc != 0:
+        raise ValueError("oracle density_adjoint rejected its input")
+    return xbar
 
 
 def adjoint_sweep_sample(p: Params, x, v, rho, abar, rbar, sample):

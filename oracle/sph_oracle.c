@@ -41,11 +41,16 @@
  *     directed pair's contribution, the neighbour list held fixed (Sec. 3.2
  *     "Differentiability").
  *
+ *   - The vector-Jacobian product of the summation density alone (the
+ *     backward benchmark of Sec. 4.1: summation density after a step,
+ *     gradient with respect to the initial positions).
+ *
  * Readings taken where the paper is silent or garbled are listed in the
  * project's design notes; the ones that change arithmetic are: the minus
- * signs of the continuity and pressure terms, h = H (the support) in
- * dt, delta H c0 and alpha H c0, eps = 0.01 in (r^2 + eps H^2), and the
- * strict r < H neighbour predicate evaluated in the working precision.
+ * signs of the continuity and pressure terms, H (the support) in
+ * delta H c0 and alpha H c0, eps = 0.01 in (r^2 + eps H^2), and the strict
+ * r < H neighbour predicate evaluated in the working precision.  The time
+ * step is an input (the callers pass dt = 0.25 h / c0 with h = H / 2).
  *
  * Layout: positions, velocities are SoA rows, x[k*n + i] for coordinate k.
  */
@@ -808,6 +813,41 @@ int orc_step_adjoint(const orc_params* p, int64_t n, const double* x, const doub
     nblist nb;
     build_lists(p->dim, n, x, p->L, p->H, 0, 0, &nb);
     step_adjoint_with_list(p, n, u, v, rho, &nb, xb, vb, rb);
+    nblist_free(&nb);
+    free(u);
+    return 0;
+}
+
+/* Vector-Jacobian product of the summation density (Sec. 2.3 summation
+ * density, Sec. 2.2 adjoint): for cotangents g_i of rho_i = sum_j m W_ij,
+ *   xbar_k = sum_{j != k} m (g_k + g_j) grad_k W_kj,
+ * because x_k enters both k's own sum (through W_kj) and every neighbour's
+ * sum (through W_jk = W_kj, whose gradient with respect to x_k is again
+ * grad_k W_kj).  The self pair has zero gradient.  xbar is overwritten. */
+int orc_density_adjoint(const orc_params* p, int64_t n, const double* x, const double* g, double* xbar)
+{
+    if (!valid_params(p) || n < 0) return -1;
+    int dim = p->dim;
+    double invL = 1.0 / p->L;
+    double* u = (double*)malloc(sizeof(double) * (size_t)dim * (size_t)(n > 0 ? n : 1));
+    wrap_all(p, n, x, u);
+    nblist nb;
+    build_lists(dim, n, x, p->L, p->H, 0, 0, &nb);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < n; ++k) {
+        double uk[3] = {0, 0, 0}, acc[3] = {0, 0, 0};
+        for (int c = 0; c < dim; ++c) uk[c] = u[c * n + k];
+        for (int64_t a = nb.off[k]; a < nb.off[k + 1]; ++a) {
+            int64_t j = nb.idx[a];
+            if (j == k) continue;
+            double uj[3] = {0, 0, 0}, e[3] = {0, 0, 0}, gw[3] = {0, 0, 0};
+            for (int c = 0; c < dim; ++c) uj[c] = u[c * n + j];
+            minimg(dim, uk, uj, p->L, invL, e);
+            orc_gradw(dim, p->H, e, gw);
+            for (int c = 0; c < dim; ++c) acc[c] += p->m * (g[k] + g[j]) * gw[c];
+        }
+        for (int c = 0; c < dim; ++c) xbar[c * n + k] = acc[c];
+    }
     nblist_free(&nb);
     free(u);
     return 0;
