@@ -252,6 +252,59 @@ def bench_batched(dev, reps):
             "speedup": round(t_plain / t_batched, 2)}
 
 
+def bench_density_backward(dev, reps=20):
+    """The paper's backward benchmark (Sec. 4.1): one step of the 2D 256^2 FP32 state, the
+    summation density of all particles after it, and the gradient of its sum with respect to
+    the initial positions.  Reports the forward and backward device times and the backward
+    share of the total (the paper measured 32 % at 64 Ki particles)."""
+    import numpy as np
+    import torch
+    from paper_2507_21684_amd import inputs as I
+    from paper_2507_21684_amd.lib import Plan
+    spec = I.SimSpec(2, 256)
+    host = [a.astype(np.float32) for a in I.make_state(spec, 0)]
+    x0, v0, r0 = (torch.tensor(a, device=dev) for a in host)
+    plan = Plan([spec.params()], [spec.n], "f32", tape_depth=1, device=dev)
+    ones = torch.ones(spec.n, dtype=torch.float32, device=dev)
+
+    def fwd():
+        x, v, r = x0.clone(), v0.clone(), r0.clone()
+        plan.step(x, v, r, 1)
+        _, _, rs = plan.rhs(x, v, r, rho_sum=True)
+        return x, v, r, rs
+
+    def bwd(x1, v1, r1):
+        xb = plan.density_adjoint(x1, v1, r1, ones)
+        vb, rb = torch.zeros_like(v0), torch.zeros_like(r0)
+        plan.step_adjoint(x0, v0, r0, xb, vb, rb)
+        return xb
+
+    for _ in range(3):
+        bwd(*fwd()[:3])
+    torch.cuda.synchronize()
+    t_f, t_b = [], []
+    for _ in range(reps):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        x1, v1, r1, _ = fwd()
+        e1.record()
+        bwd(x1, v1, r1)
+        e2.record()
+        torch.cuda.synchronize()
+        t_f.append(e0.elapsed_time(e1))
+        t_b.append(e1.elapsed_time(e2))
+    plan.pair_count()
+    fwd()
+    pairs = plan.pair_count()          # two list builds: the step's state and the state after it
+    tf, tb = float(np.median(t_f)), float(np.median(t_b))
+    return {"workload": "density_backward_tgv2d_64k_f32", "particles": spec.n,
+            "forward_ms": round(tf, 4), "backward_ms": round(tb, 4),
+            "backward_share": round(tb / (tf + tb), 3), "paper_backward_share": 0.32,
+            "pair_interactions_per_s": round(2 * pairs / ((tf + tb) * 1e-3), 1),
+            "note": "forward = one step + summation density (2 list builds); backward = density VJP + step VJP "
+                    "(2 list builds); median of %d on events around each phase" % reps}
+
+
 def log(msg):
     """Progress line on stderr (the JSON result is the only line on stdout)."""
     print("[bench] " + msg, file=sys.stderr, flush=True)
@@ -386,6 +439,11 @@ def main():
         log("batched workload")
         batched = bench_batched(dev, max(1, min(args.steps, 3)))
 
+    dens = None
+    if args.workload == "tgv2d_64k_f32":
+        log("density backward benchmark")
+        dens = bench_density_backward(dev)
+
     served = None
     if args.serving > 0 and args.workload != "batched_512_tgv2d_f32":
         torch.cuda.empty_cache()
@@ -401,7 +459,8 @@ def main():
                       "ckpt_every": wl.ckpt_every, "adjoint": wl.adjoint, "loss": wl.loss,
                       "pairs_fwd": p_fwd, "pairs_adj": p_adj, "pairs_recompute": p_rec,
                       "lanes_per_particle": list(lanes)},
-           "roofline": roof, "kernel_ms_per_job": breakdown, "cpu_baseline": cpu, "batched": batched, "serving": served}
+           "roofline": roof, "kernel_ms_per_job": breakdown, "cpu_baseline": cpu, "batched": batched, "serving": served,
+           "density_backward": dens}
     print(json.dumps(out), flush=True)
 
 

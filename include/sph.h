@@ -224,6 +224,20 @@ sph_status sph_step_adjoint(sph_plan* plan, const sph_state* s_n, sph_state* cot
 sph_status sph_rollout_backward(sph_plan* plan, const sph_state* ckpt, int32_t nsteps, int32_t ckpt_every,
                                 sph_state* cot, void* stream);
 
+/* Vector-Jacobian product of the summation density rho_i = sum_j m W_ij
+ * (Sec. 2.3 summation density; the backward benchmark of Sec. 4.1 takes the
+ * summation density after a step and differentiates it with respect to the
+ * initial positions).  Given the state s and cotangents g = rho_sum_bar
+ * (device, N values of the plan's dtype, original order), writes
+ *     x_bar[k][i] = sum_{j != i} m (g_i + g_j) dW_ij/dx_i[k]
+ * into x_bar (device, dim rows of N, overwritten; the cotangent of the
+ * positions only: rho_sum depends on nothing else).  Rebuilds the cell list
+ * and the neighbour lists of s; results are deterministic and do not depend on
+ * the batch.  Compose with sph_step_adjoint (cotangent (x_bar, 0, 0)) for the
+ * gradient through a step.  INVALID_ARG on null arrays. */
+sph_status sph_density_adjoint(sph_plan* plan, const sph_state* s, const void* rho_sum_bar, void* x_bar,
+                               void* stream);
+
 /* Copy the per-simulation status words (host int32[nsims], SPH_FLAG_* bits)
  * and clear them.  SYNCHRONOUS. */
 sph_status sph_poll(sph_plan* plan, int32_t* per_sim_status, void* stream);

@@ -566,6 +566,37 @@ void key_state(std::vector<uintptr_t>& key, const sph_state* s)
     key.push_back((uintptr_t)s->rho);
 }
 
+template <typename T, int D, int LPP>
+void launch_density_adj(sph_plan* P, const SlotLayout& L, const T* gs, T* xbar, hipStream_t st)
+{
+    const int64_t lanes = P->N * LPP;
+    k_density_adj<T, D, LPP><<<grid_for(lanes, 256), 256, 0, st>>>(
+        P->N, P->width, wsp<int32_t>(P, L.nbr), wsp<int32_t>(P, L.cnt), wsp<vec4_t<T>>(P, L.jd0), gs,
+        wsp<int32_t>(P, L.orig), wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc), xbar);
+}
+
+// Summation-density VJP of the state s: sort, lists, the cotangent gathered into sorted
+// order (adjoint scratch), then the pair sweep writing xbar in original order.
+template <typename T, int D>
+sph_status do_density_adjoint(sph_plan* P, const sph_state* s, const T* g, T* xbar, hipStream_t st)
+{
+    if (P->N == 0) return SPH_OK;
+    RC_TRY((sort_into<T, D>(P, user_state<T, D>(s), nullptr, 0, st)));
+    RC_TRY((build_lists<T, D>(P, 0, st)));
+    const SlotLayout& L = P->slot[0];
+    T* gs = wsp<T>(P, P->o_jdA);
+    ProfScope prof(P, st, SPH_KERN_ADJOINT);
+    k_gather_sorted<T><<<grid_for(P->N, 256), 256, 0, st>>>(P->N, g, wsp<int32_t>(P, L.orig), gs);
+    LAUNCH_CHECK("gather_sorted");
+    switch (P->lpp_adj) {
+    case 2: launch_density_adj<T, D, 2>(P, L, gs, xbar, st); break;
+    case 8: launch_density_adj<T, D, 8>(P, L, gs, xbar, st); break;
+    default: launch_density_adj<T, D, 4>(P, L, gs, xbar, st); break;
+    }
+    LAUNCH_CHECK("density_adj");
+    return SPH_OK;
+}
+
 template <typename T, int D>
 sph_status do_neighbors(sph_plan* P, const sph_state* s, int64_t* offsets, int32_t* nbr, int64_t capacity,
                         int64_t* total, hipStream_t st)
@@ -915,6 +946,19 @@ sph_status sph_step_adjoint(sph_plan* P, const sph_state* s_n, sph_state* cot, v
     RC_TRY(check_state(P, s_n, "state"));
     RC_TRY(check_state(P, cot, "cotangent"));
     return DISPATCH(P, do_step_adjoint, P, s_n, cot, (hipStream_t)stream);
+}
+
+sph_status sph_density_adjoint(sph_plan* P, const sph_state* s, const void* rho_sum_bar, void* x_bar, void* stream)
+{
+    RC_TRY(check_bound(P));
+    RC_TRY(check_state(P, s, "state"));
+    if (P->N > 0 && (!rho_sum_bar || !x_bar)) return fail(SPH_ERR_INVALID_ARG, "rho_sum_bar and x_bar must not be null");
+    hipStream_t st = (hipStream_t)stream;
+    if (P->dtype == SPH_F32)
+        return P->dim == 2 ? do_density_adjoint<float, 2>(P, s, (const float*)rho_sum_bar, (float*)x_bar, st)
+                           : do_density_adjoint<float, 3>(P, s, (const float*)rho_sum_bar, (float*)x_bar, st);
+    return P->dim == 2 ? do_density_adjoint<double, 2>(P, s, (const double*)rho_sum_bar, (double*)x_bar, st)
+                       : do_density_adjoint<double, 3>(P, s, (const double*)rho_sum_bar, (double*)x_bar, st);
 }
 
 sph_status sph_rollout_backward(sph_plan* P, const sph_state* ckpt, int32_t nsteps, int32_t ckpt_every,

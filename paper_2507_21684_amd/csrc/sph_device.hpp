@@ -887,6 +887,97 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
     }
 }
 
+// ---------------------------------------------------------------- density-summation adjoint
+//
+// Cotangent of the positions for cotangents g of the summation density rho_i = m sum_j W_ij
+// (the backward benchmark of Sec. 4.1): xbar_k = m sum_{j != k} (g_k + g_j) grad_k W_kj, since
+// x_k enters k's own sum and, through W_jk = W_kj, every neighbour's.  The self entry of the
+// list has a zero pair vector and adds nothing.  Same list traversal and canonical partial
+// sums as the forward sweep.
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_sorted(int64_t N, const T* __restrict__ in,
+                                                       const int32_t* __restrict__ orig, T* __restrict__ out)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < N) out[q] = in[orig[q]];
+}
+
+template <typename T, int DIM, int LPP>
+__global__ __launch_bounds__(256) void k_density_adj(int64_t N, int32_t width, const int32_t* __restrict__ nbr,
+                                                     const int32_t* __restrict__ nbr_count,
+                                                     const vec4_t<T>* __restrict__ jd0, const T* __restrict__ gs,
+                                                     const int32_t* __restrict__ orig,
+                                                     const int32_t* __restrict__ psim,
+                                                     const SimConst<T>* __restrict__ sims, T* __restrict__ xbar)
+{
+    constexpr int NQ = kLeaves / LPP;
+    constexpr int U = kPairsInFlight;
+    static_assert(LPP >= 2 && LPP <= 8 && U % NQ == 0, "lanes per particle must be 2, 4 or 8");
+    const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int64_t i = t / LPP;
+    const int r = (int)(t - i * LPP);
+    if (i >= N) return;
+    const SimConst<T>& S = sims[psim[i]];
+    const PairConst<T> c = pair_const(S);
+    T ui[3] = {0, 0, 0};
+    unpack_u<T, DIM>(jd0[i], ui);
+    const T gi = gs[i];
+    int n = nbr_count[i];
+    n = n < width ? n : width;
+    const int mcount = (n - r + LPP - 1) / LPP;
+    const int32_t* row = nbr + i * (int64_t)width;
+    T acc[NQ][3];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q][0] = acc[q][1] = acc[q][2] = T(0);
+    for (int m0 = 0; m0 < mcount; m0 += U) {
+        uint32_t jj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) jj[u] = (m0 + u < mcount) ? (uint32_t)row[r + LPP * (m0 + u)] : (uint32_t)i;
+        vec4_t<T> a[U];
+        T gj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            a[u] = ldo(jd0, jj[u]);
+            gj[u] = ldo(gs, jj[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (m0 + u >= mcount) continue;
+            T uj[3] = {0, 0, 0}, d[3] = {0, 0, 0};
+            unpack_u<T, DIM>(a[u], uj);
+            T r2 = 0;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                T dd = ui[k] - uj[k];
+                dd -= c.L * rint(dd * c.invL);
+                d[k] = dd;
+                r2 += dd * dd;
+            }
+            const T q = fast_sqrt(r2) * c.invH;
+            const T tt = T(1) - q;
+            const T t2 = tt * tt;
+            const T t5 = t2 * t2 * tt;
+            const T gF = c.kG * (T(-56.0 / 3.0) * t5 * (T(1) + T(5) * q));
+            const T w = (gi + gj[u]) * gF;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) acc[u % NQ][k] += w * d[k];
+        }
+    }
+    T out[3] = {0, 0, 0};
+    T tmp[NQ];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) tmp[q] = acc[q][k];
+        out[k] = combine_leaves<LPP>(tmp);
+    }
+    if (r != 0) return;
+    const int o = orig[i];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) xbar[(int64_t)k * N + o] = S.m * out[k];
+}
+
 // ---------------------------------------------------------------- unsort
 
 template <typename T, int DIM>

@@ -61,6 +61,8 @@ def lib():
         L.sph_set_tuning.restype = st
         L.sph_set_tuning.argtypes = [_VP, ctypes.c_int32, ctypes.c_int32]
         L.sph_get_tuning.restype = st
+        L.sph_density_adjoint.restype = st
+        L.sph_density_adjoint.argtypes = [_VP, ctypes.POINTER(SphState), _VP, _VP, _VP]
         L.sph_set_graphs.argtypes = [_VP, ctypes.c_int32]
         L.sph_set_graphs.restype = ctypes.c_int32
         L.sph_get_tuning.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
@@ -112,7 +114,7 @@ def exported_symbols() -> List[str]:
     return ["sph_plan_create", "sph_plan_destroy", "sph_workspace_size", "sph_plan_info", "sph_bind",
             "sph_build_cells", "sph_neighbors", "sph_rhs", "sph_step", "sph_step_adjoint", "sph_poll",
             "sph_pair_count", "sph_profile_enable", "sph_profile_read", "sph_last_error", "sph_set_tuning",
-            "sph_get_tuning", "sph_rollout_backward", "sph_set_graphs"]
+            "sph_get_tuning", "sph_rollout_backward", "sph_set_graphs", "sph_density_adjoint"]
 
 
 KERNEL_CLASSES = ["sort", "build", "sweep", "adjoint", "other"]
@@ -261,6 +263,17 @@ class Plan:
         c = self.state(gx, gv, grho)
         _check(lib().sph_rollout_backward(self._h, cp, int(nsteps), int(ckpt_every), ctypes.byref(c),
                                           _stream_ptr(stream)))
+
+    def density_adjoint(self, x, v, rho, rho_sum_bar, stream=None) -> torch.Tensor:
+        """Cotangent of the positions for cotangents rho_sum_bar[N] of the summation density."""
+        s = self.state(x, v, rho)
+        g = rho_sum_bar.contiguous()
+        if tuple(g.shape) != (self.N,) or g.dtype != self.torch_dtype or not g.is_cuda:
+            raise ValueError("rho_sum_bar must be a %s GPU tensor of shape (%d,)" % (self.torch_dtype, self.N))
+        xbar = torch.empty((self.dim, self.N), dtype=self.torch_dtype, device=self.device)
+        _check(lib().sph_density_adjoint(self._h, ctypes.byref(s), g.data_ptr(), xbar.data_ptr(),
+                                         _stream_ptr(stream)))
+        return xbar
 
     def set_tuning(self, lanes_fwd: int, lanes_adj: int):
         _check(lib().sph_set_tuning(self._h, int(lanes_fwd), int(lanes_adj)))

@@ -52,3 +52,28 @@ class SPHRollout(torch.autograd.Function):
 def rollout(plan: Plan, x0, v0, rho0, nsteps: int, ckpt_every: int = 8) -> Tuple[torch.Tensor, ...]:
     """Differentiable T-step rollout of all simulations of `plan`."""
     return SPHRollout.apply(x0, v0, rho0, plan, nsteps, ckpt_every)
+
+
+class SPHDensitySum(torch.autograd.Function):
+    """(x, v, rho) -> summation density rho_i = sum_j m W_ij (Sec. 2.3); differentiable in x
+    through `sph_density_adjoint` (the density depends on nothing else)."""
+
+    @staticmethod
+    def forward(ctx, x: torch.Tensor, v: torch.Tensor, rho: torch.Tensor, plan: Plan):
+        xs, vs, rs = x.detach().contiguous(), v.detach().contiguous(), rho.detach().contiguous()
+        _, _, rho_sum = plan.rhs(xs, vs, rs, rho_sum=True)
+        ctx.plan = plan
+        ctx.save_for_backward(xs, vs, rs)
+        return rho_sum
+
+    @staticmethod
+    def backward(ctx, g: Optional[torch.Tensor]):
+        xs, vs, rs = ctx.saved_tensors
+        if g is None:
+            return None, None, None, None
+        return ctx.plan.density_adjoint(xs, vs, rs, g.detach().contiguous()), None, None, None
+
+
+def density_sum(plan: Plan, x, v, rho) -> torch.Tensor:
+    """Differentiable summation density of all simulations of `plan` (original order)."""
+    return SPHDensitySum.apply(x, v, rho, plan)

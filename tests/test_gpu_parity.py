@@ -318,3 +318,54 @@ def test_graph_mode_bitwise():
     out = run(plan, b1)
     for a, r in zip(out, ref):
         assert torch.equal(a, r)
+
+
+@pytest.mark.parametrize("dtype,dim,side", [("f64", 2, 24), ("f32", 2, 40), ("f32", 3, 16)])
+def test_density_adjoint_parity(orc, dtype, dim, side):
+    """Summation-density VJP against the oracle on identical inputs (gradient tolerance)."""
+    spec = SimSpec(dim, side)
+    x, v, rho = _inputs(spec, 9, dtype)
+    g = np.random.default_rng(3).normal(size=spec.n).astype(x.dtype)
+    plan = _plan([spec], dtype)
+    gx, gv, gr, gg = _to_gpu([x, v, rho, g], dtype)
+    got = plan.density_adjoint(gx, gv, gr, gg).cpu().numpy().astype(np.float64)
+    ref = orc.density_adjoint(_oparams(orc, spec), x, g)
+    tol = 1e-9 if dtype == "f64" else 1e-3
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+
+
+def test_backward_benchmark_gradient(orc):
+    """One step, summation density of all particles, gradient w.r.t. the initial positions
+    (the backward benchmark), through autograd, against the oracle's composition."""
+    from paper_2507_21684_amd.rollout import density_sum, rollout
+    spec = SimSpec(2, 48)
+    x, v, rho = _inputs(spec, 2, "f32")
+    plan = _plan([spec], "f32")
+    gx0, gv0, gr0 = _to_gpu([x, v, rho], "f32")
+    gx0.requires_grad_(True)
+    x1, v1, r1 = rollout(plan, gx0, gv0, gr0, 1, 1)
+    loss = density_sum(plan, x1, v1, r1).sum()
+    loss.backward()
+    p = _oparams(orc, spec)
+    ox1, ov1, or1 = orc.step(p, x, v, rho, 1)
+    xb1 = orc.density_adjoint(p, ox1, np.ones(spec.n))
+    ref, _, _ = orc.step_adjoint(p, x, v, rho, xb1, np.zeros_like(v), np.zeros_like(rho))
+    got = gx0.grad.cpu().numpy().astype(np.float64)
+    assert np.abs(got - ref).max() <= 1e-3 * np.abs(ref).max()
+
+
+def test_density_adjoint_batch_invariance():
+    """A simulation's density VJP is bitwise the same alone and inside a batch."""
+    specs = [SimSpec(2, 20), SimSpec(2, 33, amplitude=1.7)]
+    states = [_inputs(s, 30 + k, "f32") for k, s in enumerate(specs)]
+    gs = [np.random.default_rng(k).normal(size=s.n).astype(np.float32) for k, s in enumerate(specs)]
+    solo = []
+    for s, st, g in zip(specs, states, gs):
+        p = _plan([s], "f32")
+        t = _to_gpu(list(st) + [g], "f32")
+        solo.append(p.density_adjoint(*t).cpu().numpy())
+    cat = [np.concatenate([st[k] for st in states], axis=-1) for k in range(3)] + [np.concatenate(gs)]
+    pb = _plan(specs, "f32")
+    out = pb.density_adjoint(*_to_gpu(cat, "f32")).cpu().numpy()
+    np.testing.assert_array_equal(out[:, :specs[0].n], solo[0])
+    np.testing.assert_array_equal(out[:, specs[0].n:], solo[1])
