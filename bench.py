@@ -101,6 +101,22 @@ def count_pairs(plan, x0, v0, r0, wl):
     return per_state
 
 
+def count_pairs_schedule(plan, x0, v0, r0, wl):
+    """Directed pairs (j != i) of the forward states n = 0..T-1 along the job's own trajectory:
+    calls of one rebuild interval each keep the job's schedule of list builds."""
+    import torch
+    R = getattr(plan, "rebuild_every", 1)
+    xs, vs, rs = x0.clone(), v0.clone(), r0.clone()
+    plan.pair_count()
+    done = 0
+    while done < wl.steps:
+        n = min(R, wl.steps - done)
+        plan.step(xs, vs, rs, n)
+        done += n
+    torch.cuda.synchronize()
+    return plan.pair_count()
+
+
 def cpu_baseline(wl, host):
     """The oracle as it stands, on this host's cores, over the same job."""
     from oracle import oracle as O
@@ -169,8 +185,10 @@ def roofline(prof, dom, wl, per_state, reps, dim, n_particles, lanes=(4, 4)):
     mean_launch_s = ms_dom / n_dom * 1e-3
     kernel = {"sweep": "k_sweep", "adjoint": "k_adj_sweep", "build": "k_build_list"}[dom]
     if dom == "build":
-        # one build per forward state; the backward pass rebuilds every state of each segment
-        states = list(range(wl.steps)) * (2 if wl.adjoint else 1)
+        # one build per rebuild interval, forward and again in the backward's recomputation
+        # (with a list skin the lists hold more entries than the pairs counted here)
+        R = lanes[2] if len(lanes) > 2 else 1
+        states = [n for n in range(wl.steps) if n % R == 0] * (2 if wl.adjoint else 1)
         entries = sum(per_state[n] + n_particles for n in states) * reps
         launches = len(states) * reps
         bytes_per_launch = (4 * entries + launches * n_particles * (4 + (16 if wl.dtype == "f32" else 32))) / launches
@@ -388,9 +406,14 @@ def main():
     torch.cuda.set_device(dev)
     wl = workloads()[args.workload]()
     host, (x0, v0, r0) = packed_inputs(wl, dev)
-    plan = Plan([s.params() for s in wl.sims], [s.n for s in wl.sims], wl.dtype,
-                tape_depth=wl.ckpt_every if wl.adjoint else 0, device=dev)
-    lanes = autotune.tune(plan, x0, v0, r0) if wl.adjoint else plan.get_tuning()
+    if wl.adjoint:
+        # lanes, list skin and rebuild interval tuned on this state (cached per size bucket)
+        plan = autotune.tune_plan([s.params() for s in wl.sims], [s.n for s in wl.sims], wl.dtype,
+                                  wl.ckpt_every, x0, v0, r0, dev)
+    else:
+        plan = Plan([s.params() for s in wl.sims], [s.n for s in wl.sims], wl.dtype, tape_depth=0, device=dev)
+    lanes = plan.get_tuning()
+    list_skin, list_rebuild = plan.skin, plan.rebuild_every
 
     for _ in range(args.warmup):
         run_job(plan, x0, v0, r0, wl)
@@ -404,10 +427,14 @@ def main():
         return
     per_state = count_pairs(plan, x0, v0, r0, wl)
     K = wl.ckpt_every
-    p_fwd = sum(per_state)
+    # pairs of the timed trajectory itself: calls of one rebuild interval each follow the job's
+    # build schedule; single steps give the per-state split (equal to within a few pairs)
+    p_fwd = count_pairs_schedule(plan, x0, v0, r0, wl)
+    scale = p_fwd / max(sum(per_state), 1)
+    per_state = [c * scale for c in per_state]
     p_adj = p_fwd if wl.adjoint else 0          # adjoint step n runs on forward state n
     recompute_swept = [n for n in range(wl.steps) if wl.adjoint and (n + 1) % K != 0 and n != wl.steps - 1]
-    p_rec = sum(per_state[n] for n in recompute_swept)
+    p_rec = int(round(sum(per_state[n] for n in recompute_swept)))
     plan.poll()
 
     log("workload %s: %d particles, pairs per job %d" % (wl.name, int(sum(s.n for s in wl.sims)), p_fwd + p_adj))
@@ -421,7 +448,8 @@ def main():
     assert np.all(status == 0), "device reported non-finite values or neighbour overflow: %s" % status
     value = (p_fwd + p_adj) * args.steps / elapsed
     dim = wl.sims[0].dim
-    roof = roofline(prof, dom, wl, per_state, args.steps, dim, int(sum(s.n for s in wl.sims)), lanes)
+    roof = roofline(prof, dom, wl, per_state, args.steps, dim, int(sum(s.n for s in wl.sims)),
+                    tuple(lanes) + (list_rebuild,))
 
     log("timed %d jobs: %.3f ms per job" % (args.steps, 1e3 * elapsed / args.steps))
     cpu = None
@@ -458,7 +486,8 @@ def main():
                       "particles": int(sum(s.n for s in wl.sims)), "sim_steps": wl.steps,
                       "ckpt_every": wl.ckpt_every, "adjoint": wl.adjoint, "loss": wl.loss,
                       "pairs_fwd": p_fwd, "pairs_adj": p_adj, "pairs_recompute": p_rec,
-                      "lanes_per_particle": list(lanes)},
+                      "lanes_per_particle": list(lanes), "list_skin": list_skin,
+                      "list_rebuild_every": list_rebuild},
            "roofline": roof, "kernel_ms_per_job": breakdown, "cpu_baseline": cpu, "batched": batched, "serving": served,
            "density_backward": dens}
     print(json.dumps(out), flush=True)

@@ -63,6 +63,9 @@ typedef int32_t sph_status;
 /* per-simulation device status bits, read by sph_poll() */
 #define SPH_FLAG_NONFINITE 1
 #define SPH_FLAG_NEIGHBOR_OVERFLOW 2
+#define SPH_FLAG_SKIN 4 /* with list reuse: a particle moved more than half the skin since its
+                           lists were built, so a pair may be missing; rerun with a larger skin
+                           or a shorter reuse interval */
 
 #define SPH_F32 0
 #define SPH_F64 1
@@ -83,6 +86,10 @@ typedef struct sph_params {
     double alpha;     /* artificial-viscosity coefficient */
     double eps;       /* regulariser in 1/(r^2 + eps H^2) */
     double dt;        /* fixed time step */
+    double skin;      /* neighbour-list skin as a fraction of the support: lists hold the
+                         pairs with r < H (1 + skin) and the sweeps keep those with r < H;
+                         0 = lists of exactly the pairs with r < H.  Needs 2 H (1 + skin) < L.
+                         Cells are sized for the list radius. */
 } sph_params;
 
 /* Device pointers to one packed state in the plan's dtype.  Entries k >= dim
@@ -127,6 +134,21 @@ sph_status sph_plan_info(const sph_plan* plan, int64_t* total_particles, int32_t
  * the same for every setting; only speed changes.  INVALID_ARG otherwise. */
 sph_status sph_set_tuning(sph_plan* plan, int32_t lanes_fwd, int32_t lanes_adj);
 sph_status sph_get_tuning(const sph_plan* plan, int32_t* lanes_fwd, int32_t* lanes_adj);
+
+/* Neighbour-list reuse (Verlet lists; the paper keeps one list for short rollouts,
+ * Sec. 4.1).  With rebuild_every = R > 1 (needs a skin in every simulation's
+ * parameters), a step sorts and rebuilds its lists only when its index within the
+ * call is a multiple of R; the steps in between keep the particle order and the
+ * lists of the last build, and their sweeps keep only the pairs with r < H, so
+ * every step still evaluates exactly the pairs the method defines.  Each sweep
+ * that hands its state to a reusing step checks every particle's displacement
+ * since the build against skin H / 2 and sets SPH_FLAG_SKIN if it is exceeded.
+ * Checkpoint intervals must be multiples of R, so a backward recomputation
+ * follows the forward's build schedule exactly.  Results differ from R = 1 only
+ * by summation order (the lists hold extra entries); they stay deterministic and
+ * independent of the batch.  Host-side setting; default 1.  INVALID_ARG for
+ * R < 1, or R > 1 without a skin. */
+sph_status sph_set_reuse(sph_plan* plan, int32_t rebuild_every);
 
 /* Graph mode (default off; host-side switch, no device work).  When on, every
  * sph_step and sph_rollout_backward call is issued as one executable HIP graph

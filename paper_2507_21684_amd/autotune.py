@@ -1,25 +1,36 @@
-"""Autotuner for the lanes-per-particle setting of the forward and adjoint sweeps.
+"""Autotuner for the plan settings that change speed but not the physics.
 
-The sweeps sum every particle's neighbours as eight canonical partial sums, so the number of
-lanes sharing a particle (2, 4 or 8) changes only the speed, never the result.  The tuner
-times each setting on the caller's own state with the library's HIP-event profiler (a few
-forward steps and one taped backward segment), keeps the fastest setting per sweep, and
-caches it in a JSON file keyed by GPU architecture, dimension, dtype and a power-of-two
-bucket of the plan's particle count.  The cache path is $SPH_TUNING_CACHE, else
-~/.cache/paper_2507_21684_amd/tuning.json.
+* Lanes per particle of the forward and adjoint sweeps (2, 4 or 8).  The sweeps sum every
+  particle's neighbours as eight canonical partial sums, so this changes only the speed, never
+  the result.  `tune` times each setting on the caller's own state with the library's
+  HIP-event profiler (a few forward steps and one taped backward segment) and keeps the
+  fastest per sweep.
+* Neighbour-list skin and rebuild interval (the cell size follows the list radius).  Lists
+  reused for R steps save R - 1 of every R sorts and builds but hold more entries, which the
+  sweeps filter back to r < H.  `tune_plan` builds a plan per candidate (skin, R) with R
+  dividing the checkpoint interval, tunes its lanes, times one checkpoint segment forward and
+  backward, discards candidates whose run raised the displacement flag, and returns the
+  fastest plan.
+
+Choices are cached in a JSON file keyed by GPU architecture, dimension, dtype and a
+power-of-two bucket of the plan's particle count (the cache path is $SPH_TUNING_CACHE, else
+~/.cache/paper_2507_21684_amd/tuning.json).
 """
 from __future__ import annotations
 
 import json
 import math
 import os
-from typing import Dict, Optional, Tuple
+import time
+from typing import Dict, Optional, Sequence, Tuple
 
 import torch
 
 from .lib import Plan
 
 LANE_CHOICES = (2, 4, 8)
+# (skin as a fraction of the support, rebuild interval in steps)
+REUSE_CHOICES = ((0.0, 1), (0.15, 4), (0.25, 8))
 
 
 def cache_path() -> str:
@@ -62,7 +73,9 @@ def _store(table: Dict[str, list]) -> None:
 def measure(plan: Plan, x, v, rho, steps: int = 4, reps: int = 2) -> Dict[int, Tuple[float, float]]:
     """{lanes: (forward-sweep ms per launch, adjoint-sweep ms per launch)} on copies of the state."""
     out = {}
+    R = getattr(plan, "rebuild_every", 1)
     K = min(steps, max(1, plan.tape_depth))
+    K = R * max(1, K // R)          # checkpoint intervals are multiples of the rebuild interval
     for lanes in LANE_CHOICES:
         plan.set_tuning(lanes, lanes)
         best_f, best_a = float("inf"), float("inf")
@@ -110,3 +123,56 @@ def apply_cached(plan: Plan) -> Optional[Tuple[int, int]]:
     lf, la = int(entry[0]), int(entry[1])
     plan.set_tuning(lf, la)
     return lf, la
+
+
+def _segment_seconds(plan: Plan, x, v, rho, K: int, reps: int = 3) -> Tuple[float, int]:
+    """Wall time of K forward steps with a checkpoint plus their taped backward; status bits."""
+    ck = [plan.empty_state()]
+    best = float("inf")
+    plan.poll()
+    for _ in range(reps + 1):
+        xs, vs, rs = x.clone(), v.clone(), rho.clone()
+        gx, gv, gr = torch.zeros_like(x), torch.ones_like(v), torch.zeros_like(rho)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.step(xs, vs, rs, K, ck, K)
+        plan.rollout_backward(ck, K, K, gx, gv, gr)
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    status = int(plan.poll().max()) if plan.nsims else 0
+    return best, status
+
+
+def tune_plan(sims: Sequence[dict], counts: Sequence[int], dtype: str, ckpt_every: int, x, v, rho,
+              device=None, use_cache: bool = True, choices=REUSE_CHOICES) -> Plan:
+    """Plan with the fastest (skin, rebuild interval, lanes) for one checkpoint segment of this state."""
+    K = int(ckpt_every)
+    probe = Plan(sims, counts, dtype, tape_depth=K, device=device)
+    key = cache_key(probe) + ":K%d:reuse" % K
+    del probe
+    table = _load() if use_cache else {}
+    if key in table:
+        skin, R, lf, la = table[key][:4]
+        plan = Plan(sims, counts, dtype, tape_depth=K, device=device, skin=float(skin), rebuild_every=int(R))
+        plan.set_tuning(int(lf), int(la))
+        return plan
+    best, trials = None, {}
+    for skin, R in choices:
+        if K % R:
+            continue
+        plan = Plan(sims, counts, dtype, tape_depth=K, device=device, skin=skin, rebuild_every=R)
+        lf, la = tune(plan, x, v, rho, use_cache=False)
+        secs, status = _segment_seconds(plan, x, v, rho, K)
+        trials["%g/%d" % (skin, R)] = [secs, status, lf, la]
+        if status == 0 and (best is None or secs < best[0]):
+            best = (secs, skin, R, lf, la)
+        del plan
+    if best is None:
+        raise RuntimeError("no list setting ran without device flags: %s" % trials)
+    _, skin, R, lf, la = best
+    if use_cache:
+        table[key] = [skin, R, lf, la, trials]
+        _store(table)
+    plan = Plan(sims, counts, dtype, tape_depth=K, device=device, skin=skin, rebuild_every=R)
+    plan.set_tuning(lf, la)
+    return plan

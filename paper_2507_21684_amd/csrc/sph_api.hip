@@ -78,6 +78,9 @@ struct SlotLayout {
 struct sph_plan {
     int32_t dim = 0, dtype = 0, nsims = 0, width = 0, tape_depth = 0, nslots = 2;
     int32_t lpp_fwd = 4, lpp_adj = 4;
+    bool filter = false;      // some simulation has a skin: sweeps keep only pairs with r < H
+    int32_t reuse = 1;        // a step rebuilds the cell list and the lists every `reuse` steps
+    std::vector<int> list_of; // tape slot -> slot whose neighbour lists it uses
     int64_t N = 0;
     int64_t ncell = 0, nblk = 0;
     std::vector<sph_params> prm;
@@ -87,7 +90,7 @@ struct sph_plan {
     // workspace layout (byte offsets)
     size_t o_simc = 0, o_psim = 0, o_cell_sim = 0, o_blk_coord = 0, o_blk_rank = 0;
     size_t o_cell_count = 0, o_cell_start = 0, o_part = 0, o_cell_of = 0, o_slot_of = 0, o_tmp = 0;
-    size_t o_SB = 0, o_jdA = 0, o_jdB = 0, o_status = 0, o_part64 = 0, o_pairs = 0, o_ticket = 0;
+    size_t o_SB = 0, o_jdA = 0, o_jdB = 0, o_status = 0, o_part64 = 0, o_pairs = 0, o_ticket = 0, o_uref = 0;
     std::vector<SlotLayout> slot;
     int64_t nparts = 0, nparts64 = 0;
     size_t bytes = 0;
@@ -193,6 +196,12 @@ void fill_simconst(const sph_plan* P, std::vector<unsigned char>& out)
         c.invL = T(1) / c.L;
         c.H = (T)q.support;
         c.H2 = c.H * c.H;
+        {
+            const T HL = (T)(q.support * (1.0 + q.skin));
+            c.HL2 = HL * HL;
+            const double half = 0.5 * q.skin * q.support;
+            c.disp2 = (T)(half * half);
+        }
         c.invH = (T)(1.0 / q.support);
         c.cinv = (T)((double)h.nc / q.box);
         c.m = (T)q.mass;
@@ -298,79 +307,98 @@ sph_status sort_into(sph_plan* P, StatePtrs<T, D> src, const int32_t* orig_in, i
     LAUNCH_CHECK("scatter");
     k_order_gather<T, D><<<g, 256, 0, st>>>(N, tmp, cell_of, cell_start, orig_in, src, ws_state<T, D>(P, L.SA),
                                             orig_out, wsp<vec4_t<T>>(P, L.jd0), wsp<vec4_t<T>>(P, L.jd1), psim,
-                                            simc);
+                                            simc, P->filter ? wsp<vec4_t<T>>(P, P->o_uref) : nullptr);
     LAUNCH_CHECK("order_gather");
     return SPH_OK;
 }
 
 // Neighbour lists of the state sorted into `slot` (needs the cell starts of that sort, so it
 // runs before the next sort).
+// Lists reach the support plus the skin, or exactly the support (`exact`, for the export).
+// With a skin the pairs are counted by the forward sweeps, which filter them; without one,
+// here.
 template <typename T, int D>
-sph_status build_lists(sph_plan* P, int slot, hipStream_t st)
+sph_status build_lists(sph_plan* P, int slot, hipStream_t st, bool exact = false)
 {
     if (P->N == 0 || P->ncell == 0) return SPH_OK;
     const SlotLayout& L = P->slot[slot];
+    P->list_of[slot] = slot;
     ProfScope prof(P, st, SPH_KERN_BUILD);
     k_build_list<T, D><<<(unsigned)P->ncell, 64, 0, st>>>(
         wsp<int32_t>(P, P->o_cell_sim), wsp<int32_t>(P, P->o_blk_coord), wsp<int32_t>(P, P->o_blk_rank),
         wsp<SimConst<T>>(P, P->o_simc),
         wsp<int32_t>(P, P->o_cell_start), wsp<vec4_t<T>>(P, L.jd0), P->width,
         wsp<int32_t>(P, L.nbr), wsp<int32_t>(P, L.cnt), wsp<int32_t>(P, P->o_status),
-        wsp<unsigned long long>(P, P->o_pairs));
+        P->filter ? nullptr : wsp<unsigned long long>(P, P->o_pairs), exact ? 1 : 0);
     LAUNCH_CHECK("build_list");
     return SPH_OK;
 }
 
 template <typename T, int D, int MODE, int LPP>
-void launch_sweep(sph_plan* P, const SlotLayout& L, T* drho, T* acc, T* rhosum, NextCells next, hipStream_t st)
+void launch_sweep(sph_plan* P, const SlotLayout& L, const SlotLayout& LL, StatePtrs<T, D> dst, T* drho, T* acc,
+                  T* rhosum, NextCells next, NextSlot<T> ns, hipStream_t st)
 {
     const int64_t lanes = P->N * LPP;
     k_sweep<T, D, MODE, LPP><<<grid_for(lanes, 256), 256, 0, st>>>(
-        P->N, P->width, wsp<int32_t>(P, L.nbr), wsp<int32_t>(P, L.cnt), wsp<vec4_t<T>>(P, L.jd0),
-        wsp<vec4_t<T>>(P, L.jd1), ws_state<T, D>(P, L.SA), ws_state<T, D>(P, P->o_SB), wsp<int32_t>(P, L.orig), drho,
-        acc, rhosum, wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc), wsp<int32_t>(P, P->o_status), next);
+        P->N, P->width, wsp<int32_t>(P, LL.nbr), wsp<int32_t>(P, LL.cnt), wsp<vec4_t<T>>(P, L.jd0),
+        wsp<vec4_t<T>>(P, L.jd1), ws_state<T, D>(P, L.SA), dst, wsp<int32_t>(P, L.orig), drho, acc, rhosum,
+        wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc), wsp<int32_t>(P, P->o_status), next, ns,
+        P->filter ? 1 : 0, P->filter ? wsp<unsigned long long>(P, P->o_pairs) : nullptr);
 }
 
-// Forward sweep over the state in `slot`: MODE step integrates into SB (same sorted order),
-// MODE rhs writes the derivatives to the caller's arrays in original order.  With
-// assign_next (MODE step only) the sweep also does the cell assignment of the next sort.
+// Forward sweep over the state in `slot` with the lists of slot list_of[slot].  MODE step
+// integrates into SB (same sorted order), or, with next_slot >= 0 (the next step reuses the
+// lists), straight into that slot with its packed records; MODE rhs writes the derivatives
+// to the caller's arrays in original order.  With assign_next (MODE step into SB) the sweep
+// also does the cell assignment of the next sort.
 template <typename T, int D, int MODE>
-sph_status sweep(sph_plan* P, int slot, T* drho, T* acc, T* rhosum, hipStream_t st, bool assign_next = false)
+sph_status sweep(sph_plan* P, int slot, T* drho, T* acc, T* rhosum, hipStream_t st, bool assign_next = false,
+                 int next_slot = -1)
 {
     if (P->N == 0) return SPH_OK;
     const SlotLayout& L = P->slot[slot];
+    const SlotLayout& LL = P->slot[P->list_of[slot]];
     NextCells next{wsp<int32_t>(P, P->o_blk_rank), nullptr, wsp<int32_t>(P, P->o_cell_of),
                    wsp<int32_t>(P, P->o_slot_of)};
     if (assign_next) next.cell_count = wsp<int32_t>(P, P->o_cell_count);
+    NextSlot<T> ns{nullptr, nullptr, nullptr, nullptr};
+    StatePtrs<T, D> dst = ws_state<T, D>(P, P->o_SB);
+    if (next_slot >= 0) {
+        const SlotLayout& N2 = P->slot[next_slot];
+        dst = ws_state<T, D>(P, N2.SA);
+        ns = NextSlot<T>{wsp<vec4_t<T>>(P, N2.jd0), wsp<vec4_t<T>>(P, N2.jd1), wsp<int32_t>(P, N2.orig),
+                         wsp<vec4_t<T>>(P, P->o_uref)};
+    }
     ProfScope prof(P, st, SPH_KERN_SWEEP);
     switch (P->lpp_fwd) {
-    case 2: launch_sweep<T, D, MODE, 2>(P, L, drho, acc, rhosum, next, st); break;
-    case 8: launch_sweep<T, D, MODE, 8>(P, L, drho, acc, rhosum, next, st); break;
-    default: launch_sweep<T, D, MODE, 4>(P, L, drho, acc, rhosum, next, st); break;
+    case 2: launch_sweep<T, D, MODE, 2>(P, L, LL, dst, drho, acc, rhosum, next, ns, st); break;
+    case 8: launch_sweep<T, D, MODE, 8>(P, L, LL, dst, drho, acc, rhosum, next, ns, st); break;
+    default: launch_sweep<T, D, MODE, 4>(P, L, LL, dst, drho, acc, rhosum, next, ns, st); break;
     }
     LAUNCH_CHECK("sweep");
     return SPH_OK;
 }
 
+// Back to original order: the state `src` (sorted like `slot`) into dst.
 template <typename T, int D>
-sph_status unsort_SB(sph_plan* P, int slot, StatePtrs<T, D> dst, hipStream_t st)
+sph_status unsort_from(sph_plan* P, StatePtrs<T, D> src, int slot, StatePtrs<T, D> dst, hipStream_t st)
 {
     if (P->N == 0) return SPH_OK;
     ProfScope prof(P, st, SPH_KERN_OTHER);
-    k_unsort<T, D><<<grid_for(P->N, 256), 256, 0, st>>>(P->N, ws_state<T, D>(P, P->o_SB),
-                                                        wsp<int32_t>(P, P->slot[slot].orig), dst);
+    k_unsort<T, D><<<grid_for(P->N, 256), 256, 0, st>>>(P->N, src, wsp<int32_t>(P, P->slot[slot].orig), dst);
     LAUNCH_CHECK("unsort");
     return SPH_OK;
 }
 
 template <typename T, int D, int LPP>
-void launch_adj(sph_plan* P, const SlotLayout& L, StatePtrs<T, D> cot, hipStream_t st)
+void launch_adj(sph_plan* P, const SlotLayout& L, const SlotLayout& LL, StatePtrs<T, D> cot, hipStream_t st)
 {
     const int64_t lanes = P->N * LPP;
     k_adj_sweep<T, D, LPP><<<grid_for(lanes, 256), 256, 0, st>>>(
-        P->N, P->width, wsp<int32_t>(P, L.nbr), wsp<int32_t>(P, L.cnt), wsp<vec4_t<T>>(P, L.jd0),
+        P->N, P->width, wsp<int32_t>(P, LL.nbr), wsp<int32_t>(P, LL.cnt), wsp<vec4_t<T>>(P, L.jd0),
         wsp<vec4_t<T>>(P, L.jd1), wsp<vec4_t<T>>(P, P->o_jdA), wsp<vec4_t<T>>(P, P->o_jdB), wsp<int32_t>(P, L.orig),
-        cot, wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc), wsp<int32_t>(P, P->o_status));
+        cot, wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc), wsp<int32_t>(P, P->o_status),
+        P->filter ? 1 : 0);
 }
 
 // Adjoint of the step that starts from the state in `slot` (sorted with its lists built).
@@ -387,10 +415,11 @@ sph_status adjoint(sph_plan* P, int slot, StatePtrs<T, D> cot, hipStream_t st)
         LAUNCH_CHECK("adj_prologue");
     }
     ProfScope prof(P, st, SPH_KERN_ADJOINT);
+    const SlotLayout& LL = P->slot[P->list_of[slot]];
     switch (P->lpp_adj) {
-    case 2: launch_adj<T, D, 2>(P, L, cot, st); break;
-    case 8: launch_adj<T, D, 8>(P, L, cot, st); break;
-    default: launch_adj<T, D, 4>(P, L, cot, st); break;
+    case 2: launch_adj<T, D, 2>(P, L, LL, cot, st); break;
+    case 8: launch_adj<T, D, 8>(P, L, LL, cot, st); break;
+    default: launch_adj<T, D, 4>(P, L, LL, cot, st); break;
     }
     LAUNCH_CHECK("adj_sweep");
     return SPH_OK;
@@ -445,27 +474,45 @@ sph_status do_rhs(sph_plan* P, const sph_state* s, void* drho, void* acc, void* 
 }
 
 // nsteps forward steps from `src` (original order).  Without a tape, steps alternate between
-// slots 0 and 1; with a tape, step t keeps its sorted state and lists in slot t.  The sweep of
-// the last step is skipped when `last_sweep` is false (a recomputation needs only the states
-// the adjoint steps start from).  *last_slot receives the slot of the last step.
+// slots 0 and 1; with a tape, step t keeps its sorted state in slot t.  Step t sorts and
+// builds lists when t is a multiple of the plan's reuse interval; otherwise it uses the lists
+// of the last build, its state already written into its slot by the previous sweep (same
+// particle order).  The sweep of the last step is skipped when `last_sweep` is false (a
+// recomputation needs only the states the adjoint steps start from).  *last_slot receives the
+// slot of the last step.
 template <typename T, int D>
 sph_status run_steps(sph_plan* P, StatePtrs<T, D> src, int32_t nsteps, bool tape, bool last_sweep,
                      const sph_state* ckpt, int32_t every, int* last_slot, hipStream_t st)
 {
-    int slot = 0;
+    const int R = P->reuse;
+    int slot = 0, list_slot = 0;
     for (int32_t t = 0; t < nsteps; ++t) {
-        const int next = tape ? t : (t & 1);
-        if (t == 0) RC_TRY((sort_into<T, D>(P, src, nullptr, next, st)));
-        else
-            RC_TRY((sort_into<T, D>(P, ws_state<T, D>(P, P->o_SB), wsp<int32_t>(P, P->slot[slot].orig), next, st,
-                                    true)));
-        slot = next;
-        RC_TRY((build_lists<T, D>(P, slot, st)));
-        // the sweep assigns cells for the next step's sort whenever one follows
-        if (t + 1 < nsteps || last_sweep)
-            RC_TRY((sweep<T, D, kModeStep>(P, slot, nullptr, nullptr, nullptr, st, t + 1 < nsteps)));
-        if (ckpt && (t + 1) % every == 0 && t + 1 < nsteps)
-            RC_TRY((unsort_SB<T, D>(P, slot, user_state<T, D>(&ckpt[(t + 1) / every]), st)));
+        const int cur = tape ? t : (t & 1);
+        if (t % R == 0) {
+            if (t == 0) RC_TRY((sort_into<T, D>(P, src, nullptr, cur, st)));
+            else
+                RC_TRY((sort_into<T, D>(P, ws_state<T, D>(P, P->o_SB), wsp<int32_t>(P, P->slot[slot].orig), cur, st,
+                                        true)));
+            RC_TRY((build_lists<T, D>(P, cur, st)));
+            list_slot = cur;
+        }
+        P->list_of[cur] = list_slot;
+        slot = cur;
+        const bool more = t + 1 < nsteps;
+        const bool reuse_next = more && (t + 1) % R != 0;
+        const int nxt = tape ? t + 1 : ((t + 1) & 1);
+        if (more || last_sweep) {
+            if (reuse_next) RC_TRY((sweep<T, D, kModeStep>(P, cur, nullptr, nullptr, nullptr, st, false, nxt)));
+            else RC_TRY((sweep<T, D, kModeStep>(P, cur, nullptr, nullptr, nullptr, st, more)));
+        }
+        if (ckpt && (t + 1) % every == 0 && more) {
+            if (reuse_next)
+                RC_TRY((unsort_from<T, D>(P, ws_state<T, D>(P, P->slot[nxt].SA), nxt,
+                                          user_state<T, D>(&ckpt[(t + 1) / every]), st)));
+            else
+                RC_TRY((unsort_from<T, D>(P, ws_state<T, D>(P, P->o_SB), cur, user_state<T, D>(&ckpt[(t + 1) / every]),
+                                          st)));
+        }
     }
     *last_slot = slot;
     return SPH_OK;
@@ -479,7 +526,7 @@ sph_status do_step(sph_plan* P, sph_state* s, int32_t nsteps, const sph_state* c
     if (ckpt) RC_TRY((copy_state<T, D>(P, user_state<T, D>(&ckpt[0]), user, st)));
     int last = 0;
     RC_TRY((run_steps<T, D>(P, user, nsteps, false, true, ckpt, every, &last, st)));
-    return unsort_SB<T, D>(P, last, user, st);
+    return unsort_from<T, D>(P, ws_state<T, D>(P, P->o_SB), last, user, st);
 }
 
 template <typename T, int D>
@@ -520,6 +567,7 @@ sph_status run_graphed(sph_plan* P, std::vector<uintptr_t> key, hipStream_t st, 
     if (!P->graphs || P->prof) return issue(st);
     key.push_back((uintptr_t)P->lpp_fwd);
     key.push_back((uintptr_t)P->lpp_adj);
+    key.push_back((uintptr_t)P->reuse);
     for (auto& g : P->gcache) {
         if (g.key == key) {
             g.used = ++P->gclock;
@@ -572,7 +620,8 @@ void launch_density_adj(sph_plan* P, const SlotLayout& L, const T* gs, T* xbar, 
     const int64_t lanes = P->N * LPP;
     k_density_adj<T, D, LPP><<<grid_for(lanes, 256), 256, 0, st>>>(
         P->N, P->width, wsp<int32_t>(P, L.nbr), wsp<int32_t>(P, L.cnt), wsp<vec4_t<T>>(P, L.jd0), gs,
-        wsp<int32_t>(P, L.orig), wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc), xbar);
+        wsp<int32_t>(P, L.orig), wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc), xbar,
+        P->filter ? 1 : 0);
 }
 
 // Summation-density VJP of the state s: sort, lists, the cotangent gathered into sorted
@@ -602,7 +651,7 @@ sph_status do_neighbors(sph_plan* P, const sph_state* s, int64_t* offsets, int32
                         int64_t* total, hipStream_t st)
 {
     RC_TRY((sort_into<T, D>(P, user_state<T, D>(s), nullptr, 0, st)));
-    RC_TRY((build_lists<T, D>(P, 0, st)));
+    RC_TRY((build_lists<T, D>(P, 0, st, true)));
     const int64_t N = P->N;
     const SlotLayout& L = P->slot[0];
     const int32_t* orig = wsp<int32_t>(P, L.orig);
@@ -675,6 +724,13 @@ sph_status sph_plan_create(const sph_params* sims, int32_t nsims, const int64_t*
             delete P;
             return fail(SPH_ERR_INVALID_ARG, "negative particle count");
         }
+        const double HL = q.support * (1.0 + q.skin);  // list radius
+        if (!(q.skin >= 0) || !std::isfinite(q.skin) || !(2.0 * HL < q.box)) {
+            std::snprintf(buf, sizeof buf, "simulation %d: need skin >= 0 and 2 H (1 + skin) < L", s);
+            delete P;
+            return fail(SPH_ERR_INVALID_ARG, buf);
+        }
+        if (q.skin > 0) P->filter = true;
         if (!(q.box > 0) || !(q.support > 0) || !(2.0 * q.support < q.box) || !(q.mass > 0) || !(q.rho0 > 0) ||
             !(q.c0 > 0) || !(q.eps > 0) || !std::isfinite(q.dt) || !std::isfinite(q.delta) ||
             !std::isfinite(q.alpha) || !std::isfinite(q.box)) {
@@ -685,8 +741,8 @@ sph_status sph_plan_create(const sph_params* sims, int32_t nsims, const int64_t*
         SimHost h{};
         h.p0 = p0;
         h.n = counts[s];
-        const double nc2 = std::floor(2.0 * q.box / (q.support * kCellMargin));
-        const double nc1 = std::floor(q.box / (q.support * kCellMargin));
+        const double nc2 = std::floor(2.0 * q.box / (HL * kCellMargin));
+        const double nc1 = std::floor(q.box / (HL * kCellMargin));
         if (nc2 >= 5) {
             h.sub = 2;
             h.nc = (int)std::min(nc2, 1e6);
@@ -720,7 +776,7 @@ sph_status sph_plan_create(const sph_params* sims, int32_t nsims, const int64_t*
         P->sim.push_back(h);
         p0 += counts[s];
         const double dxd = q.mass / q.rho0;
-        const double vol = (d == 2) ? M_PI * q.support * q.support : 4.0 / 3.0 * M_PI * std::pow(q.support, 3);
+        const double vol = (d == 2) ? M_PI * HL * HL : 4.0 / 3.0 * M_PI * std::pow(HL, 3);
         nh_max = std::max(nh_max, vol / dxd);
     }
     // the sweeps gather per-particle records with 32-bit byte offsets
@@ -793,7 +849,9 @@ sph_status sph_plan_create(const sph_params* sims, int32_t nsims, const int64_t*
     P->o_part64 = take(8 * ((size_t)P->nparts64 + 1) + 8 * (N + 1));
     P->o_pairs = take(8 * (size_t)kPairSlots * kPairStride);
     P->o_ticket = take(4);
+    P->o_uref = take(V4 * N);
     P->slot.resize((size_t)P->nslots);
+    P->list_of.assign((size_t)P->nslots, 0);
     for (int k = 0; k < P->nslots; ++k) {
         SlotLayout& L = P->slot[k];
         L.SA = take(T * N * (2 * d + 1));
@@ -833,6 +891,16 @@ sph_status sph_set_tuning(sph_plan* plan, int32_t lanes_fwd, int32_t lanes_adj)
     if (!ok(lanes_fwd) || !ok(lanes_adj)) return fail(SPH_ERR_INVALID_ARG, "lanes per particle must be 2, 4 or 8");
     plan->lpp_fwd = lanes_fwd;
     plan->lpp_adj = lanes_adj;
+    return SPH_OK;
+}
+
+sph_status sph_set_reuse(sph_plan* plan, int32_t rebuild_every)
+{
+    if (!plan) return fail(SPH_ERR_INVALID_ARG, "plan is null");
+    if (rebuild_every < 1) return fail(SPH_ERR_INVALID_ARG, "rebuild_every must be >= 1");
+    if (rebuild_every > 1 && !plan->filter)
+        return fail(SPH_ERR_INVALID_ARG, "reusing lists needs a skin (sph_params.skin > 0)");
+    plan->reuse = rebuild_every;
     return SPH_OK;
 }
 
@@ -928,6 +996,8 @@ sph_status sph_step(sph_plan* P, sph_state* s, int32_t nsteps, const sph_state* 
     if (nsteps < 0) return fail(SPH_ERR_INVALID_ARG, "nsteps < 0");
     if (ckpt) {
         if (ckpt_every <= 0) return fail(SPH_ERR_INVALID_ARG, "ckpt_every must be > 0");
+        if (ckpt_every % P->reuse != 0)
+            return fail(SPH_ERR_INVALID_ARG, "ckpt_every must be a multiple of the list reuse interval");
         const int32_t nslots = (nsteps + ckpt_every - 1) / ckpt_every;
         for (int32_t k = 0; k < nslots; ++k) RC_TRY(check_state(P, &ckpt[k], "checkpoint slot"));
     }
@@ -970,6 +1040,8 @@ sph_status sph_rollout_backward(sph_plan* P, const sph_state* ckpt, int32_t nste
     if (nsteps > 0 && !ckpt) return fail(SPH_ERR_INVALID_ARG, "checkpoints are null");
     if (std::min(ckpt_every, nsteps) > P->tape_depth)
         return fail(SPH_ERR_CAPACITY, "plan tape_depth is smaller than the checkpoint interval");
+    if (ckpt_every % P->reuse != 0)
+        return fail(SPH_ERR_INVALID_ARG, "ckpt_every must be a multiple of the list reuse interval");
     const int32_t nseg = nsteps > 0 ? (nsteps + ckpt_every - 1) / ckpt_every : 0;
     for (int32_t k = 0; k < nseg; ++k) RC_TRY(check_state(P, &ckpt[k], "checkpoint slot"));
     std::vector<uintptr_t> key = {2u, (uintptr_t)nsteps, (uintptr_t)ckpt_every};

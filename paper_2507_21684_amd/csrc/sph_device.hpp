@@ -22,6 +22,7 @@ namespace sph {
 
 constexpr int kFlagNonfinite = 1;
 constexpr int kFlagOverflow = 2;
+constexpr int kFlagSkin = 4;  // a particle moved more than half the skin since its list was built
 
 template <typename T> struct Vec4;
 template <> struct Vec4<float> { using type = float4; };
@@ -41,6 +42,8 @@ struct SimConst {
     T cA;       // alpha H c0 rho0
     T cD;       // 2 delta H c0
     T Bt;       // rho0 c0^2 / 7
+    T HL2;      // (H (1 + skin))^2: list radius squared (= H2 without a skin)
+    T disp2;    // (skin H / 2)^2: largest squared displacement a reused list allows
     int64_t p0, n;      // packed particle range
     int32_t cell0;      // first global cell slot
     int32_t blk0;       // first global cell block
@@ -456,7 +459,8 @@ __global__ __launch_bounds__(256) void k_order_gather(int64_t N, const int32_t* 
                                                       StatePtrs<T, DIM> dst, int32_t* __restrict__ orig_out,
                                                       vec4_t<T>* __restrict__ jd0, vec4_t<T>* __restrict__ jd1,
                                                       const int32_t* __restrict__ psim,
-                                                      const SimConst<T>* __restrict__ sims)
+                                                      const SimConst<T>* __restrict__ sims,
+                                                      vec4_t<T>* __restrict__ uref)
 {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= N) return;
@@ -496,6 +500,7 @@ __global__ __launch_bounds__(256) void k_order_gather(int64_t N, const int32_t* 
     }
     jd0[d] = a;
     jd1[d] = b;
+    if (uref) uref[d] = a;  // the positions the lists were built from (list reuse)
 }
 
 template <typename T, int DIM>
@@ -533,7 +538,7 @@ __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ c
                                                    const vec4_t<T>* __restrict__ jd0, int32_t width,
                                                    int32_t* __restrict__ nbr, int32_t* __restrict__ nbr_count,
                                                    int32_t* __restrict__ status,
-                                                   unsigned long long* __restrict__ pair_counter)
+                                                   unsigned long long* __restrict__ pair_counter, int exact)
 {
     __shared__ vec4_t<T> pu[64];
     __shared__ int32_t uc_first[128];
@@ -548,6 +553,7 @@ __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ c
     if (n == 0) return;
     const SimConst<T> S = sims[s];
     const int ncu = S.ncu;
+    const T R2 = exact ? S.H2 : S.HL2;  // list radius: the support, or the support plus the skin
     // the cell's coordinates from its block and its place inside the block
     int cc[3];
     {
@@ -619,7 +625,7 @@ __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ c
             for (int p = 0; p < nb; ++p) {
                 T ui[3] = {T(0), T(0), T(0)};
                 unpack_u<T, DIM>(pu[p], ui);
-                const bool ok = valid && dist2_exact<T, DIM>(ui, uj, sh) < S.H2;
+                const bool ok = valid && dist2_exact<T, DIM>(ui, uj, sh) < R2;
                 const unsigned long long mask = __ballot(ok);
                 const int base = __builtin_amdgcn_readlane(cnt, p);
                 const int pos = base + __popcll(mask & below);
@@ -636,7 +642,8 @@ __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ c
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) pairs_acc += __shfl_xor(pairs_acc, o, 64);
-    if (lane == 0) atomicAdd(&pair_counter[(gc & (kPairSlots - 1)) * kPairStride], (unsigned long long)pairs_acc);
+    if (lane == 0 && pair_counter)
+        atomicAdd(&pair_counter[(gc & (kPairSlots - 1)) * kPairStride], (unsigned long long)pairs_acc);
 }
 
 // ---------------------------------------------------------------- canonical pair sums
@@ -684,7 +691,38 @@ template <> __device__ __forceinline__ float fast_sqrt<float>(float x) { return 
 // Per-simulation constants the pair loops use, held in registers.
 template <typename T>
 struct PairConst {
-    T L, invL, invH, kG, kH, epsH2, cA, cD;
+    T L, invL, invH, kG, kH, epsH2, cA, cD, H2;
+};
+
+// Squared distance of a listed pair with the arithmetic of the neighbour predicate (per
+// component the minimum image, then the sum of squares in component order, no contraction),
+// so that a list with a skin can be filtered to exactly the pairs with r^2 < H^2.
+template <typename T, int DIM>
+__device__ __forceinline__ T r2_exact(const T* ui, const vec4_t<T>& a, T L, T invL)
+{
+#pragma clang fp contract(off)
+    const T uj[3] = {a.x, a.y, a.z};
+    T r2 = T(0);
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        T d = ui[k] - uj[k];
+        d = d - L * rint(d * invL);
+        T dd = d * d;
+        r2 = r2 + dd;
+    }
+    return r2;
+}
+
+// What the sweep that finishes a step does for the next step when that step reuses the lists
+// (null jd0: the next step sorts and rebuilds): the next state goes straight into the next
+// tape slot in the same particle order, with its packed records and original indices, and each
+// particle's displacement since the list build is checked against half the skin.
+template <typename T>
+struct NextSlot {
+    vec4_t<T>* jd0;
+    vec4_t<T>* jd1;
+    int32_t* orig;
+    const vec4_t<T>* uref;
 };
 
 template <typename T>
@@ -699,6 +737,7 @@ __device__ __forceinline__ PairConst<T> pair_const(const SimConst<T>& S)
     c.epsH2 = S.epsH2;
     c.cA = S.cA;
     c.cD = S.cD;
+    c.H2 = S.H2;
     return c;
 }
 
@@ -788,7 +827,8 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
                                                T* __restrict__ acc_out, T* __restrict__ rhosum_out,
                                                const int32_t* __restrict__ psim,
                                                const SimConst<T>* __restrict__ sims, int32_t* __restrict__ status,
-                                               NextCells next)
+                                               NextCells next, NextSlot<T> ns, int filter,
+                                               unsigned long long* __restrict__ pair_counter)
 {
     constexpr int NQ = kLeaves / LPP;
     constexpr int U = kPairsInFlight;
@@ -796,7 +836,8 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
     const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int64_t i = t / LPP;
     const int r = (int)(t - i * LPP);
-    if (i >= N) return;
+    int accepted = 0;  // pairs j != i kept by the filter (lists with a skin)
+    if (i < N) {
     const int s = psim[i];
     const SimConst<T>& S = sims[s];
     const PairConst<T> c = pair_const(S);
@@ -829,8 +870,14 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
             nb[u].rho = (DIM == 3) ? ldo(cur.rho, j) : T(0);
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (m0 + u < mcount) fwd_pair<T, DIM, MODE == kModeRhs>(c, ui, vi, rhoi, pi, nb[u], acc[u % NQ]);
+        for (int u = 0; u < U; ++u) {
+            if (m0 + u >= mcount) continue;
+            if (filter) {
+                if (!(r2_exact<T, DIM>(ui, nb[u].a, c.L, c.invL) < c.H2)) continue;
+                accepted += (jj[u] != (int)i) ? 1 : 0;
+            }
+            fwd_pair<T, DIM, MODE == kModeRhs>(c, ui, vi, rhoi, pi, nb[u], acc[u % NQ]);
+        }
     }
     T ax[3] = {0, 0, 0};
     T tmp[NQ];
@@ -852,7 +899,7 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
         for (int q = 0; q < NQ; ++q) tmp[q] = acc[q].rs;
         rs = combine_leaves<LPP>(tmp);
     }
-    if (r != 0) return;
+    if (r == 0) {
     const T invrho = T(1) / rhoi;
     T a[3];
 #pragma unroll
@@ -862,21 +909,53 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
         bool bad = !isfinite(drho);
         const T dt = S.dt;
         int cc[3] = {0, 0, 0};
+        T xn[3] = {0, 0, 0}, vn[3] = {0, 0, 0};
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
-            const T vn = vi[k] + dt * a[k];
-            const T xn = cur.x[k][i] + dt * vn;
-            dst.v[k][i] = vn;
-            dst.x[k][i] = xn;
-            bad = bad || !isfinite(vn) || !isfinite(xn);
-            cc[k] = cell_coord(wrap_pos(isfinite(xn) ? xn : T(0), S.L, S.invL), S.cinv, S.nc);
+            vn[k] = vi[k] + dt * a[k];
+            xn[k] = cur.x[k][i] + dt * vn[k];
+            dst.v[k][i] = vn[k];
+            dst.x[k][i] = xn[k];
+            bad = bad || !isfinite(vn[k]) || !isfinite(xn[k]);
+            cc[k] = cell_coord(wrap_pos(isfinite(xn[k]) ? xn[k] : T(0), S.L, S.invL), S.cinv, S.nc);
         }
-        dst.rho[i] = rhoi + dt * drho;
+        const T rhon = rhoi + dt * drho;
+        dst.rho[i] = rhon;
         if (bad) atomicOr(&status[s], kFlagNonfinite);
         if (next.cell_count) {
             const int gcell = global_cell<T, DIM>(S, next.blk_rank, cc[0], cc[1], cc[2]);
             next.cell_of[i] = gcell;
             next.slot_of[i] = atomicAdd(&next.cell_count[gcell], 1);
+        }
+        if (ns.jd0) {
+            // packed records of the next step, as the sort would write them
+            T u[3] = {0, 0, 0};
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) u[k] = wrap_pos(isfinite(xn[k]) ? xn[k] : T(0), S.L, S.invL);
+            const T V = S.m / rhon;
+            const T pV = tait(S, rhon) * V;
+            vec4_t<T> pa, pb;
+            if (DIM == 3) {
+                pa.x = u[0]; pa.y = u[1]; pa.z = u[2]; pa.w = V;
+                pb.x = vn[0]; pb.y = vn[1]; pb.z = vn[2]; pb.w = pV;
+            } else {
+                pa.x = u[0]; pa.y = u[1]; pa.z = V; pa.w = pV;
+                pb.x = vn[0]; pb.y = vn[1]; pb.z = rhon; pb.w = T(0);
+            }
+            ns.jd0[i] = pa;
+            ns.jd1[i] = pb;
+            ns.orig[i] = orig[i];
+            // displacement since the lists were built (minimum image)
+            const vec4_t<T> ref = ns.uref[i];
+            const T rr[3] = {ref.x, ref.y, ref.z};
+            T d2 = T(0);
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                T d = u[k] - rr[k];
+                d -= S.L * rint(d * S.invL);
+                d2 += d * d;
+            }
+            if (!(d2 <= S.disp2)) atomicOr(&status[s], kFlagSkin);
         }
     } else {
         const int o = orig[i];
@@ -884,6 +963,16 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
 #pragma unroll
         for (int k = 0; k < DIM; ++k) acc_out[(int64_t)k * N + o] = a[k];
         if (rhosum_out) rhosum_out[o] = S.m * S.kW * rs;
+    }
+    }
+    }
+    if (pair_counter) {
+        // wave total of the filtered pairs, one integer atomic per wavefront
+        int w = accepted;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o, 64);
+        if ((threadIdx.x & 63) == 0 && w)
+            atomicAdd(&pair_counter[(blockIdx.x & (kPairSlots - 1)) * kPairStride], (unsigned long long)w);
     }
 }
 
@@ -909,7 +998,8 @@ __global__ __launch_bounds__(256) void k_density_adj(int64_t N, int32_t width, c
                                                      const vec4_t<T>* __restrict__ jd0, const T* __restrict__ gs,
                                                      const int32_t* __restrict__ orig,
                                                      const int32_t* __restrict__ psim,
-                                                     const SimConst<T>* __restrict__ sims, T* __restrict__ xbar)
+                                                     const SimConst<T>* __restrict__ sims, T* __restrict__ xbar,
+                                                     int filter)
 {
     constexpr int NQ = kLeaves / LPP;
     constexpr int U = kPairsInFlight;
@@ -944,6 +1034,7 @@ __global__ __launch_bounds__(256) void k_density_adj(int64_t N, int32_t width, c
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (m0 + u >= mcount) continue;
+            if (filter && !(r2_exact<T, DIM>(ui, a[u], c.L, c.invL) < c.H2)) continue;
             T uj[3] = {0, 0, 0}, d[3] = {0, 0, 0};
             unpack_u<T, DIM>(a[u], uj);
             T r2 = 0;
@@ -1122,7 +1213,8 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
                                                    const vec4_t<T>* __restrict__ jdB,
                                                    const int32_t* __restrict__ orig, StatePtrs<T, DIM> cot,
                                                    const int32_t* __restrict__ psim,
-                                                   const SimConst<T>* __restrict__ sims, int32_t* __restrict__ status)
+                                                   const SimConst<T>* __restrict__ sims, int32_t* __restrict__ status,
+                                                   int filter)
 {
     constexpr int NQ = kLeaves / LPP;
     constexpr int U = kPairsInFlight;
@@ -1175,8 +1267,11 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
             nb[u].B = ldo(jdB, j);
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (m0 + u < mcount) adj_pair<T, DIM>(c, uk, vk, ak, rbk, Vk, rhok, pk, irk, dpk, nb[u], acc[u % NQ]);
+        for (int u = 0; u < U; ++u) {
+            if (m0 + u >= mcount) continue;
+            if (filter && !(r2_exact<T, DIM>(uk, nb[u].a, c.L, c.invL) < c.H2)) continue;
+            adj_pair<T, DIM>(c, uk, vk, ak, rbk, Vk, rhok, pk, irk, dpk, nb[u], acc[u % NQ]);
+        }
     }
     T gx[3] = {0, 0, 0}, gv[3] = {0, 0, 0};
     T tmp[NQ];

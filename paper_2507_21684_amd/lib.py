@@ -22,6 +22,7 @@ SPH_F32 = 0
 SPH_F64 = 1
 FLAG_NONFINITE = 1
 FLAG_NEIGHBOR_OVERFLOW = 2
+FLAG_SKIN = 4
 ERR_NAMES = {-1: "INVALID_ARG", -2: "TOO_FEW_CELLS", -3: "CAPACITY", -4: "NONFINITE", -5: "DEVICE",
              -6: "UNSUPPORTED", -7: "STATE"}
 
@@ -36,7 +37,7 @@ class SphParams(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("dtype", ctypes.c_int32), ("box", ctypes.c_double),
                 ("support", ctypes.c_double), ("mass", ctypes.c_double), ("rho0", ctypes.c_double),
                 ("c0", ctypes.c_double), ("delta", ctypes.c_double), ("alpha", ctypes.c_double),
-                ("eps", ctypes.c_double), ("dt", ctypes.c_double)]
+                ("eps", ctypes.c_double), ("dt", ctypes.c_double), ("skin", ctypes.c_double)]
 
 
 class SphState(ctypes.Structure):
@@ -64,6 +65,8 @@ def lib():
         L.sph_density_adjoint.restype = st
         L.sph_density_adjoint.argtypes = [_VP, ctypes.POINTER(SphState), _VP, _VP, _VP]
         L.sph_set_graphs.argtypes = [_VP, ctypes.c_int32]
+        L.sph_set_reuse.restype = st
+        L.sph_set_reuse.argtypes = [_VP, ctypes.c_int32]
         L.sph_set_graphs.restype = ctypes.c_int32
         L.sph_get_tuning.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         L.sph_rollout_backward.restype = st
@@ -114,18 +117,18 @@ def exported_symbols() -> List[str]:
     return ["sph_plan_create", "sph_plan_destroy", "sph_workspace_size", "sph_plan_info", "sph_bind",
             "sph_build_cells", "sph_neighbors", "sph_rhs", "sph_step", "sph_step_adjoint", "sph_poll",
             "sph_pair_count", "sph_profile_enable", "sph_profile_read", "sph_last_error", "sph_set_tuning",
-            "sph_get_tuning", "sph_rollout_backward", "sph_set_graphs", "sph_density_adjoint"]
+            "sph_get_tuning", "sph_rollout_backward", "sph_set_graphs", "sph_density_adjoint", "sph_set_reuse"]
 
 
 KERNEL_CLASSES = ["sort", "build", "sweep", "adjoint", "other"]
 
 
 def workspace_bytes(sims: Sequence[dict], counts: Sequence[int], dtype: str = "f32", tape_depth: int = 8,
-                    max_neighbors: int = 0) -> int:
+                    max_neighbors: int = 0, skin: float = 0.0) -> int:
     """Workspace bytes a plan for this batch needs (host-only query; allocates no device memory)."""
     L = lib()
     n = len(sims)
-    arr = (SphParams * n)(*[make_params(p, dtype) for p in sims])
+    arr = (SphParams * n)(*[make_params(p, dtype, skin) for p in sims])
     cnt = (ctypes.c_int64 * n)(*[int(c) for c in counts])
     h = _VP()
     _check(L.sph_plan_create(arr, n, cnt, int(max_neighbors), int(tape_depth), ctypes.byref(h)))
@@ -142,11 +145,12 @@ def _stream_ptr(stream=None) -> int:
     return int(s.cuda_stream)
 
 
-def make_params(p: dict, dtype: str) -> SphParams:
-    """dict with keys dim, L, H, m, rho0, c0, delta, alpha, eps, dt -> SphParams."""
+def make_params(p: dict, dtype: str, skin: float = 0.0) -> SphParams:
+    """dict with keys dim, L, H, m, rho0, c0, delta, alpha, eps, dt -> SphParams (list skin as a
+    fraction of the support)."""
     return SphParams(int(p["dim"]), SPH_F64 if dtype == "f64" else SPH_F32, float(p["L"]), float(p["H"]),
                      float(p["m"]), float(p["rho0"]), float(p["c0"]), float(p["delta"]), float(p["alpha"]),
-                     float(p["eps"]), float(p["dt"]))
+                     float(p["eps"]), float(p["dt"]), float(skin))
 
 
 class Plan:
@@ -154,17 +158,18 @@ class Plan:
 
     def __init__(self, sims: Sequence[dict], counts: Sequence[int], dtype: str = "f32",
                  max_neighbors: int = 0, tape_depth: int = 8, device: Optional[torch.device] = None,
-                 stream=None):
+                 stream=None, skin: float = 0.0, rebuild_every: int = 1):
         L = lib()
         self.dtype = dtype
         self.torch_dtype = torch.float64 if dtype == "f64" else torch.float32
         self.dim = int(sims[0]["dim"])
         n = len(sims)
-        arr = (SphParams * n)(*[make_params(p, dtype) for p in sims])
+        arr = (SphParams * n)(*[make_params(p, dtype, skin) for p in sims])
         cnt = (ctypes.c_int64 * n)(*[int(c) for c in counts])
         h = _VP()
         _check(L.sph_plan_create(arr, n, cnt, int(max_neighbors), int(tape_depth), ctypes.byref(h)))
         self.tape_depth = int(tape_depth)
+        self.skin = float(skin)
         self._h = h
         self.counts = [int(c) for c in counts]
         self.offsets = np.concatenate([[0], np.cumsum(self.counts)]).astype(np.int64)
@@ -181,6 +186,9 @@ class Plan:
         base = self.workspace.data_ptr()
         self._ws_ptr = (base + 255) // 256 * 256
         _check(L.sph_bind(h, self._ws_ptr, self.workspace_bytes, _stream_ptr(stream)))
+        self.rebuild_every = 1
+        if rebuild_every != 1:
+            self.set_reuse(rebuild_every)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -277,6 +285,11 @@ class Plan:
 
     def set_tuning(self, lanes_fwd: int, lanes_adj: int):
         _check(lib().sph_set_tuning(self._h, int(lanes_fwd), int(lanes_adj)))
+
+    def set_reuse(self, rebuild_every: int):
+        """Rebuild the cell list and neighbour lists every `rebuild_every` steps (needs a skin)."""
+        _check(lib().sph_set_reuse(self._h, int(rebuild_every)))
+        self.rebuild_every = int(rebuild_every)
 
     def set_graphs(self, enable: bool = True):
         """Issue step / rollout_backward calls as cached executable HIP graphs."""

@@ -1,0 +1,157 @@
+"""Neighbour-list reuse (lists with a skin, rebuilt every R steps) on the GPU.
+
+The sweeps filter reused lists to exactly the pairs with r < H, so the physics is the
+method's; only the summation order differs from rebuilding every step.  Checked here: the
+forward state and the rollout gradient against the FP64 oracle at the usual tolerances, the
+pair count of the filter against the exact lists, the exported lists, bitwise determinism and
+batch invariance, the displacement flag, and argument checks.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2507_21684_amd.inputs import SimSpec, make_state
+from paper_2507_21684_amd.lib import FLAG_SKIN, Plan, SphError
+
+pytestmark = pytest.mark.gpu
+
+SKIN, R = 0.15, 4
+
+
+def _dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch.device("cuda", 0)
+
+
+def _gpu(arrs, dtype="f32"):
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    return [torch.tensor(a, dtype=tdt, device=_dev()).contiguous() for a in arrs]
+
+
+def _state(spec, seed, dtype="f32"):
+    npdt = np.float32 if dtype == "f32" else np.float64
+    return [a.astype(npdt) for a in make_state(spec, seed)]
+
+
+def _plan(specs, dtype="f32", skin=SKIN, rebuild=R, **kw):
+    return Plan([s.params() for s in specs], [s.n for s in specs], dtype, skin=skin, rebuild_every=rebuild, **kw)
+
+
+@pytest.mark.parametrize("dim,side,steps", [(2, 48, 16), (3, 16, 8)])
+def test_reuse_forward_parity(orc, dim, side, steps):
+    spec = SimSpec(dim, side)
+    x, v, rho = _state(spec, 1)
+    plan = _plan([spec])
+    g = _gpu([x, v, rho])
+    plan.step(*g, steps)
+    assert np.all(plan.poll() == 0)
+    xr, vr, rr = orc.step(orc.Params(**spec.params()), x, v, rho, steps)
+    gx, gv, gr = [t.cpu().numpy().astype(np.float64) for t in g]
+    assert np.abs(gr / rr - 1).max() <= 1e-5
+    err = np.sqrt(((gv - vr) ** 2).sum(axis=0)).max() / np.sqrt((vr ** 2).sum(axis=0)).max()
+    assert err <= 1e-4
+    assert np.abs(gx - xr).max() <= 1e-4 * spec.dx
+
+
+def test_reuse_rollout_gradient(orc):
+    from paper_2507_21684_amd.rollout import rollout
+    spec = SimSpec(2, 48)
+    x, v, rho = _state(spec, 0)
+    plan = _plan([spec], tape_depth=4)
+    gx0, gv0, gr0 = _gpu([x, v, rho])
+    for t in (gx0, gv0, gr0):
+        t.requires_grad_(True)
+    xT, vT, rT = rollout(plan, gx0, gv0, gr0, 16, 4)
+    loss = (vT.double() ** 2).sum()
+    loss.backward()
+    assert np.all(plan.poll() == 0)
+    ref = orc.rollout(orc.Params(**spec.params()), x, v, rho, 16, 0)
+    assert float(loss) == pytest.approx(ref["loss"], rel=1e-5)
+    for got, want in ((gv0.grad, ref["gv0"]), (gx0.grad, ref["gx0"]), (gr0.grad, ref["grho0"])):
+        got = got.cpu().numpy().astype(np.float64)
+        assert np.abs(got - want).max() <= 1e-3 * np.abs(want).max()
+
+
+def test_filtered_pair_count_and_export_are_exact():
+    spec = SimSpec(2, 40, amplitude=1.5)
+    x, v, rho = _state(spec, 4)
+    exact = Plan([spec.params()], [spec.n], "f32")
+    skinned = _plan([spec])
+    g = _gpu([x, v, rho])
+    exact.pair_count()
+    skinned.pair_count()
+    exact.step(*[t.clone() for t in g], 1)
+    skinned.step(*[t.clone() for t in g], 1)
+    assert skinned.pair_count() == exact.pair_count()
+    o1, n1 = exact.neighbors(*g)
+    o2, n2 = skinned.neighbors(*g)
+    o1, n1, o2, n2 = (t.cpu().numpy() for t in (o1, n1, o2, n2))
+    np.testing.assert_array_equal(o1, o2)
+    for i in range(0, spec.n, 97):
+        np.testing.assert_array_equal(np.sort(n1[o1[i]:o1[i + 1]]), np.sort(n2[o2[i]:o2[i + 1]]))
+
+
+def test_reuse_deterministic_and_batch_invariant():
+    specs = [SimSpec(2, 24, amplitude=0.7), SimSpec(2, 37, amplitude=1.6)]
+    states = [_state(s, 20 + k) for k, s in enumerate(specs)]
+    solo = []
+    for s, st in zip(specs, states):
+        p = _plan([s])
+        g = _gpu(st)
+        p.step(*g, 12, [p.empty_state() for _ in range(3)], 4)
+        solo.append([t.cpu().numpy() for t in g])
+    cat = [np.concatenate([st[k] for st in states], axis=-1) for k in range(3)]
+    for rep in range(2):
+        pb = _plan(specs)
+        g = _gpu(cat)
+        pb.step(*g, 12, [pb.empty_state() for _ in range(3)], 4)
+        out = [t.cpu().numpy() for t in g]
+        off = 0
+        for s, ref in zip(specs, solo):
+            for k in range(3):
+                np.testing.assert_array_equal(out[k][..., off:off + s.n], ref[k])
+            off += s.n
+
+
+def test_reuse_checkpoint_resume_bitwise():
+    spec = SimSpec(2, 32, amplitude=1.2)
+    st = _state(spec, 6)
+    p = _plan([spec])
+    g = _gpu(st)
+    ck = [p.empty_state() for _ in range(2)]
+    p.step(*g, 16, ck, 8)
+    full = [t.cpu().numpy() for t in g]
+    # resume from the checkpoint at step 8
+    g2 = [t.clone() for t in ck[1]]
+    p.step(*g2, 8)
+    for a, b in zip(full, g2):
+        np.testing.assert_array_equal(a, b.cpu().numpy())
+
+
+def test_displacement_beyond_half_the_skin_is_flagged():
+    spec = SimSpec(2, 32, amplitude=2.0)
+    p = _plan([spec], skin=0.01, rebuild=8)
+    g = _gpu(_state(spec, 2))
+    p.step(*g, 8)
+    assert p.poll()[0] & FLAG_SKIN
+    # the same run with the rebuild every step raises nothing
+    p.set_reuse(1)
+    g = _gpu(_state(spec, 2))
+    p.step(*g, 8)
+    assert p.poll()[0] == 0
+
+
+def test_reuse_argument_checks():
+    spec = SimSpec(2, 24)
+    exact = Plan([spec.params()], [spec.n], "f32")
+    with pytest.raises(SphError):
+        exact.set_reuse(2)              # no skin
+    p = _plan([spec])
+    with pytest.raises(SphError):
+        p.set_reuse(0)
+    g = _gpu(_state(spec, 0))
+    with pytest.raises(SphError):
+        p.step(*g, 12, [p.empty_state() for _ in range(2)], 6)   # 6 is not a multiple of 4
+    Plan([SimSpec(2, 13).params()], [169], "f32")                 # valid without a skin
+    with pytest.raises(SphError):
+        Plan([SimSpec(2, 13).params()], [169], "f32", skin=0.7)   # 2 H (1 + skin) >= L
