@@ -224,12 +224,11 @@ def bench_batched(dev, reps):
     from paper_2507_21684_amd.lib import Plan
     wl = batched_512_f32()
     host, (x0, v0, r0) = packed_inputs(wl, dev)
-    plan = Plan([s.params() for s in wl.sims], [s.n for s in wl.sims], wl.dtype, tape_depth=wl.ckpt_every,
-                device=dev)
-    autotune.tune(plan, x0, v0, r0)
+    plan = autotune.tune_plan([s.params() for s in wl.sims], [s.n for s in wl.sims], wl.dtype, wl.ckpt_every,
+                              x0, v0, r0, dev)
+    skins, R = list(plan.skins), plan.rebuild_every
     run_job(plan, x0, v0, r0, wl)
-    per_state = count_pairs(plan, x0, v0, r0, wl)
-    work = 2 * sum(per_state)
+    work = 2 * count_pairs_schedule(plan, x0, v0, r0, wl)
     t_batched, _ = timed_jobs(plan, x0, v0, r0, wl, reps, ())
     t_batched /= reps
     assert np.all(plan.poll() == 0)
@@ -241,7 +240,9 @@ def bench_batched(dev, reps):
         sub = Workload("one", [s], [wl.seeds[k]], wl.dtype, wl.steps, wl.ckpt_every, True, wl.loss)
         st = (x0[:, offs[k]:offs[k + 1]].contiguous(), v0[:, offs[k]:offs[k + 1]].contiguous(),
               r0[offs[k]:offs[k + 1]].contiguous())
-        p = Plan([s.params()], [s.n], wl.dtype, tape_depth=wl.ckpt_every, device=dev)
+        # the same list settings as the batch, each simulation in its own plan
+        p = Plan([s.params()], [s.n], wl.dtype, tape_depth=wl.ckpt_every, device=dev, skin=skins[k],
+                 rebuild_every=R)
         autotune.tune(p, *st)
         run_job(p, *st, sub)
         plains.append((p, sub, st))
@@ -260,7 +261,8 @@ def bench_batched(dev, reps):
     lat_plain = np.array([ev0.elapsed_time(e) for e in evs])
     lat_batched = np.full(len(wl.sims), t_batched * 1e3)
     return {"workload": wl.name, "simulations": len(wl.sims), "particles": int(offs[-1]), "sim_steps": wl.steps,
-            "pair_interactions": work, "unit": "pair interactions/s",
+            "pair_interactions": work, "unit": "pair interactions/s", "list_rebuild_every": R,
+            "list_skin_range": [round(min(skins), 4), round(max(skins), 4)],
             "batched": {"value": round(work / t_batched, 1), "ms_per_job": round(t_batched * 1e3, 3),
                         "p50_ms": round(float(np.percentile(lat_batched, 50)), 3),
                         "p99_ms": round(float(np.percentile(lat_batched, 99)), 3)},

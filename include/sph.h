@@ -143,8 +143,9 @@ sph_status sph_get_tuning(const sph_plan* plan, int32_t* lanes_fwd, int32_t* lan
  * every step still evaluates exactly the pairs the method defines.  Each sweep
  * that hands its state to a reusing step checks every particle's displacement
  * since the build against skin H / 2 and sets SPH_FLAG_SKIN if it is exceeded.
- * Checkpoint intervals must be multiples of R, so a backward recomputation
- * follows the forward's build schedule exactly.  Results differ from R = 1 only
+ * A call that spans more than one checkpoint interval needs the interval to be a
+ * multiple of R (INVALID_ARG otherwise), so a backward recomputation, which starts
+ * every segment with a build, follows the forward's build schedule exactly.  Results differ from R = 1 only
  * by summation order (the lists hold extra entries); they stay deterministic and
  * independent of the batch.  Host-side setting; default 1.  INVALID_ARG for
  * R < 1, or R > 1 without a skin. */

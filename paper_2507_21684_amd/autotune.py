@@ -5,11 +5,13 @@
   the result.  `tune` times each setting on the caller's own state with the library's
   HIP-event profiler (a few forward steps and one taped backward segment) and keeps the
   fastest per sweep.
-* Neighbour-list skin and rebuild interval (the cell size follows the list radius).  Lists
+* Neighbour-list rebuild interval R and skin (the cell size follows the list radius).  Lists
   reused for R steps save R - 1 of every R sorts and builds but hold more entries, which the
-  sweeps filter back to r < H.  `tune_plan` builds a plan per candidate (skin, R) with R
-  dividing the checkpoint interval, tunes its lanes, times one checkpoint segment forward and
-  backward, discards candidates whose run raised the displacement flag, and returns the
+  sweeps filter back to r < H.  Half the skin must cover R steps of travel, so each
+  simulation's skin is 2 x 1.3 x v_max dt R / H from the largest speed of its state (30 %
+  margin; the device flags any particle that moves farther).  `tune_plan` builds a plan per
+  candidate R dividing the checkpoint interval, tunes its lanes, times one checkpoint segment
+  forward and backward, discards candidates whose run raised a device flag, and returns the
   fastest plan.
 
 Choices are cached in a JSON file keyed by GPU architecture, dimension, dtype and a
@@ -29,8 +31,39 @@ import torch
 from .lib import Plan
 
 LANE_CHOICES = (2, 4, 8)
-# (skin as a fraction of the support, rebuild interval in steps)
-REUSE_CHOICES = ((0.0, 1), (0.15, 4), (0.25, 8))
+REBUILD_CHOICES = (1, 4, 8)
+SKIN_MARGIN = 1.3
+
+
+def rebuild_for(ckpt_every: int, want: int = 8) -> int:
+    """Largest rebuild interval not above `want` that divides the checkpoint interval."""
+    for R in range(min(want, ckpt_every), 0, -1):
+        if ckpt_every % R == 0:
+            return R
+    return 1
+
+
+def skin_from_speed(vmax: float, p: dict, R: int) -> float:
+    """List skin (fraction of the support) whose half covers R steps at SKIN_MARGIN x vmax."""
+    if R <= 1:
+        return 0.0
+    skin = 2.0 * SKIN_MARGIN * vmax * float(p["dt"]) * R / float(p["H"])
+    cap = 0.95 * (float(p["L"]) / (2.0 * float(p["H"])) - 1.0)   # keeps 2 H (1 + skin) < L
+    return min(max(skin, 0.05), cap, 1.0)
+
+
+def skins_for(sims, counts, v, R: int):
+    """Per-simulation list skin (fraction of the support) for rebuild interval R: half the skin
+    covers R steps at SKIN_MARGIN times the largest speed of the simulation's state."""
+    if R <= 1:
+        return [0.0] * len(sims)
+    speed = torch.sqrt((v.double() ** 2).sum(dim=0)).cpu().numpy()
+    out, a = [], 0
+    for p, c in zip(sims, counts):
+        vmax = float(speed[a:a + c].max()) if c > 0 else 0.0
+        a += c
+        out.append(skin_from_speed(vmax, p, R))
+    return out
 
 
 def cache_path() -> str:
@@ -144,35 +177,38 @@ def _segment_seconds(plan: Plan, x, v, rho, K: int, reps: int = 3) -> Tuple[floa
 
 
 def tune_plan(sims: Sequence[dict], counts: Sequence[int], dtype: str, ckpt_every: int, x, v, rho,
-              device=None, use_cache: bool = True, choices=REUSE_CHOICES) -> Plan:
-    """Plan with the fastest (skin, rebuild interval, lanes) for one checkpoint segment of this state."""
+              device=None, use_cache: bool = True, choices=REBUILD_CHOICES) -> Plan:
+    """Plan with the fastest (rebuild interval, skins, lanes) for one checkpoint segment of this state."""
     K = int(ckpt_every)
     probe = Plan(sims, counts, dtype, tape_depth=K, device=device)
     key = cache_key(probe) + ":K%d:reuse" % K
     del probe
     table = _load() if use_cache else {}
     if key in table:
-        skin, R, lf, la = table[key][:4]
-        plan = Plan(sims, counts, dtype, tape_depth=K, device=device, skin=float(skin), rebuild_every=int(R))
-        plan.set_tuning(int(lf), int(la))
+        R, lf, la = (int(t) for t in table[key][:3])
+        plan = Plan(sims, counts, dtype, tape_depth=K, device=device, skin=skins_for(sims, counts, v, R),
+                    rebuild_every=R)
+        plan.set_tuning(lf, la)
         return plan
     best, trials = None, {}
-    for skin, R in choices:
+    for R in choices:
         if K % R:
             continue
-        plan = Plan(sims, counts, dtype, tape_depth=K, device=device, skin=skin, rebuild_every=R)
+        plan = Plan(sims, counts, dtype, tape_depth=K, device=device, skin=skins_for(sims, counts, v, R),
+                    rebuild_every=R)
         lf, la = tune(plan, x, v, rho, use_cache=False)
         secs, status = _segment_seconds(plan, x, v, rho, K)
-        trials["%g/%d" % (skin, R)] = [secs, status, lf, la]
+        trials[str(R)] = [secs, status, lf, la, round(plan.skin, 4)]
         if status == 0 and (best is None or secs < best[0]):
-            best = (secs, skin, R, lf, la)
+            best = (secs, R, lf, la)
         del plan
     if best is None:
         raise RuntimeError("no list setting ran without device flags: %s" % trials)
-    _, skin, R, lf, la = best
+    _, R, lf, la = best
     if use_cache:
-        table[key] = [skin, R, lf, la, trials]
+        table[key] = [R, lf, la, trials]
         _store(table)
-    plan = Plan(sims, counts, dtype, tape_depth=K, device=device, skin=skin, rebuild_every=R)
+    plan = Plan(sims, counts, dtype, tape_depth=K, device=device, skin=skins_for(sims, counts, v, R),
+                rebuild_every=R)
     plan.set_tuning(lf, la)
     return plan

@@ -996,7 +996,7 @@ sph_status sph_step(sph_plan* P, sph_state* s, int32_t nsteps, const sph_state* 
     if (nsteps < 0) return fail(SPH_ERR_INVALID_ARG, "nsteps < 0");
     if (ckpt) {
         if (ckpt_every <= 0) return fail(SPH_ERR_INVALID_ARG, "ckpt_every must be > 0");
-        if (ckpt_every % P->reuse != 0)
+        if (nsteps > ckpt_every && ckpt_every % P->reuse != 0)
             return fail(SPH_ERR_INVALID_ARG, "ckpt_every must be a multiple of the list reuse interval");
         const int32_t nslots = (nsteps + ckpt_every - 1) / ckpt_every;
         for (int32_t k = 0; k < nslots; ++k) RC_TRY(check_state(P, &ckpt[k], "checkpoint slot"));
@@ -1040,7 +1040,7 @@ sph_status sph_rollout_backward(sph_plan* P, const sph_state* ckpt, int32_t nste
     if (nsteps > 0 && !ckpt) return fail(SPH_ERR_INVALID_ARG, "checkpoints are null");
     if (std::min(ckpt_every, nsteps) > P->tape_depth)
         return fail(SPH_ERR_CAPACITY, "plan tape_depth is smaller than the checkpoint interval");
-    if (ckpt_every % P->reuse != 0)
+    if (nsteps > ckpt_every && ckpt_every % P->reuse != 0)
         return fail(SPH_ERR_INVALID_ARG, "ckpt_every must be a multiple of the list reuse interval");
     const int32_t nseg = nsteps > 0 ? (nsteps + ckpt_every - 1) / ckpt_every : 0;
     for (int32_t k = 0; k < nseg; ++k) RC_TRY(check_state(P, &ckpt[k], "checkpoint slot"));

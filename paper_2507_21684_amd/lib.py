@@ -123,12 +123,22 @@ def exported_symbols() -> List[str]:
 KERNEL_CLASSES = ["sort", "build", "sweep", "adjoint", "other"]
 
 
+def _skins(skin, n: int) -> List[float]:
+    """One list skin per simulation from a scalar or a sequence."""
+    if isinstance(skin, (int, float)):
+        return [float(skin)] * n
+    out = [float(x) for x in skin]
+    if len(out) != n:
+        raise ValueError("need one skin per simulation")
+    return out
+
+
 def workspace_bytes(sims: Sequence[dict], counts: Sequence[int], dtype: str = "f32", tape_depth: int = 8,
-                    max_neighbors: int = 0, skin: float = 0.0) -> int:
+                    max_neighbors: int = 0, skin=0.0) -> int:
     """Workspace bytes a plan for this batch needs (host-only query; allocates no device memory)."""
     L = lib()
     n = len(sims)
-    arr = (SphParams * n)(*[make_params(p, dtype, skin) for p in sims])
+    arr = (SphParams * n)(*[make_params(p, dtype, k) for p, k in zip(sims, _skins(skin, n))])
     cnt = (ctypes.c_int64 * n)(*[int(c) for c in counts])
     h = _VP()
     _check(L.sph_plan_create(arr, n, cnt, int(max_neighbors), int(tape_depth), ctypes.byref(h)))
@@ -158,18 +168,20 @@ class Plan:
 
     def __init__(self, sims: Sequence[dict], counts: Sequence[int], dtype: str = "f32",
                  max_neighbors: int = 0, tape_depth: int = 8, device: Optional[torch.device] = None,
-                 stream=None, skin: float = 0.0, rebuild_every: int = 1):
+                 stream=None, skin=0.0, rebuild_every: int = 1):
         L = lib()
         self.dtype = dtype
         self.torch_dtype = torch.float64 if dtype == "f64" else torch.float32
         self.dim = int(sims[0]["dim"])
         n = len(sims)
-        arr = (SphParams * n)(*[make_params(p, dtype, skin) for p in sims])
+        skins = _skins(skin, n)
+        arr = (SphParams * n)(*[make_params(p, dtype, k) for p, k in zip(sims, skins)])
         cnt = (ctypes.c_int64 * n)(*[int(c) for c in counts])
         h = _VP()
         _check(L.sph_plan_create(arr, n, cnt, int(max_neighbors), int(tape_depth), ctypes.byref(h)))
         self.tape_depth = int(tape_depth)
-        self.skin = float(skin)
+        self.skins = skins
+        self.skin = max(skins) if skins else 0.0
         self._h = h
         self.counts = [int(c) for c in counts]
         self.offsets = np.concatenate([[0], np.cumsum(self.counts)]).astype(np.int64)

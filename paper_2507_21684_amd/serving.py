@@ -17,6 +17,10 @@ is admitted when its footprint (its states, checkpoints and cotangent plus the w
 a plan of its size) fits beside the requests already running; the head of the queue is
 always admitted into an empty server so that every request makes progress.
 
+2D neighbour lists are rebuilt every R steps (the largest R <= 8 dividing K, so every segment
+starts with a build) with a skin per request that covers R steps at 1.3 times the largest speed
+of its initial state; 3D lists are rebuilt every step.  The plain path uses the same settings.
+
 The segment boundaries of a request are the same (every K steps from its step 0, the last
 segment possibly shorter) whether it runs alone or in a mix, and the library's results do
 not depend on the batch composition, so a served request returns bitwise the gradient that
@@ -202,12 +206,19 @@ def percentiles(lat_s: Sequence[float]) -> Dict[str, float]:
 class GpuEngine:
     """Runs the scheduler's groups through batched plans of the HIP library."""
 
-    def __init__(self, dtype: str = "f32", ckpt_every: int = 8, device=None, tuned: bool = True):
+    def __init__(self, dtype: str = "f32", ckpt_every: int = 8, device=None, tuned: bool = True,
+                 reuse: int = 8):
         import torch
+        from .autotune import rebuild_for
         self.torch = torch
         self.dtype = dtype
         self.tdt = torch.float32 if dtype == "f32" else torch.float64
         self.K = int(ckpt_every)
+        # 2D neighbour lists rebuilt every R steps (R divides K, so segments start with a build),
+        # each request's skin from the largest speed of its own initial state; 3D lists are
+        # rebuilt every step (their longer skinned lists cost the sweeps more than they save)
+        self.R = {2: rebuild_for(self.K, reuse), 3: 1}
+        self._skin: Dict[int, float] = {}
         self.device = device if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.tuned = tuned
         self._plans: Dict[tuple, object] = {}
@@ -221,10 +232,13 @@ class GpuEngine:
 
     # -- accounting
     def workspace_bytes(self, spec) -> int:
+        return self.workspace_bytes_skin(spec, 0.0)
+
+    def workspace_bytes_skin(self, spec, skin: float) -> int:
         from .lib import workspace_bytes
-        key = (spec.dim, spec.side)
+        key = (spec.dim, spec.side, round(skin, 6))
         if key not in self._ws_cache:
-            self._ws_cache[key] = workspace_bytes([spec.params()], [spec.n], self.dtype, self.K)
+            self._ws_cache[key] = workspace_bytes([spec.params()], [spec.n], self.dtype, self.K, skin=skin)
         return self._ws_cache[key]
 
     def footprint(self, req: Request) -> int:
@@ -232,13 +246,17 @@ class GpuEngine:
         also when its initial state (the request's payload) is generated on the host."""
         from .inputs import make_state
         npdt = np.float32 if self.dtype == "f32" else np.float64
-        self._host[req.rid] = [a.astype(npdt) for a in make_state(req.spec, req.seed)]
+        from .autotune import skin_from_speed
+        host = [a.astype(npdt) for a in make_state(req.spec, req.seed)]
+        self._host[req.rid] = host
+        vmax = float(np.sqrt((host[1].astype(np.float64) ** 2).sum(axis=0)).max())
+        self._skin[req.rid] = skin_from_speed(vmax, req.spec.params(), self.R[req.spec.dim])
         spec = req.spec
         esz = 4 if self.dtype == "f32" else 8
         state = (2 * spec.dim + 1) * spec.n * esz
         nseg = (req.steps + self.K - 1) // self.K
         # checkpoints, current state, cotangent, and packed copies of both for a group call
-        return (nseg + 4) * state + self.workspace_bytes(spec)
+        return (nseg + 4) * state + self.workspace_bytes_skin(spec, self._skin[req.rid])
 
     # neighbours per particle (self excluded) on the jittered lattices, and the cost model of
     # one simulation step used for fair sharing: a fixed launch cost per step plus the pair
@@ -258,7 +276,8 @@ class GpuEngine:
         if p is None:
             t0 = time.perf_counter()
             p = Plan([j.req.spec.params() for j in jobs], [j.req.spec.n for j in jobs], dtype=self.dtype,
-                     tape_depth=tape, device=self.device)
+                     tape_depth=tape, device=self.device, skin=[self._skin[j.req.rid] for j in jobs],
+                     rebuild_every=self.R[jobs[0].dim])
             if self.tuned:
                 from .autotune import apply_cached
                 apply_cached(p)
@@ -344,15 +363,16 @@ class GpuEngine:
 
 def serve(trace: Sequence[Request], dtype: str = "f32", ckpt_every: int = 8, budget_bytes: int = 64 << 30,
           device=None, tuned: bool = True, progress: Optional[Callable[[str], None]] = None,
-          quantum: float = 2e-3):
+          quantum: float = 2e-3, reuse: int = 8):
     """Serve `trace` with continuous batching; returns (scheduler, engine, finished jobs)."""
-    eng = GpuEngine(dtype, ckpt_every, device, tuned)
+    eng = GpuEngine(dtype, ckpt_every, device, tuned, reuse)
     sch = Scheduler(eng, ckpt_every, budget_bytes, quantum=quantum, progress=progress)
     done = sch.run(trace)
     return sch, eng, done
 
 
-def plain_request(req: Request, dtype: str = "f32", ckpt_every: int = 8, device=None, tuned: bool = True):
+def plain_request(req: Request, dtype: str = "f32", ckpt_every: int = 8, device=None, tuned: bool = True,
+                  reuse: int = 8):
     """The plain path for one request: its own plan, sph_step with checkpoints, sph_rollout_backward.
 
     Returns (service seconds, gradient tuple)."""
@@ -362,11 +382,15 @@ def plain_request(req: Request, dtype: str = "f32", ckpt_every: int = 8, device=
     spec = req.spec
     npdt = np.float32 if dtype == "f32" else np.float64
     host = [a.astype(npdt) for a in make_state(spec, req.seed)]
+    from .autotune import rebuild_for, skin_from_speed
+    R = rebuild_for(ckpt_every, reuse) if spec.dim == 2 else 1
+    skin = skin_from_speed(float(np.sqrt((host[1].astype(np.float64) ** 2).sum(axis=0)).max()), spec.params(), R)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
     x, v, r = (torch.tensor(a, device=dev) for a in host)
-    plan = Plan([spec.params()], [spec.n], dtype=dtype, tape_depth=ckpt_every, device=dev)
+    plan = Plan([spec.params()], [spec.n], dtype=dtype, tape_depth=ckpt_every, device=dev, skin=skin,
+                rebuild_every=R)
     if tuned:
         from .autotune import apply_cached
         apply_cached(plan)
