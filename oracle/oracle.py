@@ -99,6 +99,12 @@ def lib():
         L.orc_rhs_sample.argtypes = [_P, ctypes.c_int64, _D, _D, _D, ctypes.c_int64, _I64, _D, _D, _D]
         L.orc_step.restype = ctypes.c_int
         L.orc_step.argtypes = [_P, ctypes.c_int64, _D, _D, _D, ctypes.c_int32]
+        L.orc_rhs_vjp.restype = ctypes.c_int
+        L.orc_rhs_vjp.argtypes = [_P, ctypes.c_int64, _D, _D, _D, _D, _D, _D, _D, _D]
+        L.orc_step_rk.restype = ctypes.c_int
+        L.orc_step_rk.argtypes = [_P, ctypes.c_int64, _D, _D, _D, ctypes.c_int32, ctypes.c_int32, _D, _D]
+        L.orc_step_rk_adjoint.restype = ctypes.c_int
+        L.orc_step_rk_adjoint.argtypes = [_P, ctypes.c_int64, _D, _D, _D, ctypes.c_int32, _D, _D, _D, _D, _D]
         L.orc_density_adjoint.restype = ctypes.c_int
         L.orc_density_adjoint.argtypes = [_P, ctypes.c_int64, _D, _D, _D]
         L.orc_step_adjoint.restype = ctypes.c_int
@@ -254,6 +260,59 @@ def step_adjoint(p: Params, x, v, rho, xb, vb, rb):
     rc = lib().orc_step_adjoint(ctypes.byref(pc), rho.shape[0], _d(x), _d(v), _d(rho), _d(xb), _d(vb), _d(rb))
     if rc != 0:
         raise ValueError("oracle step_adjoint rejected its input")
+    return xb, vb, rb
+
+
+# Butcher tableaus of the explicit schemes (A strictly lower triangular, weights b).
+TABLEAUS = {
+    "euler": ([[0.0]], [1.0]),
+    "midpoint": ([[0.0, 0.0], [0.5, 0.0]], [0.0, 1.0]),
+    "heun": ([[0.0, 0.0], [1.0, 0.0]], [0.5, 0.5]),
+    "rk4": ([[0.0, 0.0, 0.0, 0.0], [0.5, 0.0, 0.0, 0.0], [0.0, 0.5, 0.0, 0.0], [0.0, 0.0, 1.0, 0.0]],
+            [1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0]),
+}
+
+
+def _tableau(scheme):
+    A, b = TABLEAUS[scheme] if isinstance(scheme, str) else scheme
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.float64))
+    b = np.ascontiguousarray(np.asarray(b, dtype=np.float64))
+    return A.shape[0], A, b
+
+
+def rhs_vjp(p: Params, x, v, rho, abar, rbar):
+    """J^T terms (xbar, vbar, rhobar) of the update function for cotangents of (a, drho/dt)."""
+    x, v, rho, abar, rbar = _f64(x), _f64(v), _f64(rho), _f64(abar), _f64(rbar)
+    n = rho.shape[0]
+    xb, vb, rb = np.zeros((p.dim, n)), np.zeros((p.dim, n)), np.zeros(n)
+    pc = p.c()
+    rc = lib().orc_rhs_vjp(ctypes.byref(pc), n, _d(x), _d(v), _d(rho), _d(abar), _d(rbar), _d(xb), _d(vb), _d(rb))
+    if rc != 0:
+        raise ValueError("oracle rhs_vjp rejected its input")
+    return xb, vb, rb
+
+
+def step_rk(p: Params, x, v, rho, nsteps: int, scheme="rk4"):
+    """nsteps explicit Runge-Kutta steps of the named (or given (A, b)) tableau."""
+    s, A, b = _tableau(scheme)
+    x, v, rho = _f64(x).copy(), _f64(v).copy(), _f64(rho).copy()
+    pc = p.c()
+    rc = lib().orc_step_rk(ctypes.byref(pc), rho.shape[0], _d(x), _d(v), _d(rho), nsteps, s, _d(A), _d(b))
+    if rc != 0:
+        raise ValueError("oracle step_rk rejected its input")
+    return x, v, rho
+
+
+def step_rk_adjoint(p: Params, x, v, rho, xb, vb, rb, scheme="rk4"):
+    """Cotangents of the state at the start of a Runge-Kutta step from those of its output."""
+    s, A, b = _tableau(scheme)
+    x, v, rho = _f64(x), _f64(v), _f64(rho)
+    xb, vb, rb = _f64(xb).copy(), _f64(vb).copy(), _f64(rb).copy()
+    pc = p.c()
+    rc = lib().orc_step_rk_adjoint(ctypes.byref(pc), rho.shape[0], _d(x), _d(v), _d(rho), s, _d(A), _d(b),
+                                   _d(xb), _d(vb), _d(rb))
+    if rc != 0:
+        raise ValueError("oracle step_rk_adjoint rejected its input")
     return xb, vb, rb
 
 

@@ -728,32 +728,17 @@ int orc_step(const orc_params* p, int64_t n, double* x, double* v, double* rho, 
     return 0;
 }
 
-/* Vector-Jacobian product of one step.  On entry (xb, vb, rb) hold the
- * cotangents of the step's output (x', v', rho'); on exit those of its input
- * (x, v, rho), the state at the start of the step.
- *   v' = v + dt a(x,v,rho);  rho' = rho + dt rdot(x,v,rho);  x' = x + dt v'
- * gives  vt = vb' + dt xb',  abar = dt vt,  rbar = dt rb',
- *        xb = xb' + (J_x)^T,  vb = vt + (J_v)^T,  rb = rb' + (J_rho)^T
- * where the J^T terms gather, for every particle k and neighbour j != k, the
- * partials of the two directed pairs (k,j) and (j,k) that involve k. */
-static void step_adjoint_with_list(const orc_params* p, int64_t n, const double* u, const double* v,
-                                   const double* rho, const nblist* nb, double* xb, double* vb, double* rb)
+/* The J^T terms of the update function's vector-Jacobian product (Sec. 2.2):
+ * for cotangents abar of the accelerations and rbar of drho/dt, the
+ * cotangents (gx, gv, gr) of the positions, velocities and densities, which
+ * gather, for every particle k and neighbour j != k, the partials of the two
+ * directed pairs (k,j) and (j,k) that involve k.  Outputs are overwritten. */
+static void rhs_vjp_with_list(const orc_params* p, int64_t n, const double* u, const double* v,
+                              const double* rho, const nblist* nb, const double* abar, const double* rbar,
+                              double* gx, double* gv, double* gr)
 {
     int dim = p->dim;
     double invL = 1.0 / p->L;
-    double* abar = (double*)malloc(sizeof(double) * (size_t)dim * (size_t)(n > 0 ? n : 1));
-    double* rbar = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
-    for (int64_t i = 0; i < n; ++i) {
-        for (int k = 0; k < dim; ++k) {
-            double vt = vb[k * n + i] + p->dt * xb[k * n + i];
-            vb[k * n + i] = vt;
-            abar[k * n + i] = p->dt * vt;
-        }
-        rbar[i] = p->dt * rb[i];
-    }
-    double* gx = (double*)calloc((size_t)dim * (size_t)(n > 0 ? n : 1), sizeof(double));
-    double* gv = (double*)calloc((size_t)dim * (size_t)(n > 0 ? n : 1), sizeof(double));
-    double* gr = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t k = 0; k < n; ++k) {
         double uk[3] = {0, 0, 0}, vk[3] = {0, 0, 0}, ak[3] = {0, 0, 0};
@@ -790,6 +775,32 @@ static void step_adjoint_with_list(const orc_params* p, int64_t n, const double*
         }
         gr[k] = sr;
     }
+}
+
+/* Vector-Jacobian product of one step.  On entry (xb, vb, rb) hold the
+ * cotangents of the step's output (x', v', rho'); on exit those of its input
+ * (x, v, rho), the state at the start of the step.
+ *   v' = v + dt a(x,v,rho);  rho' = rho + dt rdot(x,v,rho);  x' = x + dt v'
+ * gives  vt = vb' + dt xb',  abar = dt vt,  rbar = dt rb',
+ *        xb = xb' + (J_x)^T,  vb = vt + (J_v)^T,  rb = rb' + (J_rho)^T. */
+static void step_adjoint_with_list(const orc_params* p, int64_t n, const double* u, const double* v,
+                                   const double* rho, const nblist* nb, double* xb, double* vb, double* rb)
+{
+    int dim = p->dim;
+    double* abar = (double*)malloc(sizeof(double) * (size_t)dim * (size_t)(n > 0 ? n : 1));
+    double* rbar = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        for (int k = 0; k < dim; ++k) {
+            double vt = vb[k * n + i] + p->dt * xb[k * n + i];
+            vb[k * n + i] = vt;
+            abar[k * n + i] = p->dt * vt;
+        }
+        rbar[i] = p->dt * rb[i];
+    }
+    double* gx = (double*)calloc((size_t)dim * (size_t)(n > 0 ? n : 1), sizeof(double));
+    double* gv = (double*)calloc((size_t)dim * (size_t)(n > 0 ? n : 1), sizeof(double));
+    double* gr = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    rhs_vjp_with_list(p, n, u, v, rho, nb, abar, rbar, gx, gv, gr);
     for (int64_t i = 0; i < n; ++i) {
         for (int c = 0; c < dim; ++c) {
             xb[c * n + i] += gx[c * n + i];
@@ -951,6 +962,142 @@ int orc_rollout(const orc_params* p, int64_t n, const double* x0, const double* 
     free(vs);
     free(rs);
     free(work);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Explicit Runge-Kutta steps from a Butcher tableau (Sec. 3.4 and the  */
+/* time-integration appendix: explicit schemes given by their tableau)  */
+/* ------------------------------------------------------------------ */
+
+/* The update function's vector-Jacobian product for one state: given the
+ * cotangents abar of a and rbar of drho/dt, (xbar, vbar, rhobar) receive the
+ * J^T terms (overwritten).  dx/dt = v is not part of it. */
+int orc_rhs_vjp(const orc_params* p, int64_t n, const double* x, const double* v, const double* rho,
+                const double* abar, const double* rbar, double* xbar, double* vbar, double* rhobar)
+{
+    if (!valid_params(p) || n < 0) return -1;
+    double* u = (double*)malloc(sizeof(double) * (size_t)p->dim * (size_t)(n > 0 ? n : 1));
+    wrap_all(p, n, x, u);
+    nblist nb;
+    build_lists(p->dim, n, x, p->L, p->H, 0, 0, &nb);
+    rhs_vjp_with_list(p, n, u, v, rho, &nb, abar, rbar, xbar, vbar, rhobar);
+    nblist_free(&nb);
+    free(u);
+    return 0;
+}
+
+/* Stage derivative k = f(u) = (v, a(u), drho/dt(u)) of the state u = (x, v, rho),
+ * packed as [x-rate (dim*n) | v-rate (dim*n) | rho-rate (n)]. */
+static void stage_rate(const orc_params* p, int64_t n, const double* x, const double* v, const double* rho,
+                       double* k)
+{
+    int dim = p->dim;
+    double* u = (double*)malloc(sizeof(double) * (size_t)dim * (size_t)(n > 0 ? n : 1));
+    wrap_all(p, n, x, u);
+    nblist nb;
+    build_lists(dim, n, x, p->L, p->H, 0, 0, &nb);
+    rhs_with_list(p, n, u, v, rho, &nb, k + (size_t)2 * dim * n, k + (size_t)dim * n, NULL);
+    nblist_free(&nb);
+    free(u);
+    memcpy(k, v, sizeof(double) * (size_t)dim * (size_t)n);
+}
+
+/* Stage states of one step: u_i = u + dt sum_{j<i} A_ij k_j, k_i = f(u_i).
+ * us and ks hold `stages` packed states / rates of (2 dim + 1) n each. */
+static void rk_stages(const orc_params* p, int64_t n, const double* x, const double* v, const double* rho,
+                      int stages, const double* A, double* us, double* ks)
+{
+    int dim = p->dim;
+    size_t m = ((size_t)2 * dim + 1) * (size_t)n;
+    for (int i = 0; i < stages; ++i) {
+        double* ui = us + (size_t)i * m;
+        memcpy(ui, x, sizeof(double) * (size_t)dim * (size_t)n);
+        memcpy(ui + (size_t)dim * n, v, sizeof(double) * (size_t)dim * (size_t)n);
+        memcpy(ui + (size_t)2 * dim * n, rho, sizeof(double) * (size_t)n);
+        for (int j = 0; j < i; ++j) {
+            double a = A[i * stages + j];
+            if (a == 0.0) continue;
+            const double* kj = ks + (size_t)j * m;
+            for (size_t e = 0; e < m; ++e) ui[e] += p->dt * a * kj[e];
+        }
+        stage_rate(p, n, ui, ui + (size_t)dim * n, ui + (size_t)2 * dim * n, ks + (size_t)i * m);
+    }
+}
+
+/* nsteps explicit Runge-Kutta steps with the tableau (A strictly lower
+ * triangular, stages x stages, row-major; weights b): u' = u + dt sum_i b_i k_i. */
+int orc_step_rk(const orc_params* p, int64_t n, double* x, double* v, double* rho, int32_t nsteps,
+                int32_t stages, const double* A, const double* b)
+{
+    if (!valid_params(p) || n < 0 || nsteps < 0 || stages < 1 || stages > 8) return -1;
+    int dim = p->dim;
+    size_t m = ((size_t)2 * dim + 1) * (size_t)n;
+    double* us = (double*)malloc(sizeof(double) * m * (size_t)stages + 1);
+    double* ks = (double*)malloc(sizeof(double) * m * (size_t)stages + 1);
+    for (int32_t t = 0; t < nsteps; ++t) {
+        rk_stages(p, n, x, v, rho, stages, A, us, ks);
+        for (int i = 0; i < stages; ++i) {
+            const double* ki = ks + (size_t)i * m;
+            double w = p->dt * b[i];
+            if (w == 0.0) continue;
+            for (int64_t e = 0; e < (int64_t)dim * n; ++e) x[e] += w * ki[e];
+            for (int64_t e = 0; e < (int64_t)dim * n; ++e) v[e] += w * ki[(size_t)dim * n + e];
+            for (int64_t e = 0; e < n; ++e) rho[e] += w * ki[(size_t)2 * dim * n + e];
+        }
+    }
+    free(us);
+    free(ks);
+    return 0;
+}
+
+/* Vector-Jacobian product of one Runge-Kutta step.  On entry (xb, vb, rb) are
+ * the cotangents of the step's output, on exit those of its input.  With the
+ * stage states u_i recomputed, stages are taken in reverse:
+ *   kbar_i = dt b_i ubar' + dt sum_{l>i} A_li Ubar_l,
+ *   Ubar_i = (df/du at u_i)^T kbar_i
+ *          = (J_x^T, kbar_x + J_v^T, J_rho^T) applied to (kbar_v, kbar_rho),
+ * and ubar = ubar' + sum_i Ubar_i. */
+int orc_step_rk_adjoint(const orc_params* p, int64_t n, const double* x, const double* v, const double* rho,
+                        int32_t stages, const double* A, const double* b, double* xb, double* vb, double* rb)
+{
+    if (!valid_params(p) || n < 0 || stages < 1 || stages > 8) return -1;
+    int dim = p->dim;
+    size_t dn = (size_t)dim * (size_t)n, m = 2 * dn + (size_t)n;
+    double* us = (double*)malloc(sizeof(double) * m * (size_t)stages + 1);
+    double* ks = (double*)malloc(sizeof(double) * m * (size_t)stages + 1);
+    double* Ub = (double*)calloc(m * (size_t)stages + 1, sizeof(double));
+    double* kb = (double*)malloc(sizeof(double) * m + 1);
+    double* out = (double*)malloc(sizeof(double) * m + 1);
+    rk_stages(p, n, x, v, rho, stages, A, us, ks);
+    for (int i = stages - 1; i >= 0; --i) {
+        for (size_t e = 0; e < dn; ++e) kb[e] = p->dt * b[i] * xb[e];
+        for (size_t e = 0; e < dn; ++e) kb[dn + e] = p->dt * b[i] * vb[e];
+        for (size_t e = 0; e < (size_t)n; ++e) kb[2 * dn + e] = p->dt * b[i] * rb[e];
+        for (int l = i + 1; l < stages; ++l) {
+            double a = A[l * stages + i];
+            if (a == 0.0) continue;
+            const double* Ul = Ub + (size_t)l * m;
+            for (size_t e = 0; e < m; ++e) kb[e] += p->dt * a * Ul[e];
+        }
+        const double* ui = us + (size_t)i * m;
+        orc_rhs_vjp(p, n, ui, ui + dn, ui + 2 * dn, kb + dn, kb + 2 * dn, out, out + dn, out + 2 * dn);
+        double* Ui = Ub + (size_t)i * m;
+        for (size_t e = 0; e < dn; ++e) Ui[e] = out[e];
+        for (size_t e = 0; e < dn; ++e) Ui[dn + e] = kb[e] + out[dn + e];
+        for (size_t e = 0; e < (size_t)n; ++e) Ui[2 * dn + e] = out[2 * dn + e];
+    }
+    for (int i = 0; i < stages; ++i) {
+        const double* Ui = Ub + (size_t)i * m;
+        for (size_t e = 0; e < dn; ++e) xb[e] += Ui[e];
+        for (size_t e = 0; e < dn; ++e) vb[e] += Ui[dn + e];
+        for (size_t e = 0; e < (size_t)n; ++e) rb[e] += Ui[2 * dn + e];
+    }
+    free(us);
+    free(ks);
+    free(Ub);
+    free(kb);
+    free(out);
     return 0;
 }
 
