@@ -135,6 +135,23 @@ sph_status sph_plan_info(const sph_plan* plan, int64_t* total_particles, int32_t
 sph_status sph_set_tuning(sph_plan* plan, int32_t lanes_fwd, int32_t lanes_adj);
 sph_status sph_get_tuning(const sph_plan* plan, int32_t* lanes_fwd, int32_t* lanes_adj);
 
+/* Time integrator (Sec. 3.4; the time-stepping appendix describes explicit
+ * schemes by their Butcher tableau).  stages = 0 selects the default
+ * semi-implicit Euler step (v' = v + dt a, rho' = rho + dt drho/dt,
+ * x' = x + dt v').  stages = 1..4 selects the explicit Runge-Kutta scheme with
+ * the tableau A (host, stages x stages, row-major, strictly lower triangular)
+ * and weights b (host, stages) for the state u = (x, v, rho) with
+ * du/dt = f(u) = (v, a(u), drho/dt(u)):
+ *     u_i = u + dt sum_{j<i} A_ij k_i,  k_i = f(u_i),  u' = u + dt sum_i b_i k_i,
+ * every stage with its own sort and neighbour lists (a reuse interval applies
+ * to the semi-implicit Euler step only).  sph_step, sph_step_adjoint and
+ * sph_rollout_backward then use the scheme; the adjoint reverses the stages
+ * over the update function's VJP.  The first call with stages > 0 reserves the
+ * stage storage and so grows sph_workspace_size(): make it before sph_bind
+ * (CAPACITY afterwards).  INVALID_ARG for stages outside 0..4, null arrays,
+ * non-finite entries, or a tableau that is not explicit. */
+sph_status sph_set_integrator(sph_plan* plan, int32_t stages, const double* A, const double* b);
+
 /* Neighbour-list reuse (Verlet lists; the paper keeps one list for short rollouts,
  * Sec. 4.1).  With rebuild_every = R > 1 (needs a skin in every simulation's
  * parameters), a step sorts and rebuilds its lists only when its index within the

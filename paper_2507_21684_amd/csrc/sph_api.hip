@@ -81,6 +81,11 @@ struct sph_plan {
     bool filter = false;      // some simulation has a skin: sweeps keep only pairs with r < H
     int32_t reuse = 1;        // a step rebuilds the cell list and the lists every `reuse` steps
     std::vector<int> list_of; // tape slot -> slot whose neighbour lists it uses
+    // explicit Runge-Kutta tableau (0 stages: the semi-implicit Euler step)
+    int32_t rk_stages = 0, rk_reserved = 0;
+    double rk_A[kMaxStages * kMaxStages] = {}, rk_b[kMaxStages] = {};
+    size_t bytes_base = 0, state_block = 0;
+    size_t o_rkU = 0, o_rkK = 0, o_rkUb = 0, o_rkB0 = 0, o_rkTape = 0;
     int64_t N = 0;
     int64_t ncell = 0, nblk = 0;
     std::vector<sph_params> prm;
@@ -391,19 +396,22 @@ sph_status unsort_from(sph_plan* P, StatePtrs<T, D> src, int slot, StatePtrs<T, 
 }
 
 template <typename T, int D, int LPP>
-void launch_adj(sph_plan* P, const SlotLayout& L, const SlotLayout& LL, StatePtrs<T, D> cot, hipStream_t st)
+void launch_adj(sph_plan* P, const SlotLayout& L, const SlotLayout& LL, StatePtrs<T, D> cot, hipStream_t st,
+                bool vjp)
 {
     const int64_t lanes = P->N * LPP;
     k_adj_sweep<T, D, LPP><<<grid_for(lanes, 256), 256, 0, st>>>(
         P->N, P->width, wsp<int32_t>(P, LL.nbr), wsp<int32_t>(P, LL.cnt), wsp<vec4_t<T>>(P, L.jd0),
         wsp<vec4_t<T>>(P, L.jd1), wsp<vec4_t<T>>(P, P->o_jdA), wsp<vec4_t<T>>(P, P->o_jdB), wsp<int32_t>(P, L.orig),
         cot, wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc), wsp<int32_t>(P, P->o_status),
-        P->filter ? 1 : 0);
+        P->filter ? 1 : 0, vjp ? 1 : 0);
 }
 
 // Adjoint of the step that starts from the state in `slot` (sorted with its lists built).
+// With vjp, the update function's VJP instead: cot holds the cotangents (kx, ka, krho) of
+// (v, a, drho/dt) on entry and (xbar, vbar, rhobar) on exit.
 template <typename T, int D>
-sph_status adjoint(sph_plan* P, int slot, StatePtrs<T, D> cot, hipStream_t st)
+sph_status adjoint(sph_plan* P, int slot, StatePtrs<T, D> cot, hipStream_t st, bool vjp = false)
 {
     if (P->N == 0) return SPH_OK;
     const SlotLayout& L = P->slot[slot];
@@ -411,15 +419,15 @@ sph_status adjoint(sph_plan* P, int slot, StatePtrs<T, D> cot, hipStream_t st)
         ProfScope prof(P, st, SPH_KERN_OTHER);
         k_adj_prologue<T, D><<<grid_for(P->N, 256), 256, 0, st>>>(
             P->N, wsp<int32_t>(P, L.orig), cot, ws_state<T, D>(P, L.SA), wsp<vec4_t<T>>(P, P->o_jdA),
-            wsp<vec4_t<T>>(P, P->o_jdB), wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc));
+            wsp<vec4_t<T>>(P, P->o_jdB), wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc), vjp ? 1 : 0);
         LAUNCH_CHECK("adj_prologue");
     }
     ProfScope prof(P, st, SPH_KERN_ADJOINT);
     const SlotLayout& LL = P->slot[P->list_of[slot]];
     switch (P->lpp_adj) {
-    case 2: launch_adj<T, D, 2>(P, L, LL, cot, st); break;
-    case 8: launch_adj<T, D, 8>(P, L, LL, cot, st); break;
-    default: launch_adj<T, D, 4>(P, L, LL, cot, st); break;
+    case 2: launch_adj<T, D, 2>(P, L, LL, cot, st, vjp); break;
+    case 8: launch_adj<T, D, 8>(P, L, LL, cot, st, vjp); break;
+    default: launch_adj<T, D, 4>(P, L, LL, cot, st, vjp); break;
     }
     LAUNCH_CHECK("adj_sweep");
     return SPH_OK;
@@ -518,11 +526,127 @@ sph_status run_steps(sph_plan* P, StatePtrs<T, D> src, int32_t nsteps, bool tape
     return SPH_OK;
 }
 
+// ---------------------------------------------------------------- explicit Runge-Kutta steps
+
+template <typename T, int D>
+StatePtrs<T, D> rk_block(const sph_plan* P, size_t base, int i)
+{
+    return ws_state<T, D>(P, base + (size_t)i * P->state_block);
+}
+
+template <typename T, int D>
+sph_status lincomb(sph_plan* P, StatePtrs<T, D> out, StatePtrs<T, D> base, double s0, bool s0_dt, int n,
+                   const double* c, const StatePtrs<T, D>* K, bool c_dt, hipStream_t st)
+{
+    if (P->N == 0) return SPH_OK;
+    LinComb<T, D> L{};
+    L.out = out;
+    L.base = base;
+    L.s0 = (T)s0;
+    L.s0_dt = s0_dt ? 1 : 0;
+    L.c_dt = c_dt ? 1 : 0;
+    L.nterm = n;
+    for (int j = 0; j < n; ++j) {
+        L.c[j] = (T)c[j];
+        L.K[j] = K[j];
+    }
+    ProfScope prof(P, st, SPH_KERN_OTHER);
+    k_lincomb<T, D><<<grid_for(P->N, 256), 256, 0, st>>>(P->N, L, wsp<int32_t>(P, P->o_psim),
+                                                         wsp<SimConst<T>>(P, P->o_simc));
+    LAUNCH_CHECK("lincomb");
+    return SPH_OK;
+}
+
+// Stage states and rates of one Runge-Kutta step from u (original order): u_i = u + dt
+// sum_{j<i} A_ij k_j (u_0 = u itself), k_i = f(u_i) = (v_i, a(u_i), drho/dt(u_i)), each rate
+// from a sort, a list build and a right-hand-side sweep of the stage state.  The x-rate of
+// a stage is its velocity, so K[i].x refers to U[i].v.
+template <typename T, int D>
+sph_status rk_stages(sph_plan* P, StatePtrs<T, D> u, StatePtrs<T, D>* U, StatePtrs<T, D>* K, hipStream_t st)
+{
+    const int s = P->rk_stages;
+    for (int i = 0; i < s; ++i) {
+        U[i] = (i == 0) ? u : rk_block<T, D>(P, P->o_rkU, i);
+        if (i > 0) {
+            double c[kMaxStages];
+            StatePtrs<T, D> Ks[kMaxStages];
+            int n = 0;
+            for (int j = 0; j < i; ++j)
+                if (P->rk_A[i * kMaxStages + j] != 0.0) {
+                    c[n] = P->rk_A[i * kMaxStages + j];
+                    Ks[n++] = K[j];
+                }
+            RC_TRY((lincomb<T, D>(P, U[i], u, 1.0, false, n, c, Ks, true, st)));
+        }
+        K[i] = rk_block<T, D>(P, P->o_rkK, i);
+        RC_TRY((sort_into<T, D>(P, U[i], nullptr, 0, st)));
+        RC_TRY((build_lists<T, D>(P, 0, st)));
+        RC_TRY((sweep<T, D, kModeRhs>(P, 0, K[i].rho, K[i].v[0], nullptr, st)));
+        for (int k = 0; k < 3; ++k) K[i].x[k] = U[i].v[k];
+    }
+    return SPH_OK;
+}
+
+// One Runge-Kutta step of u in place: u <- u + dt sum_i b_i k_i.
+template <typename T, int D>
+sph_status rk_step(sph_plan* P, StatePtrs<T, D> u, hipStream_t st)
+{
+    StatePtrs<T, D> U[kMaxStages], K[kMaxStages];
+    RC_TRY((rk_stages<T, D>(P, u, U, K, st)));
+    double c[kMaxStages];
+    StatePtrs<T, D> Ks[kMaxStages];
+    int n = 0;
+    for (int i = 0; i < P->rk_stages; ++i)
+        if (P->rk_b[i] != 0.0) {
+            c[n] = P->rk_b[i];
+            Ks[n++] = K[i];
+        }
+    return lincomb<T, D>(P, u, u, 1.0, false, n, c, Ks, true, st);
+}
+
+// Vector-Jacobian product of one Runge-Kutta step started at u, cot in place (output
+// cotangents in, input cotangents out).  Stages in reverse: kbar_i = dt b_i ubar' + dt
+// sum_{l>i} A_li Ubar_l, Ubar_i = (df/du at u_i)^T kbar_i (the adjoint sweep's VJP mode), and
+// ubar = ubar' + sum_i Ubar_i.
+template <typename T, int D>
+sph_status rk_step_adjoint(sph_plan* P, StatePtrs<T, D> u, StatePtrs<T, D> cot, hipStream_t st)
+{
+    const int s = P->rk_stages;
+    StatePtrs<T, D> U[kMaxStages], K[kMaxStages], Ub[kMaxStages];
+    RC_TRY((rk_stages<T, D>(P, u, U, K, st)));
+    const StatePtrs<T, D> B0 = rk_block<T, D>(P, P->o_rkB0, 0);
+    RC_TRY((lincomb<T, D>(P, B0, cot, 1.0, false, 0, nullptr, nullptr, false, st)));
+    for (int i = s - 1; i >= 0; --i) {
+        Ub[i] = rk_block<T, D>(P, P->o_rkUb, i);
+        double c[kMaxStages];
+        StatePtrs<T, D> Ks[kMaxStages];
+        int n = 0;
+        for (int l = i + 1; l < s; ++l)
+            if (P->rk_A[l * kMaxStages + i] != 0.0) {
+                c[n] = P->rk_A[l * kMaxStages + i];
+                Ks[n++] = Ub[l];
+            }
+        RC_TRY((lincomb<T, D>(P, Ub[i], B0, P->rk_b[i], true, n, c, Ks, true, st)));
+        RC_TRY((sort_into<T, D>(P, U[i], nullptr, 0, st)));
+        RC_TRY((build_lists<T, D>(P, 0, st)));
+        RC_TRY((adjoint<T, D>(P, 0, Ub[i], st, true)));
+    }
+    double ones[kMaxStages] = {1.0, 1.0, 1.0, 1.0};
+    return lincomb<T, D>(P, cot, B0, 1.0, false, s, ones, Ub, false, st);
+}
+
 template <typename T, int D>
 sph_status do_step(sph_plan* P, sph_state* s, int32_t nsteps, const sph_state* ckpt, int32_t every, hipStream_t st)
 {
     if (nsteps == 0) return SPH_OK;
     StatePtrs<T, D> user = user_state<T, D>(s);
+    if (P->rk_stages > 0) {
+        for (int32_t t = 0; t < nsteps; ++t) {
+            if (ckpt && t % every == 0) RC_TRY((copy_state<T, D>(P, user_state<T, D>(&ckpt[t / every]), user, st)));
+            RC_TRY((rk_step<T, D>(P, user, st)));
+        }
+        return SPH_OK;
+    }
     if (ckpt) RC_TRY((copy_state<T, D>(P, user_state<T, D>(&ckpt[0]), user, st)));
     int last = 0;
     RC_TRY((run_steps<T, D>(P, user, nsteps, false, true, ckpt, every, &last, st)));
@@ -532,6 +656,7 @@ sph_status do_step(sph_plan* P, sph_state* s, int32_t nsteps, const sph_state* c
 template <typename T, int D>
 sph_status do_step_adjoint(sph_plan* P, const sph_state* sn, sph_state* cot, hipStream_t st)
 {
+    if (P->rk_stages > 0) return rk_step_adjoint<T, D>(P, user_state<T, D>(sn), user_state<T, D>(cot), st);
     RC_TRY((sort_into<T, D>(P, user_state<T, D>(sn), nullptr, 0, st)));
     RC_TRY((build_lists<T, D>(P, 0, st)));
     return adjoint<T, D>(P, 0, user_state<T, D>(cot), st);
@@ -547,6 +672,21 @@ sph_status do_rollout_backward(sph_plan* P, const sph_state* ckpt, int32_t nstep
     if (nsteps == 0) return SPH_OK;
     const int32_t nseg = (nsteps + every - 1) / every;
     StatePtrs<T, D> c = user_state<T, D>(cot);
+    if (P->rk_stages > 0) {
+        // each segment's step states recomputed into the state tape, then the step VJPs
+        for (int32_t seg = nseg - 1; seg >= 0; --seg) {
+            const int32_t len = std::min(every, nsteps - seg * every);
+            RC_TRY((copy_state<T, D>(P, rk_block<T, D>(P, P->o_rkTape, 0), user_state<T, D>(&ckpt[seg]), st)));
+            for (int32_t t = 0; t + 1 < len; ++t) {
+                RC_TRY((copy_state<T, D>(P, rk_block<T, D>(P, P->o_rkTape, t + 1), rk_block<T, D>(P, P->o_rkTape, t),
+                                         st)));
+                RC_TRY((rk_step<T, D>(P, rk_block<T, D>(P, P->o_rkTape, t + 1), st)));
+            }
+            for (int32_t t = len - 1; t >= 0; --t)
+                RC_TRY((rk_step_adjoint<T, D>(P, rk_block<T, D>(P, P->o_rkTape, t), c, st)));
+        }
+        return SPH_OK;
+    }
     for (int32_t seg = nseg - 1; seg >= 0; --seg) {
         const int32_t len = std::min(every, nsteps - seg * every);
         int last = 0;
@@ -568,6 +708,7 @@ sph_status run_graphed(sph_plan* P, std::vector<uintptr_t> key, hipStream_t st, 
     key.push_back((uintptr_t)P->lpp_fwd);
     key.push_back((uintptr_t)P->lpp_adj);
     key.push_back((uintptr_t)P->reuse);
+    key.push_back((uintptr_t)P->rk_stages);
     for (auto& g : P->gcache) {
         if (g.key == key) {
             g.used = ++P->gclock;
@@ -861,6 +1002,8 @@ sph_status sph_plan_create(const sph_params* sims, int32_t nsims, const int64_t*
         L.nbr = take(4 * (size_t)P->width * N);
         L.cnt = take(4 * N);
     }
+    P->bytes_base = off;
+    P->state_block = align_up(T * N * (2 * d + 1), A);
     P->bytes = off;
     *out = P;
     return SPH_OK;
@@ -891,6 +1034,48 @@ sph_status sph_set_tuning(sph_plan* plan, int32_t lanes_fwd, int32_t lanes_adj)
     if (!ok(lanes_fwd) || !ok(lanes_adj)) return fail(SPH_ERR_INVALID_ARG, "lanes per particle must be 2, 4 or 8");
     plan->lpp_fwd = lanes_fwd;
     plan->lpp_adj = lanes_adj;
+    return SPH_OK;
+}
+
+sph_status sph_set_integrator(sph_plan* P, int32_t stages, const double* A, const double* b)
+{
+    if (!P) return fail(SPH_ERR_INVALID_ARG, "plan is null");
+    if (stages < 0 || stages > kMaxStages) return fail(SPH_ERR_INVALID_ARG, "stages must be 0..4");
+    if (stages > 0 && (!A || !b)) return fail(SPH_ERR_INVALID_ARG, "tableau arrays are null");
+    for (int i = 0; i < stages; ++i) {
+        if (!std::isfinite(b[i])) return fail(SPH_ERR_INVALID_ARG, "non-finite tableau weight");
+        for (int j = 0; j < stages; ++j) {
+            const double a = A[i * stages + j];
+            if (!std::isfinite(a) || (j >= i && a != 0.0))
+                return fail(SPH_ERR_INVALID_ARG, "the tableau must be explicit (A strictly lower triangular)");
+        }
+    }
+    if (stages > P->rk_reserved) {
+        if (P->bound) return fail(SPH_ERR_CAPACITY, "more stages than reserved when the workspace was bound");
+        // stage states, stage rates, stage cotangents, the output cotangent and a state tape
+        size_t off = P->bytes_base;
+        const size_t sb = P->state_block;
+        P->o_rkU = off;
+        off += kMaxStages * sb;
+        P->o_rkK = off;
+        off += kMaxStages * sb;
+        P->o_rkUb = off;
+        off += kMaxStages * sb;
+        P->o_rkB0 = off;
+        off += sb;
+        P->o_rkTape = off;
+        off += (size_t)std::max(1, P->tape_depth) * sb;
+        P->bytes = off;
+        P->rk_reserved = kMaxStages;
+    }
+    P->rk_stages = stages;
+    std::fill(P->rk_A, P->rk_A + kMaxStages * kMaxStages, 0.0);
+    std::fill(P->rk_b, P->rk_b + kMaxStages, 0.0);
+    for (int i = 0; i < stages; ++i) {
+        P->rk_b[i] = b[i];
+        for (int j = 0; j < i; ++j) P->rk_A[i * kMaxStages + j] = A[i * stages + j];
+    }
+    P->clear_graphs();
     return SPH_OK;
 }
 

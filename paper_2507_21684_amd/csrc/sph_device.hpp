@@ -1069,6 +1069,56 @@ __global__ __launch_bounds__(256) void k_density_adj(int64_t N, int32_t width, c
     for (int k = 0; k < DIM; ++k) xbar[(int64_t)k * N + o] = S.m * out[k];
 }
 
+// ---------------------------------------------------------------- explicit Runge-Kutta stages
+
+// out = s0 base + sum_j c[j] K[j] over every field of the states (original order), with up to
+// four terms; out may be base (every element is read before it is written).  s0 and the c[j]
+// are multiplied by the particle's simulation time step when s0_dt / c_dt are set.  Stage
+// states u_i = u + dt sum_j A_ij k_j, the step's end u + dt sum_i b_i k_i, and the adjoint's
+// stage cotangents are all of this form.
+constexpr int kMaxStages = 4;
+
+template <typename T, int DIM>
+struct LinComb {
+    StatePtrs<T, DIM> out, base;
+    T s0;
+    int s0_dt, c_dt, nterm;
+    T c[kMaxStages];
+    StatePtrs<T, DIM> K[kMaxStages];
+};
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_lincomb(int64_t N, LinComb<T, DIM> L, const int32_t* __restrict__ psim,
+                                                 const SimConst<T>* __restrict__ sims)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const T dt = sims[psim[i]].dt;
+    const T s0 = L.s0_dt ? L.s0 * dt : L.s0;
+    T x[3], v[3], r;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        x[k] = s0 * L.base.x[k][i];
+        v[k] = s0 * L.base.v[k][i];
+    }
+    r = s0 * L.base.rho[i];
+    for (int j = 0; j < L.nterm; ++j) {
+        const T c = L.c_dt ? L.c[j] * dt : L.c[j];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            x[k] += c * L.K[j].x[k][i];
+            v[k] += c * L.K[j].v[k][i];
+        }
+        r += c * L.K[j].rho[i];
+    }
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        L.out.x[k][i] = x[k];
+        L.out.v[k][i] = v[k];
+    }
+    L.out.rho[i] = r;
+}
+
 // ---------------------------------------------------------------- unsort
 
 template <typename T, int DIM>
@@ -1095,16 +1145,25 @@ __global__ __launch_bounds__(256) void k_adj_prologue(int64_t N, const int32_t* 
                                                       StatePtrs<T, DIM> cot, StatePtrs<T, DIM> cur,
                                                       vec4_t<T>* __restrict__ jdA, vec4_t<T>* __restrict__ jdB,
                                                       const int32_t* __restrict__ psim,
-                                                      const SimConst<T>* __restrict__ sims)
+                                                      const SimConst<T>* __restrict__ sims, int vjp)
 {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= N) return;
     const SimConst<T>& S = sims[psim[q]];
     const int o = orig[q];
     T ab[3] = {0, 0, 0};
+    T rb;
+    if (vjp) {
+        // the update function's VJP: cot holds the cotangents (kx, ka, krho) of (v, a, drho/dt)
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) ab[k] = S.dt * (cot.v[k][o] + S.dt * cot.x[k][o]);
-    const T rb = S.dt * cot.rho[o];
+        for (int k = 0; k < DIM; ++k) ab[k] = cot.v[k][o];
+        rb = cot.rho[o];
+    } else {
+        // one semi-implicit Euler step: abar = dt (vbar' + dt xbar'), rbar = dt rhobar'
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) ab[k] = S.dt * (cot.v[k][o] + S.dt * cot.x[k][o]);
+        rb = S.dt * cot.rho[o];
+    }
     vec4_t<T> a;
     if (DIM == 3) {
         a.x = ab[0]; a.y = ab[1]; a.z = ab[2]; a.w = rb;
@@ -1214,7 +1273,7 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
                                                    const int32_t* __restrict__ orig, StatePtrs<T, DIM> cot,
                                                    const int32_t* __restrict__ psim,
                                                    const SimConst<T>* __restrict__ sims, int32_t* __restrict__ status,
-                                                   int filter)
+                                                   int filter, int vjp)
 {
     constexpr int NQ = kLeaves / LPP;
     constexpr int U = kPairsInFlight;
@@ -1295,11 +1354,17 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
     for (int d = 0; d < DIM; ++d) {
         const T xb = cot.x[d][o];
         const T vb = cot.v[d][o];
-        cot.x[d][o] = xb + gx[d];
-        cot.v[d][o] = vb + dt * xb + gv[d];
+        if (vjp) {
+            // (xbar, vbar, rhobar) = (J_x^T, kx + J_v^T, J_rho^T): dx/dt = v adds kx to vbar
+            cot.x[d][o] = gx[d];
+            cot.v[d][o] = xb + gv[d];
+        } else {
+            cot.x[d][o] = xb + gx[d];
+            cot.v[d][o] = vb + dt * xb + gv[d];
+        }
         bad = bad || !isfinite(gx[d]) || !isfinite(gv[d]);
     }
-    cot.rho[o] = cot.rho[o] + gr;
+    cot.rho[o] = vjp ? gr : cot.rho[o] + gr;
     if (bad) atomicOr(&status[s], kFlagNonfinite);
 }
 

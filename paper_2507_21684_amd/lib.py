@@ -65,6 +65,9 @@ def lib():
         L.sph_density_adjoint.restype = st
         L.sph_density_adjoint.argtypes = [_VP, ctypes.POINTER(SphState), _VP, _VP, _VP]
         L.sph_set_graphs.argtypes = [_VP, ctypes.c_int32]
+        L.sph_set_integrator.restype = st
+        L.sph_set_integrator.argtypes = [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double)]
         L.sph_set_reuse.restype = st
         L.sph_set_reuse.argtypes = [_VP, ctypes.c_int32]
         L.sph_set_graphs.restype = ctypes.c_int32
@@ -117,10 +120,37 @@ def exported_symbols() -> List[str]:
     return ["sph_plan_create", "sph_plan_destroy", "sph_workspace_size", "sph_plan_info", "sph_bind",
             "sph_build_cells", "sph_neighbors", "sph_rhs", "sph_step", "sph_step_adjoint", "sph_poll",
             "sph_pair_count", "sph_profile_enable", "sph_profile_read", "sph_last_error", "sph_set_tuning",
-            "sph_get_tuning", "sph_rollout_backward", "sph_set_graphs", "sph_density_adjoint", "sph_set_reuse"]
+            "sph_get_tuning", "sph_rollout_backward", "sph_set_graphs", "sph_density_adjoint", "sph_set_reuse",
+            "sph_set_integrator"]
 
 
 KERNEL_CLASSES = ["sort", "build", "sweep", "adjoint", "other"]
+
+# Explicit Runge-Kutta tableaus (A strictly lower triangular, weights b); None is the default
+# semi-implicit Euler step.
+TABLEAUS = {
+    "semi_implicit_euler": None,
+    "explicit_euler": ([[0.0]], [1.0]),
+    "midpoint": ([[0.0, 0.0], [0.5, 0.0]], [0.0, 1.0]),
+    "heun": ([[0.0, 0.0], [1.0, 0.0]], [0.5, 0.5]),
+    "rk4": ([[0.0, 0.0, 0.0, 0.0], [0.5, 0.0, 0.0, 0.0], [0.0, 0.5, 0.0, 0.0], [0.0, 0.0, 1.0, 0.0]],
+            [1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0]),
+}
+
+
+def _set_integrator(handle, integrator):
+    """integrator: a TABLEAUS name, (A, b), or None."""
+    tab = TABLEAUS[integrator] if isinstance(integrator, str) or integrator is None else integrator
+    if isinstance(integrator, str) and integrator not in TABLEAUS:
+        raise ValueError("unknown integrator %r" % integrator)
+    if tab is None:
+        _check(lib().sph_set_integrator(handle, 0, None, None))
+        return
+    A = np.ascontiguousarray(np.asarray(tab[0], dtype=np.float64))
+    b = np.ascontiguousarray(np.asarray(tab[1], dtype=np.float64))
+    n = int(b.shape[0])
+    _check(lib().sph_set_integrator(handle, n, A.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
 
 
 def _skins(skin, n: int) -> List[float]:
@@ -168,7 +198,7 @@ class Plan:
 
     def __init__(self, sims: Sequence[dict], counts: Sequence[int], dtype: str = "f32",
                  max_neighbors: int = 0, tape_depth: int = 8, device: Optional[torch.device] = None,
-                 stream=None, skin=0.0, rebuild_every: int = 1):
+                 stream=None, skin=0.0, rebuild_every: int = 1, integrator=None):
         L = lib()
         self.dtype = dtype
         self.torch_dtype = torch.float64 if dtype == "f64" else torch.float32
@@ -179,6 +209,13 @@ class Plan:
         cnt = (ctypes.c_int64 * n)(*[int(c) for c in counts])
         h = _VP()
         _check(L.sph_plan_create(arr, n, cnt, int(max_neighbors), int(tape_depth), ctypes.byref(h)))
+        if integrator is not None:
+            try:
+                _set_integrator(h, integrator)   # before the workspace is sized
+            except Exception:
+                L.sph_plan_destroy(h)
+                raise
+        self.integrator = integrator or "semi_implicit_euler"
         self.tape_depth = int(tape_depth)
         self.skins = skins
         self.skin = max(skins) if skins else 0.0

@@ -121,3 +121,35 @@ def test_tape_depth_validation():
     spec = SimSpec(2, 16)
     rc, _ = _plan([_p(spec)], [spec.n], 0, -1)
     assert rc == -1
+
+
+def test_integrator_settings_on_an_unbound_plan():
+    """Tableau checks and the stage storage it reserves (host-only calls)."""
+    import ctypes
+    import numpy as np
+    from paper_2507_21684_amd.inputs import SimSpec
+    spec = SimSpec(2, 32)
+    arr = (L.SphParams * 1)(L.make_params(spec.params(), "f32"))
+    cnt = (ctypes.c_int64 * 1)(spec.n)
+    h = L._VP()
+    assert L.lib().sph_plan_create(arr, 1, cnt, 0, 4, ctypes.byref(h)) == 0
+    size0 = ctypes.c_size_t()
+    L.lib().sph_workspace_size(h, ctypes.byref(size0))
+    dp = ctypes.POINTER(ctypes.c_double)
+
+    def setp(A, b):
+        A = np.ascontiguousarray(A, dtype=np.float64)
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        return L.lib().sph_set_integrator(h, len(b), A.ctypes.data_as(dp), b.ctypes.data_as(dp))
+
+    A, b = L.TABLEAUS["rk4"]
+    assert setp(A, b) == 0
+    size1 = ctypes.c_size_t()
+    L.lib().sph_workspace_size(h, ctypes.byref(size1))
+    assert size1.value > size0.value
+    assert setp([[0.0, 1.0], [0.0, 0.0]], [0.5, 0.5]) == -1     # not explicit
+    assert setp([[0.5, 0.0], [0.5, 0.0]], [0.5, 0.5]) == -1     # diagonal entry
+    assert setp(np.zeros((5, 5)), np.ones(5) / 5) == -1          # too many stages
+    assert setp([[0.0]], [float("nan")]) == -1
+    assert L.lib().sph_set_integrator(h, 0, None, None) == 0    # back to semi-implicit Euler
+    L.lib().sph_plan_destroy(h)
