@@ -325,6 +325,41 @@ def bench_density_backward(dev, reps=20):
                     "(2 list builds); median of %d on events around each phase" % reps}
 
 
+def bench_rk4(dev, reps=3):
+    """Classic RK4 (four right-hand sides per step) on the 2D 256^2 FP32 state: 16 steps with a
+    checkpoint every 8 and the checkpointed backward; pair interactions of every stage's RHS
+    and VJP per second."""
+    import numpy as np
+    import torch
+    from paper_2507_21684_amd import inputs as I
+    from paper_2507_21684_amd.lib import Plan
+    from paper_2507_21684_amd.rollout import rollout
+    spec = I.SimSpec(2, 256)
+    T, K = 16, 8
+    x0, v0, r0 = (torch.tensor(a.astype(np.float32), device=dev) for a in I.make_state(spec, 0))
+    plan = Plan([spec.params()], [spec.n], "f32", tape_depth=K, device=dev, integrator="rk4")
+
+    def job():
+        v = v0.clone().requires_grad_(True)
+        xT, vT, rT = rollout(plan, x0.clone(), v, r0.clone(), T, K)
+        (vT ** 2).sum().backward()
+
+    job()
+    torch.cuda.synchronize()
+    plan.pair_count()
+    xs, vs, rs = x0.clone(), v0.clone(), r0.clone()
+    plan.step(xs, vs, rs, T)
+    pairs = plan.pair_count()          # every stage's right-hand side of the forward pass
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        job()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    return {"workload": "rk4_tgv2d_64k_f32", "steps": T, "ckpt_every": K, "ms_per_job": round(t * 1e3, 3),
+            "pair_interactions": 2 * pairs, "value": round(2 * pairs / t, 1), "unit": "pair interactions/s",
+            "note": "4 right-hand sides per step forward and 4 stage VJPs per step backward are counted"}
+
+
 def log(msg):
     """Progress line on stderr (the JSON result is the only line on stdout)."""
     print("[bench] " + msg, file=sys.stderr, flush=True)
@@ -474,6 +509,11 @@ def main():
         log("density backward benchmark")
         dens = bench_density_backward(dev)
 
+    rk4 = None
+    if args.workload == "tgv2d_64k_f32":
+        log("RK4 job")
+        rk4 = bench_rk4(dev)
+
     served = None
     if args.serving > 0 and args.workload != "batched_512_tgv2d_f32":
         torch.cuda.empty_cache()
@@ -491,7 +531,7 @@ def main():
                       "lanes_per_particle": list(lanes), "list_skin": list_skin,
                       "list_rebuild_every": list_rebuild},
            "roofline": roof, "kernel_ms_per_job": breakdown, "cpu_baseline": cpu, "batched": batched, "serving": served,
-           "density_backward": dens}
+           "density_backward": dens, "rk4": rk4}
     print(json.dumps(out), flush=True)
 
 
