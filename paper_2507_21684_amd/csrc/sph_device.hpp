@@ -681,6 +681,18 @@ __device__ __forceinline__ V ldo(const V* __restrict__ base, uint32_t idx)
     return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(V));
 }
 
+// List entries of lane r at its positions m0 .. m0 + U - 1 (position k = r + LPP m of the row);
+// positions past the lane's count read as the particle itself, a valid index whose pair is
+// skipped.  The sweeps load the next group's entries before computing the current one, so
+// that only the record gathers stand between consecutive groups.
+template <int LPP, int U>
+__device__ __forceinline__ void load_entries(const int32_t* __restrict__ row, int r, int m0, int mcount, int self,
+                                             int* jj)
+{
+#pragma unroll
+    for (int u = 0; u < U; ++u) jj[u] = (m0 + u < mcount) ? row[r + LPP * (m0 + u)] : self;
+}
+
 // FP32 sweeps use the hardware reciprocal and square root (about 1 ulp); FP64 keeps IEEE
 // division and square root.
 template <typename T> __device__ __forceinline__ T fast_rcp(T x) { return T(1) / x; }
@@ -816,8 +828,9 @@ struct NextCells {
 
 // The neighbour list positions of lane r among the LPP lanes of a particle are
 // k = r + LPP m (m = 0, 1, ...); position k belongs to partial sum k mod 8, which is
-// accumulator m mod (8 / LPP) of the lane.  Lanes load kPairsInFlight positions before
-// computing them, in increasing m.
+// accumulator m mod (8 / LPP) of the lane.  Lanes gather the records of kPairsInFlight
+// positions before computing them, in increasing m, with the list entries of the following
+// group already in flight.
 template <typename T, int DIM, int MODE, int LPP>
 __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const int32_t* __restrict__ nbr,
                                                const int32_t* __restrict__ nbr_count,
@@ -857,18 +870,21 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
         acc[q].ax[0] = acc[q].ax[1] = acc[q].ax[2] = T(0);
         acc[q].rdv = acc[q].rdd = acc[q].rs = T(0);
     }
+    int jn[U];
+    load_entries<LPP, U>(row, r, 0, mcount, (int)i, jn);
     for (int m0 = 0; m0 < mcount; m0 += U) {
         int jj[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) jj[u] = (m0 + u < mcount) ? row[r + LPP * (m0 + u)] : 0;
+        for (int u = 0; u < U; ++u) jj[u] = jn[u];
         FwdNbr<T, DIM> nb[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint32_t j = (m0 + u < mcount) ? (uint32_t)jj[u] : (uint32_t)i;
+            const uint32_t j = (uint32_t)jj[u];
             nb[u].a = ldo(jd0, j);
             nb[u].b = ldo(jd1, j);
             nb[u].rho = (DIM == 3) ? ldo(cur.rho, j) : T(0);
         }
+        load_entries<LPP, U>(row, r, m0 + U, mcount, (int)i, jn);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (m0 + u >= mcount) continue;
@@ -1020,17 +1036,17 @@ __global__ __launch_bounds__(256) void k_density_adj(int64_t N, int32_t width, c
     T acc[NQ][3];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q][0] = acc[q][1] = acc[q][2] = T(0);
+    int jn[U];
+    load_entries<LPP, U>(row, r, 0, mcount, (int)i, jn);
     for (int m0 = 0; m0 < mcount; m0 += U) {
-        uint32_t jj[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) jj[u] = (m0 + u < mcount) ? (uint32_t)row[r + LPP * (m0 + u)] : (uint32_t)i;
         vec4_t<T> a[U];
         T gj[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            a[u] = ldo(jd0, jj[u]);
-            gj[u] = ldo(gs, jj[u]);
+            a[u] = ldo(jd0, (uint32_t)jn[u]);
+            gj[u] = ldo(gs, (uint32_t)jn[u]);
         }
+        load_entries<LPP, U>(row, r, m0 + U, mcount, (int)i, jn);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (m0 + u >= mcount) continue;
@@ -1312,19 +1328,19 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
         for (int d = 0; d < 3; ++d) acc[q].gx[d] = acc[q].gv[d] = T(0);
         acc[q].gr = T(0);
     }
+    int jn[U];
+    load_entries<LPP, U>(row, r, 0, mcount, (int)k, jn);
     for (int m0 = 0; m0 < mcount; m0 += U) {
-        int jj[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) jj[u] = (m0 + u < mcount) ? row[r + LPP * (m0 + u)] : 0;
         AdjNbr<T> nb[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint32_t j = (m0 + u < mcount) ? (uint32_t)jj[u] : (uint32_t)k;
+            const uint32_t j = (uint32_t)jn[u];
             nb[u].a = ldo(jd0, j);
             nb[u].b = ldo(jd1, j);
             nb[u].A = ldo(jdA, j);
             nb[u].B = ldo(jdB, j);
         }
+        load_entries<LPP, U>(row, r, m0 + U, mcount, (int)k, jn);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (m0 + u >= mcount) continue;
