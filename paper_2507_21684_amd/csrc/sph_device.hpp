@@ -693,6 +693,21 @@ __device__ __forceinline__ void load_entries(const int32_t* __restrict__ row, in
     for (int u = 0; u < U; ++u) jj[u] = (m0 + u < mcount) ? row[r + LPP * (m0 + u)] : self;
 }
 
+// The same entries with every load issued unconditionally: the position is clamped to the row
+// (width entries), so the load needs no branch, and past the lane's count the entry read is
+// replaced by the particle itself.
+template <int LPP, int U>
+__device__ __forceinline__ void load_entries_clamped(const int32_t* __restrict__ row, int width, int r, int m0,
+                                                     int mcount, int self, int* jj)
+{
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int pos = r + LPP * (m0 + u);
+        const int e = row[pos < width ? pos : width - 1];
+        jj[u] = (m0 + u < mcount) ? e : self;
+    }
+}
+
 // FP32 sweeps use the hardware reciprocal and square root (about 1 ulp); FP64 keeps IEEE
 // division and square root.
 template <typename T> __device__ __forceinline__ T fast_rcp(T x) { return T(1) / x; }
@@ -709,17 +724,19 @@ struct PairConst {
 // Squared distance of a listed pair with the arithmetic of the neighbour predicate (per
 // component the minimum image, then the sum of squares in component order, no contraction),
 // so that a list with a skin can be filtered to exactly the pairs with r^2 < H^2.
+// The minimum-image pair vector is returned in d.
 template <typename T, int DIM>
-__device__ __forceinline__ T r2_exact(const T* ui, const vec4_t<T>& a, T L, T invL)
+__device__ __forceinline__ T r2_exact(const T* ui, const vec4_t<T>& a, T L, T invL, T* d)
 {
 #pragma clang fp contract(off)
     const T uj[3] = {a.x, a.y, a.z};
     T r2 = T(0);
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-        T d = ui[k] - uj[k];
-        d = d - L * rint(d * invL);
-        T dd = d * d;
+        T dk = ui[k] - uj[k];
+        dk = dk - L * rint(dk * invL);
+        d[k] = dk;
+        T dd = dk * dk;
         r2 = r2 + dd;
     }
     return r2;
@@ -777,30 +794,25 @@ struct FwdNbr {
 //   drho_i += V_j (v_i - v_j).gW     (times rho_i later)   and   V_j (rho_i - rho_j) x_ij.gW / (r^2 + eps H^2)
 //   rho_i  += W shape (times m C_d / H^d later)
 // In 3D jd0 = (u, V), jd1 = (v, p V) and rho comes separately; in 2D jd0 = (u, V, p V) and
-// jd1 = (v, rho, 0).
+// jd1 = (v, rho, 0).  d and r2 are the pair vector x_ij and its square; with keep false the
+// pair is computed but leaves acc unchanged (a select, not a branch).
 template <typename T, int DIM, bool RHOSUM>
-__device__ __forceinline__ void fwd_pair(const PairConst<T>& c, const T* ui, const T* vi, T rhoi, T pi,
-                                         const FwdNbr<T, DIM>& nb, FwdAcc<T, DIM>& acc)
+__device__ __forceinline__ void fwd_pair(const PairConst<T>& c, const T* vi, T rhoi, T pi, const FwdNbr<T, DIM>& nb,
+                                         const T* d, T r2, bool keep, FwdAcc<T, DIM>& acc)
 {
-    T uj[3], vj[3], d[3];
+    T vj[3];
     T Vj, pVj, rhoj;
     if (DIM == 3) {
-        uj[0] = nb.a.x; uj[1] = nb.a.y; uj[2] = nb.a.z; Vj = nb.a.w;
+        Vj = nb.a.w;
         vj[0] = nb.b.x; vj[1] = nb.b.y; vj[2] = nb.b.z; pVj = nb.b.w;
         rhoj = nb.rho;
     } else {
-        uj[0] = nb.a.x; uj[1] = nb.a.y; Vj = nb.a.z; pVj = nb.a.w;
+        Vj = nb.a.z; pVj = nb.a.w;
         vj[0] = nb.b.x; vj[1] = nb.b.y; rhoj = nb.b.z;
     }
-    T r2 = 0, ue = 0;
+    T ue = 0;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-        T dd = ui[k] - uj[k];
-        dd -= c.L * rint(dd * c.invL);
-        d[k] = dd;
-        r2 += dd * dd;
-        ue += (vi[k] - vj[k]) * dd;
-    }
+    for (int k = 0; k < DIM; ++k) ue += (vi[k] - vj[k]) * d[k];
     const T q = fast_sqrt(r2) * c.invH;
     const T t = T(1) - q;
     const T t2 = t * t;
@@ -811,10 +823,10 @@ __device__ __forceinline__ void fwd_pair(const PairConst<T>& c, const T* ui, con
     const T pij = ue * inv;
     const T cg = ((c.cA * pij - pi) * Vj - pVj) * gF;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) acc.ax[k] += cg * d[k];
-    acc.rdv += Vj * (gF * ue);
-    acc.rdd += Vj * (rhoi - rhoj) * (gF * r2 * inv);
-    if (RHOSUM) acc.rs += t4 * t2 * (T(1) + q * (T(6) + q * T(35.0 / 3.0)));
+    for (int k = 0; k < DIM; ++k) acc.ax[k] = keep ? acc.ax[k] + cg * d[k] : acc.ax[k];
+    acc.rdv = keep ? acc.rdv + Vj * (gF * ue) : acc.rdv;
+    acc.rdd = keep ? acc.rdd + Vj * (rhoi - rhoj) * (gF * r2 * inv) : acc.rdd;
+    if (RHOSUM) acc.rs = keep ? acc.rs + t4 * t2 * (T(1) + q * (T(6) + q * T(35.0 / 3.0))) : acc.rs;
 }
 
 // Cell assignment of the next step's sort, done by the sweep that produced the positions
@@ -831,6 +843,15 @@ struct NextCells {
 // accumulator m mod (8 / LPP) of the lane.  Lanes gather the records of kPairsInFlight
 // positions before computing them, in increasing m, with the list entries of the following
 // group already in flight.
+//
+// In 3D the pairs of a group are computed without branches: a position past the lane's
+// count or rejected by the filter is computed and dropped from the sums by a select (the
+// accumulators start at +0 and never become -0, so adding nothing and skipping agree
+// bitwise), which lets the compiler interleave the independent pairs of the group.  A 3D
+// sweep keeps every SIMD busy with many wavefronts, and this takes the per-pair exec-mask
+// branches out of its instruction stream.  In 2D all wavefronts of a typical launch are
+// resident at once and each lane has few groups; there the per-pair branches, which skip the
+// tail positions that no lane of the wavefront holds, measured faster.
 template <typename T, int DIM, int MODE, int LPP>
 __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const int32_t* __restrict__ nbr,
                                                const int32_t* __restrict__ nbr_count,
@@ -870,8 +891,10 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
         acc[q].ax[0] = acc[q].ax[1] = acc[q].ax[2] = T(0);
         acc[q].rdv = acc[q].rdd = acc[q].rs = T(0);
     }
+    constexpr bool kSelect = DIM == 3;
     int jn[U];
-    load_entries<LPP, U>(row, r, 0, mcount, (int)i, jn);
+    if (kSelect) load_entries_clamped<LPP, U>(row, width, r, 0, mcount, (int)i, jn);
+    else load_entries<LPP, U>(row, r, 0, mcount, (int)i, jn);
     for (int m0 = 0; m0 < mcount; m0 += U) {
         int jj[U];
 #pragma unroll
@@ -884,15 +907,17 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
             nb[u].b = ldo(jd1, j);
             nb[u].rho = (DIM == 3) ? ldo(cur.rho, j) : T(0);
         }
-        load_entries<LPP, U>(row, r, m0 + U, mcount, (int)i, jn);
+        if (kSelect) load_entries_clamped<LPP, U>(row, width, r, m0 + U, mcount, (int)i, jn);
+        else load_entries<LPP, U>(row, r, m0 + U, mcount, (int)i, jn);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (m0 + u >= mcount) continue;
-            if (filter) {
-                if (!(r2_exact<T, DIM>(ui, nb[u].a, c.L, c.invL) < c.H2)) continue;
-                accepted += (jj[u] != (int)i) ? 1 : 0;
-            }
-            fwd_pair<T, DIM, MODE == kModeRhs>(c, ui, vi, rhoi, pi, nb[u], acc[u % NQ]);
+            if (!kSelect && m0 + u >= mcount) continue;
+            T d[3];
+            const T r2 = r2_exact<T, DIM>(ui, nb[u].a, c.L, c.invL, d);
+            const bool keep = (m0 + u < mcount) && (!filter || r2 < c.H2);
+            if (!kSelect && !keep) continue;
+            accepted += (filter && keep && jj[u] != (int)i) ? 1 : 0;
+            fwd_pair<T, DIM, MODE == kModeRhs>(c, vi, rhoi, pi, nb[u], d, r2, keep, acc[u % NQ]);
         }
     }
     T ax[3] = {0, 0, 0};
@@ -1050,7 +1075,8 @@ __global__ __launch_bounds__(256) void k_density_adj(int64_t N, int32_t width, c
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (m0 + u >= mcount) continue;
-            if (filter && !(r2_exact<T, DIM>(ui, a[u], c.L, c.invL) < c.H2)) continue;
+            T e_[3];
+            if (filter && !(r2_exact<T, DIM>(ui, a[u], c.L, c.invL, e_) < c.H2)) continue;
             T uj[3] = {0, 0, 0}, d[3] = {0, 0, 0};
             unpack_u<T, DIM>(a[u], uj);
             T r2 = 0;
@@ -1344,7 +1370,8 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (m0 + u >= mcount) continue;
-            if (filter && !(r2_exact<T, DIM>(uk, nb[u].a, c.L, c.invL) < c.H2)) continue;
+            T e_[3];
+            if (filter && !(r2_exact<T, DIM>(uk, nb[u].a, c.L, c.invL, e_) < c.H2)) continue;
             adj_pair<T, DIM>(c, uk, vk, ak, rbk, Vk, rhok, pk, irk, dpk, nb[u], acc[u % NQ]);
         }
     }
