@@ -12,7 +12,8 @@ FP32, 64 steps of dt = 0.125 H / c0, checkpoint every 8, loss sum |v_T|^2, gradi
 respect to the initial state.  Inputs are synthetic (seeded jittered lattice).
 
 The JSON line also carries the roofline of the dominant pair kernel (device time from HIP
-events the library records on its launch stream during the timed region), the CPU oracle
+events that the library hands to that kernel's launches in the timed region, which hold
+each launch's own start and end), the CPU oracle
 on the host's cores, the batched workload (512 uneven 2D simulations in one plan)
 against the plain path (one plan per simulation, run one after the other), with the
 per-simulation completion latency p50/p99 of both, and the served workload (Poisson
@@ -479,7 +480,7 @@ def main():
     _, prof_all = timed_jobs(plan, x0, v0, r0, wl, 1)
     breakdown = {k: round(v[0], 3) for k, v in prof_all.items()}
     dom = max(("build", "sweep", "adjoint") if wl.adjoint else ("build", "sweep"), key=lambda k: prof_all[k][0])
-    # timed region: only the dominant kernel's launches carry events (each event pair costs ~1 us)
+    # timed region: only the dominant kernel's launches carry events
     elapsed, prof = timed_jobs(plan, x0, v0, r0, wl, args.steps, [dom])
     status = plan.poll()
     assert np.all(status == 0), "device reported non-finite values or neighbour overflow: %s" % status

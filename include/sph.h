@@ -296,10 +296,12 @@ sph_status sph_pair_count(sph_plan* plan, int64_t* pairs, void* stream);
 #define SPH_KERN_COUNT 5
 
 /* Per-launch HIP-event timing of the plan's kernels: `classes` is a bit mask, bit k
- * selecting kernel class k (SPH_PROFILE_ALL for every class, 0 to stop).  A pair of
- * events is recorded around each selected launch group, on the stream it is launched
- * on; each pair costs about a microsecond of device time, so time only the classes of
- * interest in a timed run. */
+ * selecting kernel class k (SPH_PROFILE_ALL for every class, 0 to stop).  The build, sweep
+ * and adjoint classes are one kernel per launch group: their event pair is handed to that
+ * launch (hipExtLaunchKernelGGL) and holds the kernel's own start and end.  The sort and
+ * other classes span several kernels and are bracketed by events recorded on the stream,
+ * each costing about a microsecond of device time, so time only the classes of interest
+ * in a timed run.  While profiling is on, graph mode is not used. */
 #define SPH_PROFILE_ALL ((1 << SPH_KERN_COUNT) - 1)
 sph_status sph_profile_enable(sph_plan* plan, int32_t classes);
 

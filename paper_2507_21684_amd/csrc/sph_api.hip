@@ -1,5 +1,6 @@
 // sph_api.hip -- host side of libsph: plans, workspace layout, launch sequences and the
 // C ABI declared in include/sph.h.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -154,13 +155,18 @@ T* wsp(const sph_plan* p, size_t off) { return reinterpret_cast<T*>(p->ws + off)
 size_t tsize(const sph_plan* p) { return p->dtype == SPH_F64 ? 8 : 4; }
 
 // Brackets a group of launches of one kernel class with HIP events on the launch stream
-// when profiling is enabled.
+// when profiling is enabled.  A scope that holds exactly one kernel launch (one_kernel) gives
+// its events to that launch instead (launch_k): hipExtLaunchKernelGGL sets them to the
+// kernel's own start and end, without the gaps that events recorded around it would add.
 struct ProfScope {
     sph_plan* P;
     hipStream_t st;
     int kind;
+    bool one;
+    bool launched = false;
     hipEvent_t a = nullptr, b = nullptr;
-    ProfScope(sph_plan* P_, hipStream_t st_, int kind_) : P(P_), st(st_), kind(kind_)
+    ProfScope(sph_plan* P_, hipStream_t st_, int kind_, bool one_kernel = false)
+        : P(P_), st(st_), kind(kind_), one(one_kernel)
     {
         if (!((P->prof >> kind_) & 1)) return;
         if (P->ev_pool.empty()) {
@@ -175,15 +181,31 @@ struct ProfScope {
         a = P->ev_pool.back().first;
         b = P->ev_pool.back().second;
         P->ev_pool.pop_back();
-        (void)hipEventRecord(a, st);
+        if (!one) (void)hipEventRecord(a, st);
     }
     ~ProfScope()
     {
         if (!a) return;
-        (void)hipEventRecord(b, st);
-        P->ev_used.push_back({a, b, kind});
+        if (!one) {
+            (void)hipEventRecord(b, st);
+            launched = true;
+        }
+        if (launched) P->ev_used.push_back({a, b, kind});
+        else P->ev_pool.push_back({a, b});
     }
 };
+
+// Launch of `kern`; the kernel that a one-kernel profiling scope times carries its events.
+template <typename... KArgs, typename... Args>
+void launch_k(ProfScope* prof, void (*kern)(KArgs...), dim3 grid, dim3 block, hipStream_t st, Args... args)
+{
+    if (prof && prof->a && prof->one && !prof->launched) {
+        hipExtLaunchKernelGGL(kern, grid, block, 0, st, prof->a, prof->b, 0, args...);
+        prof->launched = true;
+    } else {
+        kern<<<grid, block, 0, st>>>(args...);
+    }
+}
 
 template <typename T>
 void fill_simconst(const sph_plan* P, std::vector<unsigned char>& out)
@@ -328,8 +350,8 @@ sph_status build_lists(sph_plan* P, int slot, hipStream_t st, bool exact = false
     if (P->N == 0 || P->ncell == 0) return SPH_OK;
     const SlotLayout& L = P->slot[slot];
     P->list_of[slot] = slot;
-    ProfScope prof(P, st, SPH_KERN_BUILD);
-    k_build_list<T, D><<<(unsigned)P->ncell, 64, 0, st>>>(
+    ProfScope prof(P, st, SPH_KERN_BUILD, true);
+    launch_k(&prof, k_build_list<T, D>, dim3((unsigned)P->ncell), dim3(64), st,
         wsp<int32_t>(P, P->o_cell_sim), wsp<int32_t>(P, P->o_blk_coord), wsp<int32_t>(P, P->o_blk_rank),
         wsp<SimConst<T>>(P, P->o_simc),
         wsp<int32_t>(P, P->o_cell_start), wsp<vec4_t<T>>(P, L.jd0), P->width,
@@ -341,10 +363,10 @@ sph_status build_lists(sph_plan* P, int slot, hipStream_t st, bool exact = false
 
 template <typename T, int D, int MODE, int LPP>
 void launch_sweep(sph_plan* P, const SlotLayout& L, const SlotLayout& LL, StatePtrs<T, D> dst, T* drho, T* acc,
-                  T* rhosum, NextCells next, NextSlot<T> ns, hipStream_t st)
+                  T* rhosum, NextCells next, NextSlot<T> ns, hipStream_t st, ProfScope* prof)
 {
     const int64_t lanes = P->N * LPP;
-    k_sweep<T, D, MODE, LPP><<<grid_for(lanes, 256), 256, 0, st>>>(
+    launch_k(prof, k_sweep<T, D, MODE, LPP>, dim3(grid_for(lanes, 256)), dim3(256), st,
         P->N, P->width, wsp<int32_t>(P, LL.nbr), wsp<int32_t>(P, LL.cnt), wsp<vec4_t<T>>(P, L.jd0),
         wsp<vec4_t<T>>(P, L.jd1), ws_state<T, D>(P, L.SA), dst, wsp<int32_t>(P, L.orig), drho, acc, rhosum,
         wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc), wsp<int32_t>(P, P->o_status), next, ns,
@@ -374,11 +396,11 @@ sph_status sweep(sph_plan* P, int slot, T* drho, T* acc, T* rhosum, hipStream_t 
         ns = NextSlot<T>{wsp<vec4_t<T>>(P, N2.jd0), wsp<vec4_t<T>>(P, N2.jd1), wsp<int32_t>(P, N2.orig),
                          wsp<vec4_t<T>>(P, P->o_uref)};
     }
-    ProfScope prof(P, st, SPH_KERN_SWEEP);
+    ProfScope prof(P, st, SPH_KERN_SWEEP, true);
     switch (P->lpp_fwd) {
-    case 2: launch_sweep<T, D, MODE, 2>(P, L, LL, dst, drho, acc, rhosum, next, ns, st); break;
-    case 8: launch_sweep<T, D, MODE, 8>(P, L, LL, dst, drho, acc, rhosum, next, ns, st); break;
-    default: launch_sweep<T, D, MODE, 4>(P, L, LL, dst, drho, acc, rhosum, next, ns, st); break;
+    case 2: launch_sweep<T, D, MODE, 2>(P, L, LL, dst, drho, acc, rhosum, next, ns, st, &prof); break;
+    case 8: launch_sweep<T, D, MODE, 8>(P, L, LL, dst, drho, acc, rhosum, next, ns, st, &prof); break;
+    default: launch_sweep<T, D, MODE, 4>(P, L, LL, dst, drho, acc, rhosum, next, ns, st, &prof); break;
     }
     LAUNCH_CHECK("sweep");
     return SPH_OK;
@@ -397,10 +419,10 @@ sph_status unsort_from(sph_plan* P, StatePtrs<T, D> src, int slot, StatePtrs<T, 
 
 template <typename T, int D, int LPP>
 void launch_adj(sph_plan* P, const SlotLayout& L, const SlotLayout& LL, StatePtrs<T, D> cot, hipStream_t st,
-                bool vjp)
+                bool vjp, ProfScope* prof)
 {
     const int64_t lanes = P->N * LPP;
-    k_adj_sweep<T, D, LPP><<<grid_for(lanes, 256), 256, 0, st>>>(
+    launch_k(prof, k_adj_sweep<T, D, LPP>, dim3(grid_for(lanes, 256)), dim3(256), st,
         P->N, P->width, wsp<int32_t>(P, LL.nbr), wsp<int32_t>(P, LL.cnt), wsp<vec4_t<T>>(P, L.jd0),
         wsp<vec4_t<T>>(P, L.jd1), wsp<vec4_t<T>>(P, P->o_jdA), wsp<vec4_t<T>>(P, P->o_jdB), wsp<int32_t>(P, L.orig),
         cot, wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc), wsp<int32_t>(P, P->o_status),
@@ -422,12 +444,12 @@ sph_status adjoint(sph_plan* P, int slot, StatePtrs<T, D> cot, hipStream_t st, b
             wsp<vec4_t<T>>(P, P->o_jdB), wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc), vjp ? 1 : 0);
         LAUNCH_CHECK("adj_prologue");
     }
-    ProfScope prof(P, st, SPH_KERN_ADJOINT);
+    ProfScope prof(P, st, SPH_KERN_ADJOINT, true);
     const SlotLayout& LL = P->slot[P->list_of[slot]];
     switch (P->lpp_adj) {
-    case 2: launch_adj<T, D, 2>(P, L, LL, cot, st, vjp); break;
-    case 8: launch_adj<T, D, 8>(P, L, LL, cot, st, vjp); break;
-    default: launch_adj<T, D, 4>(P, L, LL, cot, st, vjp); break;
+    case 2: launch_adj<T, D, 2>(P, L, LL, cot, st, vjp, &prof); break;
+    case 8: launch_adj<T, D, 8>(P, L, LL, cot, st, vjp, &prof); break;
+    default: launch_adj<T, D, 4>(P, L, LL, cot, st, vjp, &prof); break;
     }
     LAUNCH_CHECK("adj_sweep");
     return SPH_OK;
