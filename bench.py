@@ -38,7 +38,12 @@ METRIC = "pair interactions/s fwd+adjoint; batched p50/p99 latency vs plain path
 # Algorithmic FP work per directed pair (FMA = 2 flops; add, mul, division, sqrt, rint = 1),
 # counted from the operations each sweep performs per pair.
 FLOPS_PER_PAIR = {("sweep", 2): 54, ("sweep", 3): 64, ("adjoint", 2): 149, ("adjoint", 3): 178}
-PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+# Vector ALU ceilings of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz = 78.6
+# TFLOP/s for FP32 without packed instructions (the library is built with packed FP32 disabled)
+# and for FP64; the published FP32 figure, 157.3, counts packed FP32.
+PEAK_TFLOPS = {"f32": 78.6, "f64": 78.6}
+PEAK_TFLOPS_PACKED_F32 = 157.3
+PEAK_HBM_GBS = 8000.0
 
 
 def workloads():
@@ -194,7 +199,7 @@ def roofline(prof, dom, wl, per_state, reps, dim, n_particles, lanes=(4, 4)):
         launches = len(states) * reps
         bytes_per_launch = (4 * entries + launches * n_particles * (4 + (16 if wl.dtype == "f32" else 32))) / launches
         achieved = bytes_per_launch / mean_launch_s / 1e9
-        peak = 8000.0
+        peak = PEAK_HBM_GBS
         tdt = "float" if wl.dtype == "f32" else "double"
         traffic = measured_traffic(wl.name, "sph::k_build_list<%s,%d>" % (tdt, dim))
         return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": peak, "unit": "GB/s",
@@ -211,9 +216,18 @@ def roofline(prof, dom, wl, per_state, reps, dim, n_particles, lanes=(4, 4)):
     tdt = "float" if wl.dtype == "f32" else "double"
     sym = ("sph::k_sweep<%s,%d,0,%d>" % (tdt, dim, lanes[0]) if dom == "sweep"
            else "sph::k_adj_sweep<%s,%d,%d>" % (tdt, dim, lanes[1]))
-    return {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": measured_traffic(wl.name, sym), "mean_launch_us": round(mean_launch_s * 1e6, 2),
-            "launches": n_dom, "pairs_per_launch": int(pairs / n_dom)}
+    traffic = measured_traffic(wl.name, sym)
+    out = {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+           "frac": round(achieved / peak, 4), "traffic": traffic, "mean_launch_us": round(mean_launch_s * 1e6, 2),
+           "launches": n_dom, "pairs_per_launch": int(pairs / n_dom)}
+    if wl.dtype == "f32":
+        out["frac_of_packed_fp32_peak"] = round(achieved / PEAK_TFLOPS_PACKED_F32, 4)
+    if traffic is not None:
+        # the HBM view of the same launches: counted bytes over the live launch time
+        gbs = traffic / mean_launch_s / 1e9
+        out["hbm_gbs"] = round(gbs, 1)
+        out["hbm_frac"] = round(gbs / PEAK_HBM_GBS, 4)
+    return out
 
 
 def bench_batched(dev, reps):
