@@ -385,7 +385,9 @@ def bench_serving(dev, count, warmup, load=0.75, budget_gib=96):
 
     The request mix is fixed by the trace seed; the arrival rate is `load` times the plain path's
     saturation throughput (1 / mean plain service time, measured on the same requests), so the
-    same trace is offered to both servers.  Latency percentiles skip the first `warmup` requests."""
+    same trace is offered to both servers.  Latency percentiles skip the first `warmup` requests.
+    Below saturation both servers keep up with the arrivals, so their throughputs are equal; the
+    saturation leg queues the same requests at once and compares the time to serve them all."""
     import numpy as np
     import torch
     from paper_2507_21684_amd import serving as S
@@ -416,17 +418,33 @@ def bench_serving(dev, count, warmup, load=0.75, budget_gib=96):
     work = 2 * eng.pairs
     keep = slice(warmup, None)
     pp, ps = S.percentiles(lat_plain[keep]), S.percentiles(lat_served[keep])
+    # saturation: the same requests all queued at t = 0, so that throughput is set by the server
+    # and not by the arrivals (the plain path then takes the sum of its service times)
+    served_info = {"peak_admitted_gib": round(sch.peak_used / (1 << 30), 2),
+                   "failed_requests": int(sum(1 for j in done if j.error)),
+                   "mean_batch": round(float(np.mean(sch.batch_sizes)), 2), "ticks": sch.ticks,
+                   "plan_creation_s": round(eng.plan_seconds, 3)}
+    del sch, eng, done
+    torch.cuda.empty_cache()
+    burst = [Request(r.rid, 0.0, r.spec, r.seed, r.steps) for r in base]
+    sch_b, eng_b, done_b = S.serve(burst, "f32", 8, int(budget_gib * (1 << 30)), dev, progress=log)
+    makespan_burst = float(max(j.finished for j in done_b))
+    work_b = 2 * eng_b.pairs
+    log("serving, saturation: %.2f s served vs %.2f s plain" % (makespan_burst, float(service.sum())))
+    saturation = {"served": round(work_b / makespan_burst, 1), "plain": round(work_b / float(service.sum()), 1),
+                  "speedup": round(float(service.sum()) / makespan_burst, 3),
+                  "makespan_s": round(makespan_burst, 3), "mean_batch": round(float(np.mean(sch_b.batch_sizes)), 2),
+                  "peak_admitted_gib": round(sch_b.peak_used / (1 << 30), 2),
+                  "failed_requests": int(sum(1 for j in done_b if j.error))}
     return {"workload": "poisson_%d_mixed_2d3d_f32" % count, "requests": count, "warmup_requests": warmup,
             "rate_per_s": round(rate, 3), "load_vs_plain_saturation": load,
             "mean_plain_service_ms": round(float(service.mean() * 1e3), 3), "pair_interactions": work,
-            "hbm_budget_gib": budget_gib, "peak_admitted_gib": round(sch.peak_used / (1 << 30), 2),
-            "failed_requests": int(sum(1 for j in done if j.error)),
-            "mean_batch": round(float(np.mean(sch.batch_sizes)), 2), "ticks": sch.ticks,
-            "plan_creation_s": round(eng.plan_seconds, 3),
+            "hbm_budget_gib": budget_gib, **served_info,
             "served": {"value": round(work / makespan_served, 1), "p50_ms": round(ps["p50_ms"], 3),
                        "p99_ms": round(ps["p99_ms"], 3), "makespan_s": round(makespan_served, 3)},
             "plain": {"value": round(work / makespan_plain, 1), "p50_ms": round(pp["p50_ms"], 3),
                       "p99_ms": round(pp["p99_ms"], 3), "makespan_s": round(makespan_plain, 3)},
+            "saturation": saturation,
             "unit": "pair interactions/s"}
 
 

@@ -203,21 +203,27 @@ def percentiles(lat_s: Sequence[float]) -> Dict[str, float]:
 
 # ---------------------------------------------------------------- GPU engine
 
+def rebuild_intervals(ckpt_every: int, reuse: int = 8) -> Dict[int, int]:
+    """List rebuild interval per dimension for served requests (and their plain-path twins)."""
+    from .autotune import rebuild_for
+    return {2: rebuild_for(ckpt_every, reuse), 3: rebuild_for(ckpt_every, min(reuse, 2))}
+
+
 class GpuEngine:
     """Runs the scheduler's groups through batched plans of the HIP library."""
 
     def __init__(self, dtype: str = "f32", ckpt_every: int = 8, device=None, tuned: bool = True,
                  reuse: int = 8):
         import torch
-        from .autotune import rebuild_for
         self.torch = torch
         self.dtype = dtype
         self.tdt = torch.float32 if dtype == "f32" else torch.float64
         self.K = int(ckpt_every)
-        # 2D neighbour lists rebuilt every R steps (R divides K, so segments start with a build),
-        # each request's skin from the largest speed of its own initial state; 3D lists are
-        # rebuilt every step (their longer skinned lists cost the sweeps more than they save)
-        self.R = {2: rebuild_for(self.K, reuse), 3: 1}
+        # neighbour lists rebuilt every R steps (R divides K, so segments start with a build),
+        # each request's skin from the largest speed of its own initial state; 3D lists every
+        # second step at most, which keeps the 3D skin near 0.13 H at the largest amplitudes
+        # (a skinned 3D list grows as (1 + skin)^3 and its sweeps with it)
+        self.R = rebuild_intervals(self.K, reuse)
         self._skin: Dict[int, float] = {}
         self.device = device if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.tuned = tuned
@@ -382,8 +388,8 @@ def plain_request(req: Request, dtype: str = "f32", ckpt_every: int = 8, device=
     spec = req.spec
     npdt = np.float32 if dtype == "f32" else np.float64
     host = [a.astype(npdt) for a in make_state(spec, req.seed)]
-    from .autotune import rebuild_for, skin_from_speed
-    R = rebuild_for(ckpt_every, reuse) if spec.dim == 2 else 1
+    from .autotune import skin_from_speed
+    R = rebuild_intervals(ckpt_every, reuse)[spec.dim]
     skin = skin_from_speed(float(np.sqrt((host[1].astype(np.float64) ** 2).sum(axis=0)).max()), spec.params(), R)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -198,3 +198,15 @@ def test_small_request_is_not_held_at_the_pace_of_a_large_one():
     ticks_before_small_done = sum(1 for c in eng.calls[:max(i for i, c in enumerate(eng.calls) if 1 in c[1]) + 1]
                                   if 0 in c[1])
     assert ticks_before_small_done <= 3
+
+
+def test_rebuild_intervals_divide_the_checkpoint_interval():
+    from paper_2507_21684_amd.serving import rebuild_intervals
+    assert rebuild_intervals(8) == {2: 8, 3: 2}
+    assert rebuild_intervals(6) == {2: 6, 3: 2}
+    assert rebuild_intervals(3) == {2: 3, 3: 1}
+    assert rebuild_intervals(1) == {2: 1, 3: 1}
+    assert rebuild_intervals(8, reuse=1) == {2: 1, 3: 1}
+    for K in range(1, 17):
+        for R in rebuild_intervals(K).values():
+            assert K % R == 0
