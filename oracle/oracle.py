@@ -105,6 +105,14 @@ def lib():
         L.orc_step_rk.argtypes = [_P, ctypes.c_int64, _D, _D, _D, ctypes.c_int32, ctypes.c_int32, _D, _D]
         L.orc_step_rk_adjoint.restype = ctypes.c_int
         L.orc_step_rk_adjoint.argtypes = [_P, ctypes.c_int64, _D, _D, _D, ctypes.c_int32, _D, _D, _D, _D, _D]
+        L.orc_step_symplectic.restype = ctypes.c_int
+        L.orc_step_symplectic.argtypes = [_P, ctypes.c_int64, _D, _D, _D, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_int32, _I64]
+        L.orc_step_symplectic_adjoint.restype = ctypes.c_int
+        L.orc_step_symplectic_adjoint.argtypes = [_P, ctypes.c_int64, _D, _D, _D, _D, _D, _D]
+        L.orc_rollout_symplectic_adjoint.restype = ctypes.c_int
+        L.orc_rollout_symplectic_adjoint.argtypes = [_P, ctypes.c_int64, _D, _D, _D, ctypes.c_int32, ctypes.c_int32,
+                                                     ctypes.c_int32, _D, _D, _D]
         L.orc_density_adjoint.restype = ctypes.c_int
         L.orc_density_adjoint.argtypes = [_P, ctypes.c_int64, _D, _D, _D]
         L.orc_step_adjoint.restype = ctypes.c_int
@@ -313,6 +321,48 @@ def step_rk_adjoint(p: Params, x, v, rho, xb, vb, rb, scheme="rk4"):
                                    _d(xb), _d(vb), _d(rb))
     if rc != 0:
         raise ValueError("oracle step_rk_adjoint rejected its input")
+    return xb, vb, rb
+
+
+def step_symplectic(p: Params, x, v, rho, nsteps: int, reuse: bool = False, restart: int = 0):
+    """nsteps steps of DualSPHysics' symplectic Euler; with reuse, the last substep's rates stand
+    in for the next step's first substep, re-evaluated at every multiple of `restart` (0: only at
+    the first step).  Returns (x, v, rho, evaluations of the update function)."""
+    x, v, rho = _f64(x).copy(), _f64(v).copy(), _f64(rho).copy()
+    ev = np.zeros(1, dtype=np.int64)
+    pc = p.c()
+    rc = lib().orc_step_symplectic(ctypes.byref(pc), rho.shape[0], _d(x), _d(v), _d(rho), nsteps,
+                                   1 if reuse else 0, restart if restart > 0 else max(nsteps, 1),
+                                   ev.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if rc != 0:
+        raise ValueError("oracle step_symplectic rejected its input")
+    return x, v, rho, int(ev[0])
+
+
+def step_symplectic_adjoint(p: Params, x, v, rho, xb, vb, rb):
+    """Cotangents of the state at the start of a symplectic step (its first substep evaluated)
+    from those of its output."""
+    x, v, rho = _f64(x), _f64(v), _f64(rho)
+    xb, vb, rb = _f64(xb).copy(), _f64(vb).copy(), _f64(rb).copy()
+    pc = p.c()
+    rc = lib().orc_step_symplectic_adjoint(ctypes.byref(pc), rho.shape[0], _d(x), _d(v), _d(rho),
+                                           _d(xb), _d(vb), _d(rb))
+    if rc != 0:
+        raise ValueError("oracle step_symplectic_adjoint rejected its input")
+    return xb, vb, rb
+
+
+def rollout_symplectic_adjoint(p: Params, x, v, rho, nsteps: int, xb, vb, rb, reuse: bool = False,
+                               restart: int = 0):
+    """Cotangents of the initial state of a symplectic rollout from those of its final state."""
+    x, v, rho = _f64(x), _f64(v), _f64(rho)
+    xb, vb, rb = _f64(xb).copy(), _f64(vb).copy(), _f64(rb).copy()
+    pc = p.c()
+    rc = lib().orc_rollout_symplectic_adjoint(ctypes.byref(pc), rho.shape[0], _d(x), _d(v), _d(rho), nsteps,
+                                              1 if reuse else 0, restart if restart > 0 else max(nsteps, 1),
+                                              _d(xb), _d(vb), _d(rb))
+    if rc != 0:
+        raise ValueError("oracle rollout_symplectic_adjoint rejected its input")
     return xb, vb, rb
 
 

@@ -44,6 +44,9 @@
  *   - The vector-Jacobian product of the summation density alone (the
  *     backward benchmark of Sec. 4.1: summation density after a step,
  *     gradient with respect to the initial positions).
+ *   - DualSPHysics' symplectic Euler (Sec. 3.4, App. C), optionally with
+ *     the last substep's rates re-used as the next step's first substep,
+ *     and its vector-Jacobian products for one step and for a rollout.
  *
  * Readings taken where the paper is silent or garbled are listed in the
  * project's design notes; the ones that change arithmetic are: the minus
@@ -1098,6 +1101,229 @@ int orc_step_rk_adjoint(const orc_params* p, int64_t n, const double* x, const d
     free(Ub);
     free(kb);
     free(out);
+    return 0;
+}
+
+/* ---------------------------------------------------------------- symplectic Euler
+ *
+ * The symplectic scheme of DualSPHysics that the paper lists among its
+ * integrators (Sec. 3.4 and App. C, citing Dominguez et al. 2022): a
+ * position-Verlet predictor-corrector over the update function f = (a, D),
+ * D = drho/dt, with h = dt/2:
+ *   predictor  x_h = x + h v,  v_h = v + h a1,  rho_h = rho + h D1,
+ *              (a1, D1) = f(x, v, rho)
+ *   corrector  (a2, D2) = f(x_h, v_h, rho_h)
+ *              v' = v + dt a2,  x' = x_h + h v',
+ *              rho' = rho (2 - e) / (2 + e),  e = -dt D2 / rho_h.
+ * With `reuse`, the rates of a step's last substep, (a2, D2), stand in for
+ * f(x, v, rho) in the next step's predictor (the modified scheme of Sec. 3.4
+ * and App. C that re-uses the last substep's update values), so a step costs
+ * one evaluation of f.  A reusing rollout evaluates f(x, v, rho) afresh at
+ * its first step and at every step whose index is a multiple of `restart`
+ * (in a checkpointed rollout, the checkpoints, so that each segment can be
+ * recomputed on its own).
+ */
+
+/* (a, D) = f(x, v, rho), packed as [a (dim*n) | D (n)]. */
+static void rates_at(const orc_params* p, int64_t n, const double* x, const double* v, const double* rho,
+                     double* r)
+{
+    int dim = p->dim;
+    double* u = (double*)malloc(sizeof(double) * (size_t)dim * (size_t)(n > 0 ? n : 1));
+    wrap_all(p, n, x, u);
+    nblist nb;
+    build_lists(dim, n, x, p->L, p->H, 0, 0, &nb);
+    rhs_with_list(p, n, u, v, rho, &nb, r + (size_t)dim * n, r, NULL);
+    nblist_free(&nb);
+    free(u);
+}
+
+/* Predictor state u_h = [x_h | v_h | rho_h] from u and the predictor's rates r1. */
+static void symp_predict(const orc_params* p, int64_t n, const double* x, const double* v, const double* rho,
+                         const double* r1, double* uh)
+{
+    size_t dn = (size_t)p->dim * (size_t)n;
+    double h = 0.5 * p->dt;
+    for (size_t e = 0; e < dn; ++e) uh[e] = x[e] + h * v[e];
+    for (size_t e = 0; e < dn; ++e) uh[dn + e] = v[e] + h * r1[e];
+    for (int64_t i = 0; i < n; ++i) uh[2 * dn + i] = rho[i] + h * r1[dn + i];
+}
+
+/* One step in place with predictor rates r1; the corrector's rates go to r2. */
+static void symp_step(const orc_params* p, int64_t n, double* x, double* v, double* rho, const double* r1,
+                      double* uh, double* r2)
+{
+    size_t dn = (size_t)p->dim * (size_t)n;
+    double h = 0.5 * p->dt;
+    symp_predict(p, n, x, v, rho, r1, uh);
+    rates_at(p, n, uh, uh + dn, uh + 2 * dn, r2);
+    for (size_t e = 0; e < dn; ++e) {
+        v[e] = v[e] + p->dt * r2[e];
+        x[e] = uh[e] + h * v[e];
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        double e = -p->dt * r2[dn + i] / uh[2 * dn + i];
+        rho[i] = rho[i] * (2.0 - e) / (2.0 + e);
+    }
+}
+
+/* nsteps steps in place; *evals (if given) receives the number of evaluations of f. */
+int orc_step_symplectic(const orc_params* p, int64_t n, double* x, double* v, double* rho, int32_t nsteps,
+                        int32_t reuse, int32_t restart, int64_t* evals)
+{
+    if (!valid_params(p) || n < 0 || nsteps < 0 || (reuse && restart < 1)) return -1;
+    size_t dn = (size_t)p->dim * (size_t)n, m = 2 * dn + (size_t)n;
+    double* r1 = (double*)malloc(sizeof(double) * (dn + (size_t)n) + 1);
+    double* r2 = (double*)malloc(sizeof(double) * (dn + (size_t)n) + 1);
+    double* uh = (double*)malloc(sizeof(double) * m + 1);
+    int64_t ne = 0;
+    for (int32_t t = 0; t < nsteps; ++t) {
+        if (!reuse || t % restart == 0) {
+            rates_at(p, n, x, v, rho, r1);
+            ++ne;
+        }
+        symp_step(p, n, x, v, rho, r1, uh, r2);
+        ++ne;
+        memcpy(r1, r2, sizeof(double) * (dn + (size_t)n));
+    }
+    if (evals) *evals = ne;
+    free(r1);
+    free(r2);
+    free(uh);
+    return 0;
+}
+
+/* Vector-Jacobian product of one step from u = (x, v, rho) with predictor
+ * rates r1.  In: (xb, vb, rb), the cotangents of u', and cb2 (NULL for none),
+ * the cotangent of the step's corrector rates (a2, D2) where a later step
+ * re-uses them.  Out: (xb, vb, rb), the cotangents of u; if `fresh`, r1 is
+ * f(u) and its dependence on u is included, otherwise cb1 receives the
+ * cotangent of r1.  Transpose of the corrector, with vt = vb' + h xb':
+ *   a2bar = dt vt,  ebar = rb' rho g'(e),  D2bar = -dt ebar / rho_h,
+ *   the predictor state's cotangent = J_f(u_h)^T (a2bar, D2bar)
+ *     + (xb', 0, ebar dt D2 / rho_h^2),
+ * then of the predictor u_h = u + h (v, a1, D1). */
+static void symp_step_adjoint(const orc_params* p, int64_t n, const double* x, const double* v,
+                              const double* rho, const double* r1, int fresh, double* xb, double* vb, double* rb,
+                              const double* cb2, double* cb1)
+{
+    size_t dn = (size_t)p->dim * (size_t)n, m = 2 * dn + (size_t)n;
+    double h = 0.5 * p->dt, dt = p->dt;
+    double* uh = (double*)malloc(sizeof(double) * m + 1);
+    double* r2 = (double*)malloc(sizeof(double) * (dn + (size_t)n) + 1);
+    double* r2b = (double*)malloc(sizeof(double) * (dn + (size_t)n) + 1);
+    double* vt = (double*)malloc(sizeof(double) * dn + 1);
+    double* rdir = (double*)malloc(sizeof(double) * (size_t)n + 1);
+    double* uhb = (double*)calloc(m + 1, sizeof(double));
+    symp_predict(p, n, x, v, rho, r1, uh);
+    const double* rh = uh + 2 * dn;
+    rates_at(p, n, uh, uh + dn, rh, r2);
+    for (size_t e = 0; e < dn; ++e) {
+        vt[e] = vb[e] + h * xb[e];
+        r2b[e] = dt * vt[e] + (cb2 ? cb2[e] : 0.0);
+    }
+    double* rhb = (double*)malloc(sizeof(double) * (size_t)n + 1);
+    for (int64_t i = 0; i < n; ++i) {
+        double D2 = r2[dn + i];
+        double e = -dt * D2 / rh[i];
+        double g = (2.0 - e) / (2.0 + e);
+        double gp = -4.0 / ((2.0 + e) * (2.0 + e));
+        double eb = rb[i] * rho[i] * gp;
+        r2b[dn + i] = -dt * eb / rh[i] + (cb2 ? cb2[dn + i] : 0.0);
+        rhb[i] = eb * dt * D2 / (rh[i] * rh[i]);
+        rdir[i] = rb[i] * g;
+    }
+    orc_rhs_vjp(p, n, uh, uh + dn, rh, r2b, r2b + dn, uhb, uhb + dn, uhb + 2 * dn);
+    for (size_t e = 0; e < dn; ++e) uhb[e] += xb[e];
+    for (int64_t i = 0; i < n; ++i) uhb[2 * dn + i] += rhb[i];
+    /* the predictor u_h = (x + h v, v + h a1, rho + h D1) */
+    for (size_t e = 0; e < dn; ++e) {
+        xb[e] = uhb[e];
+        vb[e] = vt[e] + uhb[dn + e] + h * uhb[e];
+    }
+    for (int64_t i = 0; i < n; ++i) rb[i] = rdir[i] + uhb[2 * dn + i];
+    double* r1b = (double*)malloc(sizeof(double) * (dn + (size_t)n) + 1);
+    for (size_t e = 0; e < dn; ++e) r1b[e] = h * uhb[dn + e];
+    for (int64_t i = 0; i < n; ++i) r1b[dn + i] = h * uhb[2 * dn + i];
+    if (fresh) {
+        double* out = (double*)malloc(sizeof(double) * m + 1);
+        orc_rhs_vjp(p, n, x, v, rho, r1b, r1b + dn, out, out + dn, out + 2 * dn);
+        for (size_t e = 0; e < dn; ++e) {
+            xb[e] += out[e];
+            vb[e] += out[dn + e];
+        }
+        for (int64_t i = 0; i < n; ++i) rb[i] += out[2 * dn + i];
+        free(out);
+    } else {
+        memcpy(cb1, r1b, sizeof(double) * (dn + (size_t)n));
+    }
+    free(uh);
+    free(r2);
+    free(r2b);
+    free(vt);
+    free(rdir);
+    free(uhb);
+    free(rhb);
+    free(r1b);
+}
+
+/* VJP of one step whose predictor evaluates f(u) (a step without a re-used
+ * substep): (xb, vb, rb) from the cotangents of u' to those of u. */
+int orc_step_symplectic_adjoint(const orc_params* p, int64_t n, const double* x, const double* v,
+                                const double* rho, double* xb, double* vb, double* rb)
+{
+    if (!valid_params(p) || n < 0) return -1;
+    size_t dn = (size_t)p->dim * (size_t)n;
+    double* r1 = (double*)malloc(sizeof(double) * (dn + (size_t)n) + 1);
+    rates_at(p, n, x, v, rho, r1);
+    symp_step_adjoint(p, n, x, v, rho, r1, 1, xb, vb, rb, NULL, NULL);
+    free(r1);
+    return 0;
+}
+
+/* Gradient through a whole rollout of nsteps steps from (x, v, rho): on
+ * entry (xb, vb, rb) are the cotangents of the final state, on exit those of
+ * the initial one.  With reuse, the re-used rates carry cotangents from each
+ * step to the one before it. */
+int orc_rollout_symplectic_adjoint(const orc_params* p, int64_t n, const double* x, const double* v,
+                                   const double* rho, int32_t nsteps, int32_t reuse, int32_t restart, double* xb,
+                                   double* vb, double* rb)
+{
+    if (!valid_params(p) || n < 0 || nsteps < 0 || (reuse && restart < 1)) return -1;
+    size_t dn = (size_t)p->dim * (size_t)n, m = 2 * dn + (size_t)n, nr = dn + (size_t)n;
+    double* us = (double*)malloc(sizeof(double) * m * (size_t)(nsteps + 1) + 1);
+    double* rs = (double*)malloc(sizeof(double) * nr * (size_t)(nsteps + 1) + 1);
+    double* uh = (double*)malloc(sizeof(double) * m + 1);
+    double* r2 = (double*)malloc(sizeof(double) * nr + 1);
+    double* cb = (double*)calloc(nr + 1, sizeof(double));
+    double* cb_prev = (double*)calloc(nr + 1, sizeof(double));
+    memcpy(us, x, sizeof(double) * dn);
+    memcpy(us + dn, v, sizeof(double) * dn);
+    memcpy(us + 2 * dn, rho, sizeof(double) * (size_t)n);
+    for (int32_t t = 0; t < nsteps; ++t) {
+        double* ut = us + (size_t)t * m;
+        double* un = us + (size_t)(t + 1) * m;
+        double* rt = rs + (size_t)t * nr;
+        if (!reuse || t % restart == 0) rates_at(p, n, ut, ut + dn, ut + 2 * dn, rt);
+        else memcpy(rt, r2, sizeof(double) * nr);
+        memcpy(un, ut, sizeof(double) * m);
+        symp_step(p, n, un, un + dn, un + 2 * dn, rt, uh, r2);
+    }
+    int carry = 0;  /* cb holds the cotangent of step t's corrector rates */
+    for (int32_t t = nsteps - 1; t >= 0; --t) {
+        double* ut = us + (size_t)t * m;
+        int fresh = !reuse || t % restart == 0;
+        symp_step_adjoint(p, n, ut, ut + dn, ut + 2 * dn, rs + (size_t)t * nr, fresh, xb, vb, rb,
+                          carry ? cb : NULL, cb_prev);
+        carry = !fresh;
+        if (carry) memcpy(cb, cb_prev, sizeof(double) * nr);
+    }
+    free(us);
+    free(rs);
+    free(uh);
+    free(r2);
+    free(cb);
+    free(cb_prev);
     return 0;
 }
 
