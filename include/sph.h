@@ -152,6 +152,27 @@ sph_status sph_get_tuning(const sph_plan* plan, int32_t* lanes_fwd, int32_t* lan
  * non-finite entries, or a tableau that is not explicit. */
 sph_status sph_set_integrator(sph_plan* plan, int32_t stages, const double* A, const double* b);
 
+/* Symplectic Euler of DualSPHysics, the other integrator Sec. 3.4 and App. C
+ * name: with h = dt/2 and (a, D) = f(u) the update function's acceleration and
+ * density rate,
+ *     predictor  u_h = (x + h v, v + h a1, rho + h D1),  (a1, D1) = f(u),
+ *     corrector  (a2, D2) = f(u_h),  v' = v + dt a2,  x' = x_h + h v',
+ *                rho' = rho (2 - e) / (2 + e),  e = -dt D2 / rho_h,
+ * each evaluation of f with its own sort and neighbour lists.  With
+ * reuse_last_substep != 0, the predictor takes the previous step's corrector
+ * rates (a2, D2) instead of evaluating f(u) (the modified scheme of Sec. 3.4 /
+ * App. C that re-uses the last substep's update values): one evaluation of f
+ * per step.  The rates are evaluated afresh at the first step of every sph_step
+ * call and, when the call writes checkpoints, at every checkpoint, so each
+ * checkpoint segment can be recomputed on its own; sph_rollout_backward follows
+ * the same schedule and carries the re-used rates' cotangents from step to step.
+ * sph_step_adjoint is the adjoint of one step whose predictor evaluates f(u).
+ * sph_set_integrator(plan, 0, NULL, NULL) returns to semi-implicit Euler.  The
+ * first call reserves the stage storage and a tape of tape_depth rate blocks
+ * and so grows sph_workspace_size(): make it before sph_bind (CAPACITY
+ * afterwards).  Host-side setting. */
+sph_status sph_set_symplectic(sph_plan* plan, int32_t reuse_last_substep);
+
 /* Neighbour-list reuse (Verlet lists; the paper keeps one list for short rollouts,
  * Sec. 4.1).  With rebuild_every = R > 1 (needs a skin in every simulation's
  * parameters), a step sorts and rebuilds its lists only when its index within the

@@ -85,8 +85,11 @@ struct sph_plan {
     // explicit Runge-Kutta tableau (0 stages: the semi-implicit Euler step)
     int32_t rk_stages = 0, rk_reserved = 0;
     double rk_A[kMaxStages * kMaxStages] = {}, rk_b[kMaxStages] = {};
+    // symplectic Euler (uses the stage storage with two stages), optionally re-using the last
+    // substep's rates as the next predictor's
+    bool symplectic = false, symp_reuse = false, rate_tape = false;
     size_t bytes_base = 0, state_block = 0;
-    size_t o_rkU = 0, o_rkK = 0, o_rkUb = 0, o_rkB0 = 0, o_rkTape = 0;
+    size_t o_rkU = 0, o_rkK = 0, o_rkUb = 0, o_rkB0 = 0, o_rkTape = 0, o_rkRate = 0;
     int64_t N = 0;
     int64_t ncell = 0, nblk = 0;
     std::vector<sph_params> prm;
@@ -657,11 +660,113 @@ sph_status rk_step_adjoint(sph_plan* P, StatePtrs<T, D> u, StatePtrs<T, D> cot, 
     return lincomb<T, D>(P, cot, B0, 1.0, false, s, ones, Ub, false, st);
 }
 
+// ---------------------------------------------------------------- symplectic Euler steps
+
+// Rates (., a, D) = f(w) into r (original order) from a sort, a list build and a sweep of w.
+template <typename T, int D>
+sph_status rates_at(sph_plan* P, StatePtrs<T, D> w, StatePtrs<T, D> r, hipStream_t st)
+{
+    RC_TRY((sort_into<T, D>(P, w, nullptr, 0, st)));
+    RC_TRY((build_lists<T, D>(P, 0, st)));
+    return sweep<T, D, kModeRhs>(P, 0, r.rho, r.v[0], nullptr, st);
+}
+
+template <typename T, int D>
+sph_status symp_final(sph_plan* P, StatePtrs<T, D> u, StatePtrs<T, D> uh, StatePtrs<T, D> r2, hipStream_t st)
+{
+    if (P->N == 0) return SPH_OK;
+    ProfScope prof(P, st, SPH_KERN_OTHER);
+    k_symp_final<T, D><<<grid_for(P->N, 256), 256, 0, st>>>(P->N, u, uh, r2, wsp<int32_t>(P, P->o_psim),
+                                                            wsp<SimConst<T>>(P, P->o_simc));
+    LAUNCH_CHECK("symp_final");
+    return SPH_OK;
+}
+
+// Predictor state u_h = u + (dt/2) (v, a1, D1) of the step from u whose predictor rates are in
+// stage-rate block 0 (evaluated here from u when `fresh`, else left there by the caller), and
+// the corrector's rates f(u_h) in stage-rate block 1.
+template <typename T, int D>
+sph_status symp_stages(sph_plan* P, StatePtrs<T, D> u, bool fresh, StatePtrs<T, D>& uh, StatePtrs<T, D>& r1,
+                       StatePtrs<T, D>& r2, hipStream_t st)
+{
+    r1 = rk_block<T, D>(P, P->o_rkK, 0);
+    r2 = rk_block<T, D>(P, P->o_rkK, 1);
+    uh = rk_block<T, D>(P, P->o_rkU, 1);
+    if (fresh) RC_TRY((rates_at<T, D>(P, u, r1, st)));
+    StatePtrs<T, D> k1 = r1;
+    for (int k = 0; k < 3; ++k) k1.x[k] = u.v[k];  // the predictor's x-rate is v
+    const double half = 0.5;
+    RC_TRY((lincomb<T, D>(P, uh, u, 1.0, false, 1, &half, &k1, true, st)));
+    return rates_at<T, D>(P, uh, r2, st);
+}
+
+// One step of u in place.  With re-use the corrector's rates are copied to block 0 for the
+// next step's predictor.
+template <typename T, int D>
+sph_status symp_step(sph_plan* P, StatePtrs<T, D> u, bool fresh, hipStream_t st)
+{
+    StatePtrs<T, D> uh, r1, r2;
+    RC_TRY((symp_stages<T, D>(P, u, fresh, uh, r1, r2, st)));
+    RC_TRY((symp_final<T, D>(P, u, uh, r2, st)));
+    if (P->symp_reuse) RC_TRY((lincomb<T, D>(P, r1, r2, 1.0, false, 0, nullptr, nullptr, false, st)));
+    return SPH_OK;
+}
+
+// Vector-Jacobian product of one step from u, cot in place.  The predictor's rates are f(u)
+// when `fresh`, else the caller has put them in stage-rate block 0.  cb_in (has_cb) is the
+// cotangent of this step's corrector rates where the next step re-used them; when not
+// `fresh`, cb_out receives the cotangent of the re-used predictor rates.  Sequence: the
+// corrector's transpose, the VJP of f at u_h (its lists are the last ones built), then the
+// predictor's transpose: the VJP of f at u when fresh, else the hand-over to cb_out.
+template <typename T, int D>
+sph_status symp_step_adjoint(sph_plan* P, StatePtrs<T, D> u, StatePtrs<T, D> cot, bool fresh, bool has_cb,
+                             StatePtrs<T, D> cb_in, StatePtrs<T, D> cb_out, hipStream_t st)
+{
+    StatePtrs<T, D> uh, r1, r2;
+    RC_TRY((symp_stages<T, D>(P, u, fresh, uh, r1, r2, st)));
+    const StatePtrs<T, D> kb2 = rk_block<T, D>(P, P->o_rkUb, 1);
+    const StatePtrs<T, D> ubh = rk_block<T, D>(P, P->o_rkUb, 0);
+    const StatePtrs<T, D> b0 = rk_block<T, D>(P, P->o_rkB0, 0);
+    if (P->N > 0) {
+        ProfScope prof(P, st, SPH_KERN_OTHER);
+        k_symp_final_adj<T, D><<<grid_for(P->N, 256), 256, 0, st>>>(
+            P->N, cot, u.rho, uh.rho, r2.rho, cb_in, has_cb ? 1 : 0, kb2, ubh, b0, wsp<int32_t>(P, P->o_psim),
+            wsp<SimConst<T>>(P, P->o_simc));
+        LAUNCH_CHECK("symp_final_adj");
+    }
+    RC_TRY((adjoint<T, D>(P, 0, kb2, st, true)));               // kb2 <- J_f(u_h)^T kb2
+    const double one = 1.0;
+    RC_TRY((lincomb<T, D>(P, ubh, ubh, 1.0, false, 1, &one, &kb2, false, st)));  // ubar_h
+    RC_TRY((lincomb<T, D>(P, b0, b0, 1.0, false, 1, &one, &ubh, false, st)));
+    RC_TRY((lincomb<T, D>(P, ubh, ubh, 0.5, true, 0, nullptr, nullptr, false, st)));  // kb1 = h ubar_h
+    if (fresh) {
+        RC_TRY((sort_into<T, D>(P, u, nullptr, 0, st)));
+        RC_TRY((build_lists<T, D>(P, 0, st)));
+        RC_TRY((adjoint<T, D>(P, 0, ubh, st, true)));
+        return lincomb<T, D>(P, cot, b0, 1.0, false, 1, &one, &ubh, false, st);
+    }
+    if (P->N == 0) return SPH_OK;
+    ProfScope prof(P, st, SPH_KERN_OTHER);
+    k_symp_pred_adj<T, D><<<grid_for(P->N, 256), 256, 0, st>>>(P->N, b0, ubh, cot, cb_out);
+    LAUNCH_CHECK("symp_pred_adj");
+    return SPH_OK;
+}
+
 template <typename T, int D>
 sph_status do_step(sph_plan* P, sph_state* s, int32_t nsteps, const sph_state* ckpt, int32_t every, hipStream_t st)
 {
     if (nsteps == 0) return SPH_OK;
     StatePtrs<T, D> user = user_state<T, D>(s);
+    if (P->symplectic) {
+        // with re-use the predictor's rates are evaluated afresh at the first step and at every
+        // checkpoint, so that each checkpoint segment can be recomputed on its own
+        for (int32_t t = 0; t < nsteps; ++t) {
+            const bool at_ckpt = ckpt && t % every == 0;
+            if (at_ckpt) RC_TRY((copy_state<T, D>(P, user_state<T, D>(&ckpt[t / every]), user, st)));
+            RC_TRY((symp_step<T, D>(P, user, !P->symp_reuse || t == 0 || at_ckpt, st)));
+        }
+        return SPH_OK;
+    }
     if (P->rk_stages > 0) {
         for (int32_t t = 0; t < nsteps; ++t) {
             if (ckpt && t % every == 0) RC_TRY((copy_state<T, D>(P, user_state<T, D>(&ckpt[t / every]), user, st)));
@@ -678,6 +783,9 @@ sph_status do_step(sph_plan* P, sph_state* s, int32_t nsteps, const sph_state* c
 template <typename T, int D>
 sph_status do_step_adjoint(sph_plan* P, const sph_state* sn, sph_state* cot, hipStream_t st)
 {
+    if (P->symplectic)
+        return symp_step_adjoint<T, D>(P, user_state<T, D>(sn), user_state<T, D>(cot), true, false,
+                                       user_state<T, D>(cot), user_state<T, D>(cot), st);
     if (P->rk_stages > 0) return rk_step_adjoint<T, D>(P, user_state<T, D>(sn), user_state<T, D>(cot), st);
     RC_TRY((sort_into<T, D>(P, user_state<T, D>(sn), nullptr, 0, st)));
     RC_TRY((build_lists<T, D>(P, 0, st)));
@@ -694,6 +802,35 @@ sph_status do_rollout_backward(sph_plan* P, const sph_state* ckpt, int32_t nstep
     if (nsteps == 0) return SPH_OK;
     const int32_t nseg = (nsteps + every - 1) / every;
     StatePtrs<T, D> c = user_state<T, D>(cot);
+    if (P->symplectic) {
+        // each segment recomputed into the state tape (and, with re-use, the predictor rates of
+        // each step into the rate tape), then the step VJPs in reverse; the cotangent of re-used
+        // rates passes from a step to the one before it and never crosses a segment start, where
+        // the forward evaluated the rates afresh
+        const StatePtrs<T, D> r1 = rk_block<T, D>(P, P->o_rkK, 0);
+        StatePtrs<T, D> cb[2] = {rk_block<T, D>(P, P->o_rkUb, 2), rk_block<T, D>(P, P->o_rkUb, 3)};
+        for (int32_t seg = nseg - 1; seg >= 0; --seg) {
+            const int32_t len = std::min(every, nsteps - seg * every);
+            RC_TRY((copy_state<T, D>(P, rk_block<T, D>(P, P->o_rkTape, 0), user_state<T, D>(&ckpt[seg]), st)));
+            for (int32_t t = 0; t + 1 < len; ++t) {
+                RC_TRY((copy_state<T, D>(P, rk_block<T, D>(P, P->o_rkTape, t + 1), rk_block<T, D>(P, P->o_rkTape, t),
+                                         st)));
+                RC_TRY((symp_step<T, D>(P, rk_block<T, D>(P, P->o_rkTape, t + 1), !P->symp_reuse || t == 0, st)));
+                if (P->symp_reuse) RC_TRY((copy_state<T, D>(P, rk_block<T, D>(P, P->o_rkRate, t + 1), r1, st)));
+            }
+            int cur = 0;
+            bool has_cb = false;
+            for (int32_t t = len - 1; t >= 0; --t) {
+                const bool fresh = !P->symp_reuse || t == 0;
+                if (!fresh) RC_TRY((copy_state<T, D>(P, r1, rk_block<T, D>(P, P->o_rkRate, t), st)));
+                RC_TRY((symp_step_adjoint<T, D>(P, rk_block<T, D>(P, P->o_rkTape, t), c, fresh, has_cb, cb[cur],
+                                                cb[1 - cur], st)));
+                has_cb = !fresh;
+                cur = 1 - cur;
+            }
+        }
+        return SPH_OK;
+    }
     if (P->rk_stages > 0) {
         // each segment's step states recomputed into the state tape, then the step VJPs
         for (int32_t seg = nseg - 1; seg >= 0; --seg) {
@@ -731,6 +868,7 @@ sph_status run_graphed(sph_plan* P, std::vector<uintptr_t> key, hipStream_t st, 
     key.push_back((uintptr_t)P->lpp_adj);
     key.push_back((uintptr_t)P->reuse);
     key.push_back((uintptr_t)P->rk_stages);
+    key.push_back((uintptr_t)(P->symplectic ? 1 + (P->symp_reuse ? 1 : 0) : 0));
     for (auto& g : P->gcache) {
         if (g.key == key) {
             g.used = ++P->gclock;
@@ -1059,6 +1197,60 @@ sph_status sph_set_tuning(sph_plan* plan, int32_t lanes_fwd, int32_t lanes_adj)
     return SPH_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Stage states, stage rates, stage cotangents, the output cotangent and a state tape of
+// tape_depth blocks, after the plan's base workspace; with `rates`, also a tape of as many
+// rate blocks (the symplectic scheme's re-used rates).
+void reserve_stage_storage(sph_plan* P, bool rates)
+{
+    size_t off = P->bytes_base;
+    const size_t sb = P->state_block;
+    const size_t depth = (size_t)std::max(1, P->tape_depth);
+    P->o_rkU = off;
+    off += kMaxStages * sb;
+    P->o_rkK = off;
+    off += kMaxStages * sb;
+    P->o_rkUb = off;
+    off += kMaxStages * sb;
+    P->o_rkB0 = off;
+    off += sb;
+    P->o_rkTape = off;
+    off += depth * sb;
+    if (rates || P->rate_tape) {
+        P->o_rkRate = off;
+        off += depth * sb;
+        P->rate_tape = true;
+    }
+    P->bytes = off;
+    P->rk_reserved = kMaxStages;
+}
+
+}  // namespace
+
+extern "C" {
+
+sph_status sph_set_symplectic(sph_plan* P, int32_t reuse_last_substep)
+{
+    if (!P) return fail(SPH_ERR_INVALID_ARG, "plan is null");
+    if (P->rk_reserved < kMaxStages || !P->rate_tape) {
+        if (P->bound) return fail(SPH_ERR_CAPACITY, "stage storage was not reserved when the workspace was bound");
+        reserve_stage_storage(P, true);
+    }
+    // the predictor state is the midpoint tableau's second stage
+    P->rk_stages = 2;
+    std::fill(P->rk_A, P->rk_A + kMaxStages * kMaxStages, 0.0);
+    std::fill(P->rk_b, P->rk_b + kMaxStages, 0.0);
+    P->rk_A[1 * kMaxStages + 0] = 0.5;
+    P->rk_b[1] = 1.0;
+    P->symplectic = true;
+    P->symp_reuse = reuse_last_substep != 0;
+    P->clear_graphs();
+    return SPH_OK;
+}
+
 sph_status sph_set_integrator(sph_plan* P, int32_t stages, const double* A, const double* b)
 {
     if (!P) return fail(SPH_ERR_INVALID_ARG, "plan is null");
@@ -1074,22 +1266,10 @@ sph_status sph_set_integrator(sph_plan* P, int32_t stages, const double* A, cons
     }
     if (stages > P->rk_reserved) {
         if (P->bound) return fail(SPH_ERR_CAPACITY, "more stages than reserved when the workspace was bound");
-        // stage states, stage rates, stage cotangents, the output cotangent and a state tape
-        size_t off = P->bytes_base;
-        const size_t sb = P->state_block;
-        P->o_rkU = off;
-        off += kMaxStages * sb;
-        P->o_rkK = off;
-        off += kMaxStages * sb;
-        P->o_rkUb = off;
-        off += kMaxStages * sb;
-        P->o_rkB0 = off;
-        off += sb;
-        P->o_rkTape = off;
-        off += (size_t)std::max(1, P->tape_depth) * sb;
-        P->bytes = off;
-        P->rk_reserved = kMaxStages;
+        reserve_stage_storage(P, false);
     }
+    P->symplectic = false;
+    P->symp_reuse = false;
     P->rk_stages = stages;
     std::fill(P->rk_A, P->rk_A + kMaxStages * kMaxStages, 0.0);
     std::fill(P->rk_b, P->rk_b + kMaxStages, 0.0);

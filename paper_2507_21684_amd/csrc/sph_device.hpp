@@ -1161,6 +1161,92 @@ __global__ __launch_bounds__(256) void k_lincomb(int64_t N, LinComb<T, DIM> L, c
     L.out.rho[i] = r;
 }
 
+// ---------------------------------------------------------------- symplectic Euler
+//
+// DualSPHysics' symplectic scheme (Sec. 3.4, App. C), h = dt/2: the predictor state
+// u_h = (x + h v, v + h a1, rho + h D1) is formed by k_lincomb, the corrector's rates
+// (a2, D2) = f(u_h) by a right-hand-side sweep, and the step ends with
+//   v' = v + dt a2,  x' = x_h + h v',  rho' = rho (2 - e) / (2 + e),  e = -dt D2 / rho_h.
+// All three kernels run in original particle order.
+
+// The corrector, u in place; uh = predictor state, r2 = (., a2, D2).
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_symp_final(int64_t N, StatePtrs<T, DIM> u, StatePtrs<T, DIM> uh,
+                                                    StatePtrs<T, DIM> r2, const int32_t* __restrict__ psim,
+                                                    const SimConst<T>* __restrict__ sims)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const T dt = sims[psim[i]].dt;
+    const T h = T(0.5) * dt;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        const T vn = u.v[k][i] + dt * r2.v[k][i];
+        u.v[k][i] = vn;
+        u.x[k][i] = uh.x[k][i] + h * vn;
+    }
+    const T e = -dt * r2.rho[i] / uh.rho[i];
+    u.rho[i] = u.rho[i] * (T(2) - e) / (T(2) + e);
+}
+
+// Transpose of the corrector.  cot = (xb', vb', rb') of u'; cb (null for none) = cotangent of
+// (a2, D2) where the next step re-uses them.  With vt = vb' + h xb', g(e) = (2 - e)/(2 + e),
+// eb = rb' rho g'(e):
+//   kb2 = (0, dt vt + cb_a, -dt eb / rho_h + cb_D)       rates' cotangent, for the VJP at u_h
+//   uhd = (xb', 0, eb dt D2 / rho_h^2)                    u_h's cotangent outside that VJP
+//   b0  = (0, vt, rb' g)                                  u's cotangent outside the predictor
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_symp_final_adj(int64_t N, StatePtrs<T, DIM> cot, const T* __restrict__ rho,
+                                                        const T* __restrict__ rho_h, const T* __restrict__ d2,
+                                                        StatePtrs<T, DIM> cb, int has_cb, StatePtrs<T, DIM> kb2,
+                                                        StatePtrs<T, DIM> uhd, StatePtrs<T, DIM> b0,
+                                                        const int32_t* __restrict__ psim,
+                                                        const SimConst<T>* __restrict__ sims)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const T dt = sims[psim[i]].dt;
+    const T h = T(0.5) * dt;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        const T xb = cot.x[k][i];
+        const T vt = cot.v[k][i] + h * xb;
+        kb2.x[k][i] = T(0);
+        kb2.v[k][i] = dt * vt + (has_cb ? cb.v[k][i] : T(0));
+        uhd.x[k][i] = xb;
+        uhd.v[k][i] = T(0);
+        b0.x[k][i] = T(0);
+        b0.v[k][i] = vt;
+    }
+    const T rb = cot.rho[i], rh = rho_h[i], D2 = d2[i];
+    const T e = -dt * D2 / rh;
+    const T g = (T(2) - e) / (T(2) + e);
+    const T gp = T(-4) / ((T(2) + e) * (T(2) + e));
+    const T eb = rb * rho[i] * gp;
+    kb2.rho[i] = -dt * eb / rh + (has_cb ? cb.rho[i] : T(0));
+    uhd.rho[i] = eb * dt * D2 / (rh * rh);
+    b0.rho[i] = rb * g;
+}
+
+// Transpose of the predictor when its rates were re-used (not evaluated from u): with
+// kb1 = h ubar_h, u's cotangent is b0 + (0, kb1_x, 0) (the x-rate of the predictor is v) and
+// the re-used rates receive (kb1_v, kb1_rho).
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_symp_pred_adj(int64_t N, StatePtrs<T, DIM> b0, StatePtrs<T, DIM> kb1,
+                                                       StatePtrs<T, DIM> cot, StatePtrs<T, DIM> cb)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        cot.x[k][i] = b0.x[k][i];
+        cot.v[k][i] = b0.v[k][i] + kb1.x[k][i];
+        cb.v[k][i] = kb1.v[k][i];
+    }
+    cot.rho[i] = b0.rho[i];
+    cb.rho[i] = kb1.rho[i];
+}
+
 // ---------------------------------------------------------------- unsort
 
 template <typename T, int DIM>

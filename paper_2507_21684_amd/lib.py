@@ -68,6 +68,8 @@ def lib():
         L.sph_set_integrator.restype = st
         L.sph_set_integrator.argtypes = [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double)]
+        L.sph_set_symplectic.restype = st
+        L.sph_set_symplectic.argtypes = [_VP, ctypes.c_int32]
         L.sph_set_reuse.restype = st
         L.sph_set_reuse.argtypes = [_VP, ctypes.c_int32]
         L.sph_set_graphs.restype = ctypes.c_int32
@@ -121,13 +123,14 @@ def exported_symbols() -> List[str]:
             "sph_build_cells", "sph_neighbors", "sph_rhs", "sph_step", "sph_step_adjoint", "sph_poll",
             "sph_pair_count", "sph_profile_enable", "sph_profile_read", "sph_last_error", "sph_set_tuning",
             "sph_get_tuning", "sph_rollout_backward", "sph_set_graphs", "sph_density_adjoint", "sph_set_reuse",
-            "sph_set_integrator"]
+            "sph_set_integrator", "sph_set_symplectic"]
 
 
 KERNEL_CLASSES = ["sort", "build", "sweep", "adjoint", "other"]
 
 # Explicit Runge-Kutta tableaus (A strictly lower triangular, weights b); None is the default
-# semi-implicit Euler step.
+# semi-implicit Euler step.  The symplectic schemes are not tableaus and are named separately.
+SYMPLECTIC = {"symplectic_euler": 0, "symplectic_euler_reuse": 1}
 TABLEAUS = {
     "semi_implicit_euler": None,
     "explicit_euler": ([[0.0]], [1.0]),
@@ -139,10 +142,13 @@ TABLEAUS = {
 
 
 def _set_integrator(handle, integrator):
-    """integrator: a TABLEAUS name, (A, b), or None."""
-    tab = TABLEAUS[integrator] if isinstance(integrator, str) or integrator is None else integrator
+    """integrator: a TABLEAUS or SYMPLECTIC name, (A, b), or None."""
+    if isinstance(integrator, str) and integrator in SYMPLECTIC:
+        _check(lib().sph_set_symplectic(handle, SYMPLECTIC[integrator]))
+        return
     if isinstance(integrator, str) and integrator not in TABLEAUS:
         raise ValueError("unknown integrator %r" % integrator)
+    tab = None if integrator is None else (TABLEAUS[integrator] if isinstance(integrator, str) else integrator)
     if tab is None:
         _check(lib().sph_set_integrator(handle, 0, None, None))
         return

@@ -153,3 +153,37 @@ def test_integrator_settings_on_an_unbound_plan():
     assert setp([[0.0]], [float("nan")]) == -1
     assert L.lib().sph_set_integrator(h, 0, None, None) == 0    # back to semi-implicit Euler
     L.lib().sph_plan_destroy(h)
+
+
+def test_symplectic_setting_reserves_a_rate_tape():
+    """sph_set_symplectic on an unbound plan: stage storage plus tape_depth rate blocks."""
+    import ctypes
+    from paper_2507_21684_amd.inputs import SimSpec
+    spec = SimSpec(2, 32)
+    arr = (L.SphParams * 1)(L.make_params(spec.params(), "f32"))
+    cnt = (ctypes.c_int64 * 1)(spec.n)
+    sizes = {}
+    for name in ("euler", "rk", "symp", "symp_after_rk"):
+        h = L._VP()
+        assert L.lib().sph_plan_create(arr, 1, cnt, 0, 4, ctypes.byref(h)) == 0
+        if name in ("rk", "symp_after_rk"):
+            A, b = L.TABLEAUS["midpoint"]
+            L._set_integrator(h, "midpoint")
+        if name in ("symp", "symp_after_rk"):
+            assert L.lib().sph_set_symplectic(h, 1) == 0
+            assert L.lib().sph_set_symplectic(h, 0) == 0
+        sz = ctypes.c_size_t()
+        L.lib().sph_workspace_size(h, ctypes.byref(sz))
+        sizes[name] = sz.value
+        if name == "symp":
+            # back to a tableau and to semi-implicit Euler; the reservation stays
+            L._set_integrator(h, "rk4")
+            L._set_integrator(h, None)
+            L.lib().sph_workspace_size(h, ctypes.byref(sz))
+            assert sz.value == sizes["symp"]
+        L.lib().sph_plan_destroy(h)
+    block = 4 * spec.n * 5               # FP32, 2D: x, v (2 each) and rho, aligned below
+    assert sizes["rk"] > sizes["euler"]
+    assert sizes["symp"] - sizes["rk"] >= 4 * block
+    assert sizes["symp_after_rk"] == sizes["symp"]
+    assert L.lib().sph_set_symplectic(None, 0) != 0

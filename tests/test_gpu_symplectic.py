@@ -1,0 +1,137 @@
+"""Symplectic Euler (DualSPHysics' position Verlet, Sec. 3.4 / App. C) on the GPU against the FP64
+oracle, with and without re-use of the last substep's rates: forward steps and checkpoints, the
+step VJP, a checkpointed rollout gradient through autograd (the re-used rates' cotangents carried
+from step to step), bitwise batch invariance and graph mode."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2507_21684_amd.inputs import SimSpec, make_state
+from paper_2507_21684_amd.lib import Plan
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(arrs, dtype):
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    return [torch.tensor(a, dtype=tdt, device=torch.device("cuda", 0)).contiguous() for a in arrs]
+
+
+def _state(spec, seed, dtype):
+    npdt = np.float32 if dtype == "f32" else np.float64
+    return [a.astype(npdt) for a in make_state(spec, seed)]
+
+
+def _plan(specs, dtype, reuse, **kw):
+    return Plan([s.params() for s in specs], [s.n for s in specs], dtype,
+                integrator="symplectic_euler_reuse" if reuse else "symplectic_euler", **kw)
+
+
+def _close(g, ref, dtype, spec):
+    gx, gv, gr = [t.cpu().numpy().astype(np.float64) for t in g]
+    xr, vr, rr = ref[:3]
+    tol_r, tol_v, tol_x = (1e-10, 1e-9, 1e-9) if dtype == "f64" else (1e-5, 1e-4, 1e-4)
+    assert np.abs(gr / rr - 1).max() <= tol_r
+    err = np.sqrt(((gv - vr) ** 2).sum(axis=0)).max() / np.sqrt((vr ** 2).sum(axis=0)).max()
+    assert err <= tol_v
+    assert np.abs(gx - xr).max() <= tol_x * spec.dx
+
+
+@pytest.mark.parametrize("reuse,dtype,dim,side,steps", [(False, "f64", 2, 24, 4), (True, "f64", 2, 24, 6),
+                                                        (True, "f64", 3, 12, 3), (False, "f32", 3, 14, 4),
+                                                        (True, "f32", 2, 40, 8)])
+def test_symplectic_forward_parity(orc, reuse, dtype, dim, side, steps):
+    spec = SimSpec(dim, side)
+    x, v, rho = _state(spec, 1, dtype)
+    plan = _plan([spec], dtype, reuse)
+    g = _gpu([x, v, rho], dtype)
+    plan.step(*g, steps)
+    assert np.all(plan.poll() == 0)
+    _close(g, orc.step_symplectic(orc.Params(**spec.params()), x, v, rho, steps, reuse), dtype, spec)
+
+
+def test_reuse_restarts_at_checkpoints(orc):
+    """With checkpoints every 3 steps the re-used rates are evaluated afresh at steps 0, 3, 6."""
+    spec = SimSpec(2, 24)
+    x, v, rho = _state(spec, 2, "f64")
+    plan = _plan([spec], "f64", True, tape_depth=3)
+    g = _gpu([x, v, rho], "f64")
+    ck = [plan.empty_state() for _ in range(3)]
+    plan.step(*g, 8, ck, 3)
+    p = orc.Params(**spec.params())
+    _close(g, orc.step_symplectic(p, x, v, rho, 8, True, 3), "f64", spec)
+    for k in range(3):
+        want = orc.step_symplectic(p, x, v, rho, 3 * k, True, 3)
+        _close(ck[k], want, "f64", spec)
+    # and it differs from the call without checkpoints (fresh rates only at step 0)
+    g2 = _gpu([x, v, rho], "f64")
+    plan.step(*g2, 8)
+    assert (g2[1] - g[1]).abs().max().item() > 0
+
+
+@pytest.mark.parametrize("dtype,dim,side", [("f64", 2, 20), ("f32", 2, 32), ("f32", 3, 12)])
+def test_symplectic_step_adjoint_parity(orc, dtype, dim, side):
+    spec = SimSpec(dim, side, jitter=0.2)
+    x, v, rho = _state(spec, 9, dtype)
+    rng = np.random.default_rng(10)
+    c = [rng.normal(size=a.shape).astype(a.dtype) for a in (x, v, rho)]
+    for reuse in (False, True):       # one step's adjoint evaluates the predictor's rates either way
+        plan = _plan([spec], dtype, reuse)
+        g = _gpu([x, v, rho], dtype)
+        cg = _gpu(c, dtype)
+        plan.step_adjoint(*g, *cg)
+        ref = orc.step_symplectic_adjoint(orc.Params(**spec.params()), x, v, rho, *c)
+        tol = 1e-9 if dtype == "f64" else 1e-3
+        for got, want in zip(cg, ref):
+            got = got.cpu().numpy().astype(np.float64)
+            assert np.abs(got - want).max() <= tol * np.abs(want).max()
+
+
+@pytest.mark.parametrize("reuse,dtype,tol", [(False, "f32", 1e-3), (True, "f32", 1e-3), (True, "f64", 1e-9)])
+def test_symplectic_rollout_gradient(orc, reuse, dtype, tol):
+    """2D 32^2, 8 steps, checkpoint every 4, loss sum |v_T|^2, through autograd."""
+    from paper_2507_21684_amd.rollout import rollout
+    spec = SimSpec(2, 32)
+    x, v, rho = _state(spec, 0, dtype)
+    plan = _plan([spec], dtype, reuse, tape_depth=4)
+    gx0, gv0, gr0 = _gpu([x, v, rho], dtype)
+    for t in (gx0, gv0, gr0):
+        t.requires_grad_(True)
+    xT, vT, rT = rollout(plan, gx0, gv0, gr0, 8, 4)
+    loss = (vT.double() ** 2).sum()
+    loss.backward()
+    p = orc.Params(**spec.params())
+    xr, vr, rr, _ = orc.step_symplectic(p, x, v, rho, 8, reuse, 4)
+    cx, cv, cr = orc.rollout_symplectic_adjoint(p, x, v, rho, 8, np.zeros(x.shape), 2.0 * vr, np.zeros(rho.shape),
+                                                reuse, 4)
+    assert float(loss) == pytest.approx(float((vr ** 2).sum()), rel=1e-5)
+    for got, want in ((gx0.grad, cx), (gv0.grad, cv), (gr0.grad, cr)):
+        got = got.cpu().numpy().astype(np.float64)
+        assert np.abs(got - want).max() <= tol * np.abs(want).max()
+
+
+def test_symplectic_batch_invariance_and_graphs():
+    specs = [SimSpec(2, 20, amplitude=0.8), SimSpec(2, 29, amplitude=1.4)]
+    states = [_state(s, 40 + k, "f32") for k, s in enumerate(specs)]
+    solo = []
+    for s, st in zip(specs, states):
+        p = _plan([s], "f32", True)
+        g = _gpu(st, "f32")
+        p.step(*g, 5)
+        solo.append([t.cpu().numpy() for t in g])
+    cat = [np.concatenate([st[k] for st in states], axis=-1) for k in range(3)]
+    pb = _plan(specs, "f32", True)
+    g = _gpu(cat, "f32")
+    src = _gpu(cat, "f32")
+    for graphs in (False, True, True):     # direct, then a captured graph and its replay
+        pb.set_graphs(graphs)
+        for t, s0 in zip(g, src):
+            t.copy_(s0)
+        pb.step(*g, 5)
+        torch.cuda.synchronize()
+        out = [t.cpu().numpy() for t in g]
+        off = 0
+        for s, ref in zip(specs, solo):
+            for k in range(3):
+                np.testing.assert_array_equal(out[k][..., off:off + s.n], ref[k])
+            off += s.n
