@@ -375,6 +375,47 @@ def bench_rk4(dev, reps=3):
             "note": "4 right-hand sides per step forward and 4 stage VJPs per step backward are counted"}
 
 
+def bench_symplectic(dev, reps=3):
+    """Symplectic Euler on the 2D 256^2 FP32 state, 16 steps with a checkpoint every 8 and the
+    checkpointed backward, without and with re-use of the last substep's rates (two evaluations
+    of the update function per step, or one plus a fresh one at each checkpoint); pair
+    interactions of every evaluation and of its VJP per second."""
+    import numpy as np
+    import torch
+    from paper_2507_21684_amd import inputs as I
+    from paper_2507_21684_amd.lib import Plan
+    from paper_2507_21684_amd.rollout import rollout
+    spec = I.SimSpec(2, 256)
+    T, K = 16, 8
+    x0, v0, r0 = (torch.tensor(a.astype(np.float32), device=dev) for a in I.make_state(spec, 0))
+    out = {"workload": "symplectic_tgv2d_64k_f32", "steps": T, "ckpt_every": K, "unit": "pair interactions/s"}
+    for name in ("symplectic_euler", "symplectic_euler_reuse"):
+        plan = Plan([spec.params()], [spec.n], "f32", tape_depth=K, device=dev, integrator=name)
+
+        def job():
+            v = v0.clone().requires_grad_(True)
+            xT, vT, rT = rollout(plan, x0.clone(), v, r0.clone(), T, K)
+            (vT ** 2).sum().backward()
+
+        job()
+        torch.cuda.synchronize()
+        plan.pair_count()
+        xs, vs, rs = x0.clone(), v0.clone(), r0.clone()
+        ck = [plan.empty_state() for _ in range(T // K)]
+        plan.step(xs, vs, rs, T, ck, K)     # the job's evaluation schedule (fresh at checkpoints)
+        pairs = plan.pair_count()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            job()
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+        out[name] = {"ms_per_job": round(t * 1e3, 3), "pair_interactions": 2 * pairs,
+                     "value": round(2 * pairs / t, 1)}
+        del plan
+    out["reuse_speedup"] = round(out["symplectic_euler"]["ms_per_job"] / out["symplectic_euler_reuse"]["ms_per_job"], 3)
+    return out
+
+
 def log(msg):
     """Progress line on stderr (the JSON result is the only line on stdout)."""
     print("[bench] " + msg, file=sys.stderr, flush=True)
@@ -542,10 +583,12 @@ def main():
         log("density backward benchmark")
         dens = bench_density_backward(dev)
 
-    rk4 = None
+    rk4 = symp = None
     if args.workload == "tgv2d_64k_f32":
         log("RK4 job")
         rk4 = bench_rk4(dev)
+        log("symplectic Euler jobs")
+        symp = bench_symplectic(dev)
 
     served = None
     if args.serving > 0 and args.workload != "batched_512_tgv2d_f32":
@@ -564,7 +607,7 @@ def main():
                       "lanes_per_particle": list(lanes), "list_skin": list_skin,
                       "list_rebuild_every": list_rebuild},
            "roofline": roof, "kernel_ms_per_job": breakdown, "cpu_baseline": cpu, "batched": batched, "serving": served,
-           "density_backward": dens, "rk4": rk4}
+           "density_backward": dens, "rk4": rk4, "symplectic": symp}
     print(json.dumps(out), flush=True)
 
 
