@@ -38,7 +38,7 @@ def build(force: bool = False) -> str:
 
 
 class OrcParams(ctypes.Structure):
-    _fields_ = [("dim", ctypes.c_int32), ("pad", ctypes.c_int32), ("L", ctypes.c_double),
+    _fields_ = [("dim", ctypes.c_int32), ("renorm", ctypes.c_int32), ("L", ctypes.c_double),
                 ("H", ctypes.c_double), ("m", ctypes.c_double), ("rho0", ctypes.c_double),
                 ("c0", ctypes.c_double), ("delta", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("eps", ctypes.c_double), ("dt", ctypes.c_double)]
@@ -57,9 +57,10 @@ class Params:
     alpha: float = 0.01
     eps: float = 0.01
     dt: float = 0.0
+    renorm: int = 0      # 1: delta-diffusion with the renormalised density gradient
 
     def c(self) -> OrcParams:
-        return OrcParams(self.dim, 0, self.L, self.H, self.m, self.rho0, self.c0, self.delta,
+        return OrcParams(self.dim, int(self.renorm), self.L, self.H, self.m, self.rho0, self.c0, self.delta,
                          self.alpha, self.eps, self.dt)
 
 
@@ -113,6 +114,8 @@ def lib():
         L.orc_rollout_symplectic_adjoint.restype = ctypes.c_int
         L.orc_rollout_symplectic_adjoint.argtypes = [_P, ctypes.c_int64, _D, _D, _D, ctypes.c_int32, ctypes.c_int32,
                                                      ctypes.c_int32, _D, _D, _D]
+        L.orc_renorm_gradient.restype = ctypes.c_int
+        L.orc_renorm_gradient.argtypes = [_P, ctypes.c_int64, _D, _D, _D, _D]
         L.orc_density_adjoint.restype = ctypes.c_int
         L.orc_density_adjoint.argtypes = [_P, ctypes.c_int64, _D, _D, _D]
         L.orc_step_adjoint.restype = ctypes.c_int
@@ -364,6 +367,18 @@ def rollout_symplectic_adjoint(p: Params, x, v, rho, nsteps: int, xb, vb, rb, re
     if rc != 0:
         raise ValueError("oracle rollout_symplectic_adjoint rejected its input")
     return xb, vb, rb
+
+
+def renorm_gradient(p: Params, x, rho, A):
+    """Renormalised gradient <grad A>_i = L_i sum_j V_j (A_j - A_i) grad_i W_ij (V_j = m / rho_j)."""
+    x, rho, A = _f64(x), _f64(rho), _f64(A)
+    n = rho.shape[0]
+    G = np.zeros((p.dim, n))
+    pc = p.c()
+    rc = lib().orc_renorm_gradient(ctypes.byref(pc), n, _d(x), _d(rho), _d(A), _d(G))
+    if rc != 0:
+        raise ValueError("oracle renorm_gradient rejected its input")
+    return G
 
 
 def density_adjoint(p: Params, x, g):

@@ -69,7 +69,7 @@
 
 typedef struct {
     int32_t dim;    /* 2 or 3 */
-    int32_t pad;
+    int32_t renorm; /* 1: delta-diffusion with the renormalised density gradient */
     double L;       /* periodic box side */
     double H;       /* kernel support radius */
     double m;       /* particle mass */
@@ -612,6 +612,136 @@ static void wrap_all(const orc_params* p, int64_t n, const double* x, double* u)
         for (int64_t i = 0; i < n; ++i) u[k * n + i] = wrap_f64(x[k * n + i], p->L, invL);
 }
 
+/* ---------------------------------------------------------------- renormalised gradient
+ *
+ * App. A.5 (kernel and gradient correction terms): the corrected gradient of a field A,
+ *   <grad A>_i = L_i sum_j V_j (A_j - A_i) grad_i W_ij,
+ *   L_i = [ sum_j V_j (x_j - x_i) (x) grad_i W_ij ]^-1,   V_j = m / rho_j.
+ * The matrix M_i in the brackets is symmetric (grad_i W_ij is parallel to
+ * x_i - x_j) and close to the identity for a full support, as in the periodic
+ * box; it is inverted exactly (the paper allows a pseudo-inverse; a singular
+ * M_i gives a zero gradient here). */
+
+/* M_i and g_i = sum_j V_j (A_j - A_i) grad_i W_ij for particle i (dim x dim
+ * row-major and dim). */
+static void renorm_moments(const orc_params* p, int64_t n, const double* u, const double* rho, const double* A,
+                           const nblist* nb, int64_t i, double* M, double* g)
+{
+    int dim = p->dim;
+    double invL = 1.0 / p->L;
+    double ui[3] = {0, 0, 0};
+    for (int k = 0; k < dim; ++k) ui[k] = u[k * n + i];
+    for (int a = 0; a < 9; ++a) M[a] = 0.0;
+    for (int a = 0; a < 3; ++a) g[a] = 0.0;
+    for (int64_t q = nb->off[i]; q < nb->off[i + 1]; ++q) {
+        int64_t j = nb->idx[q];
+        if (j == i) continue;
+        double uj[3] = {0, 0, 0}, e[3] = {0, 0, 0}, w[3] = {0, 0, 0};
+        for (int k = 0; k < dim; ++k) uj[k] = u[k * n + j];
+        minimg(dim, ui, uj, p->L, invL, e);        /* e = x_i - x_j */
+        orc_gradw(dim, p->H, e, w);                /* grad_i W_ij */
+        double Vj = p->m / rho[j];
+        for (int a = 0; a < dim; ++a)
+            for (int b = 0; b < dim; ++b) M[a * dim + b] += Vj * (-e[a]) * w[b];
+        for (int b = 0; b < dim; ++b) g[b] += Vj * (A[j] - A[i]) * w[b];
+    }
+}
+
+/* Inverse of a dim x dim matrix (cofactors); 0 if singular. */
+static int inv_small(int dim, const double* M, double* L)
+{
+    if (dim == 2) {
+        double det = M[0] * M[3] - M[1] * M[2];
+        if (det == 0.0 || !isfinite(det)) return 0;
+        L[0] = M[3] / det;
+        L[1] = -M[1] / det;
+        L[2] = -M[2] / det;
+        L[3] = M[0] / det;
+        return 1;
+    }
+    double c00 = M[4] * M[8] - M[5] * M[7], c01 = M[5] * M[6] - M[3] * M[8], c02 = M[3] * M[7] - M[4] * M[6];
+    double det = M[0] * c00 + M[1] * c01 + M[2] * c02;
+    if (det == 0.0 || !isfinite(det)) return 0;
+    L[0] = c00 / det;
+    L[1] = (M[2] * M[7] - M[1] * M[8]) / det;
+    L[2] = (M[1] * M[5] - M[2] * M[4]) / det;
+    L[3] = c01 / det;
+    L[4] = (M[0] * M[8] - M[2] * M[6]) / det;
+    L[5] = (M[2] * M[3] - M[0] * M[5]) / det;
+    L[6] = c02 / det;
+    L[7] = (M[1] * M[6] - M[0] * M[7]) / det;
+    L[8] = (M[0] * M[4] - M[1] * M[3]) / det;
+    return 1;
+}
+
+/* <grad A>_i for all particles into G (dim*n); Linv (dim*dim*n) receives L_i
+ * when not NULL. */
+static void renorm_gradient(const orc_params* p, int64_t n, const double* u, const double* rho, const double* A,
+                            const nblist* nb, double* G, double* Linv)
+{
+    int dim = p->dim;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        double M[9], g[3], L[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        renorm_moments(p, n, u, rho, A, nb, i, M, g);
+        int ok = inv_small(dim, M, L);
+        for (int a = 0; a < dim; ++a) {
+            double s = 0.0;
+            if (ok)
+                for (int b = 0; b < dim; ++b) s += L[a * dim + b] * g[b];
+            G[a * n + i] = s;
+        }
+        if (Linv)
+            for (int a = 0; a < dim * dim; ++a) Linv[(size_t)a * n + i] = ok ? L[a] : 0.0;
+    }
+}
+
+/* Exported for the checks of the operator itself: G (dim*n) = <grad A> with
+ * V_j from rho. */
+int orc_renorm_gradient(const orc_params* p, int64_t n, const double* x, const double* rho, const double* A,
+                        double* G)
+{
+    if (!valid_params(p) || n < 0) return -1;
+    double* u = (double*)malloc(sizeof(double) * (size_t)p->dim * (size_t)(n > 0 ? n : 1));
+    wrap_all(p, n, x, u);
+    nblist nb;
+    build_lists(p->dim, n, x, p->L, p->H, 0, 0, &nb);
+    renorm_gradient(p, n, u, rho, A, &nb, G, NULL);
+    nblist_free(&nb);
+    free(u);
+    return 0;
+}
+
+/* The renormalised part of the delta-diffusion (Antuono et al.'s form, cited
+ * in Sec. 2.3 through the delta-SPH scheme): with G = <grad rho>,
+ *   drho_i/dt += -delta H c0 sum_j V_j (G_i + G_j) . grad_i W_ij,
+ * added to drho (n). */
+static void renorm_diffusion_add(const orc_params* p, int64_t n, const double* u, const double* rho,
+                                 const nblist* nb, const double* G, double* drho)
+{
+    int dim = p->dim;
+    double invL = 1.0 / p->L;
+    double cd = p->delta * p->H * p->c0;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        double ui[3] = {0, 0, 0};
+        for (int k = 0; k < dim; ++k) ui[k] = u[k * n + i];
+        double t = 0.0;
+        for (int64_t q = nb->off[i]; q < nb->off[i + 1]; ++q) {
+            int64_t j = nb->idx[q];
+            if (j == i) continue;
+            double uj[3] = {0, 0, 0}, e[3] = {0, 0, 0}, w[3] = {0, 0, 0};
+            for (int k = 0; k < dim; ++k) uj[k] = u[k * n + j];
+            minimg(dim, ui, uj, p->L, invL, e);
+            orc_gradw(dim, p->H, e, w);
+            double sw = 0.0;
+            for (int k = 0; k < dim; ++k) sw += (G[k * n + i] + G[k * n + j]) * w[k];
+            t += (p->m / rho[j]) * sw;
+        }
+        drho[i] += -cd * t;
+    }
+}
+
 /* Right-hand side of one evaluation of the update function: drho/dt, a, and
  * (optionally) the summation density.  Gather over the ascending neighbour
  * list; the self pair contributes only m W(0) to rho_sum. */
@@ -648,6 +778,12 @@ static void rhs_with_list(const orc_params* p, int64_t n, const double* u, const
             for (int k = 0; k < dim; ++k) acc[k * n + i] = ai[k];
         if (rhosum) rhosum[i] = rs;
     }
+    if (p->renorm && drho) {
+        double* G = (double*)malloc(sizeof(double) * (size_t)dim * (size_t)(n > 0 ? n : 1));
+        renorm_gradient(p, n, u, rho, rho, nb, G, NULL);
+        renorm_diffusion_add(p, n, u, rho, nb, G, drho);
+        free(G);
+    }
 }
 
 int orc_rhs(const orc_params* p, int64_t n, const double* x, const double* v, const double* rho,
@@ -669,7 +805,7 @@ int orc_rhs(const orc_params* p, int64_t n, const double* x, const double* v, co
 int orc_rhs_sample(const orc_params* p, int64_t n, const double* x, const double* v, const double* rho,
                    int64_t ns, const int64_t* sample, double* drho, double* acc /* dim*ns */, double* rhosum)
 {
-    if (!valid_params(p) || n < 0) return -1;
+    if (!valid_params(p) || p->renorm || n < 0) return -1;
     int dim = p->dim;
     double invL = 1.0 / p->L;
     double H2 = p->H * p->H;
@@ -736,6 +872,9 @@ int orc_step(const orc_params* p, int64_t n, double* x, double* v, double* rho, 
  * cotangents (gx, gv, gr) of the positions, velocities and densities, which
  * gather, for every particle k and neighbour j != k, the partials of the two
  * directed pairs (k,j) and (j,k) that involve k.  Outputs are overwritten. */
+static void renorm_vjp_add(const orc_params* p, int64_t n, const double* u, const double* rho, const nblist* nb,
+                           const double* rbar, double* gx, double* gr);
+
 static void rhs_vjp_with_list(const orc_params* p, int64_t n, const double* u, const double* v,
                               const double* rho, const nblist* nb, const double* abar, const double* rbar,
                               double* gx, double* gv, double* gr)
@@ -778,6 +917,104 @@ static void rhs_vjp_with_list(const orc_params* p, int64_t n, const double* u, c
         }
         gr[k] = sr;
     }
+    if (p->renorm) renorm_vjp_add(p, n, u, rho, nb, rbar, gx, gr);
+}
+
+/* The renormalised diffusion's share of the update function's VJP, for
+ * cotangents rbar of drho/dt, added to gx (positions) and gr (densities);
+ * velocities do not enter.  In scatter form over the lists, sequentially:
+ *  (a) with G fixed: T_i = c sum_j V_j s_ij . w_ij, s_ij = G_i + G_j,
+ *      c = -delta H c0, w_ij = grad_i W_ij at e = x_i - x_j:
+ *        Gbar_i += c rbar_i V_j w_ij,  Gbar_j += c rbar_i V_j w_ij,
+ *        ebar = c rbar_i V_j Hess(e) s_ij   (x_i += ebar, x_j -= ebar),
+ *        rho_j += -(V_j / rho_j) c rbar_i (s_ij . w_ij);
+ *  (b) G_i = L_i g_i:  gbar_i = L_i^T Gbar_i,  Mbar_i = -gbar_i G_i^T;
+ *  (c) M_i = sum_j V_j (-e) (x) w_ij,  g_i = sum_j V_j (rho_j - rho_i) w_ij:
+ *        ebar = -V_j (Mbar_i w + Hess Mbar_i^T e) + V_j (rho_j - rho_i) Hess gbar_i,
+ *        rho_j += V_j (gbar_i . w) - (V_j / rho_j) [(rho_j - rho_i)(gbar_i . w) - e^T Mbar_i w],
+ *        rho_i -= V_j (gbar_i . w). */
+static void renorm_vjp_add(const orc_params* p, int64_t n, const double* u, const double* rho, const nblist* nb,
+                           const double* rbar, double* gx, double* gr)
+{
+    int dim = p->dim;
+    double invL = 1.0 / p->L;
+    double c = -p->delta * p->H * p->c0;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    double* G = (double*)malloc(sizeof(double) * (size_t)dim * nn);
+    double* Linv = (double*)malloc(sizeof(double) * (size_t)dim * (size_t)dim * nn);
+    double* Gb = (double*)calloc((size_t)dim * nn, sizeof(double));
+    renorm_gradient(p, n, u, rho, rho, nb, G, Linv);
+    for (int64_t i = 0; i < n; ++i) {
+        double ui[3] = {0, 0, 0};
+        for (int k = 0; k < dim; ++k) ui[k] = u[k * n + i];
+        for (int64_t q = nb->off[i]; q < nb->off[i + 1]; ++q) {
+            int64_t j = nb->idx[q];
+            if (j == i) continue;
+            double uj[3] = {0, 0, 0}, e[3] = {0, 0, 0}, w[3] = {0, 0, 0}, Hs[9], sv[3] = {0, 0, 0};
+            for (int k = 0; k < dim; ++k) uj[k] = u[k * n + j];
+            minimg(dim, ui, uj, p->L, invL, e);
+            orc_gradw(dim, p->H, e, w);
+            orc_hessw(dim, p->H, e, Hs);
+            double Vj = p->m / rho[j], sw = 0.0;
+            for (int k = 0; k < dim; ++k) {
+                sv[k] = G[k * n + i] + G[k * n + j];
+                sw += sv[k] * w[k];
+            }
+            for (int k = 0; k < dim; ++k) {
+                Gb[k * n + i] += c * rbar[i] * Vj * w[k];
+                Gb[k * n + j] += c * rbar[i] * Vj * w[k];
+                double hs = 0.0;
+                for (int b = 0; b < dim; ++b) hs += Hs[k * dim + b] * sv[b];
+                gx[k * n + i] += c * rbar[i] * Vj * hs;
+                gx[k * n + j] -= c * rbar[i] * Vj * hs;
+            }
+            gr[j] += -(Vj / rho[j]) * c * rbar[i] * sw;
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        double ui[3] = {0, 0, 0}, gbar[3] = {0, 0, 0}, Mb[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int k = 0; k < dim; ++k) ui[k] = u[k * n + i];
+        for (int a = 0; a < dim; ++a)
+            for (int b = 0; b < dim; ++b) gbar[a] += Linv[(size_t)(b * dim + a) * n + i] * Gb[b * n + i];
+        for (int a = 0; a < dim; ++a)
+            for (int b = 0; b < dim; ++b) Mb[a * dim + b] = -gbar[a] * G[b * n + i];
+        for (int64_t q = nb->off[i]; q < nb->off[i + 1]; ++q) {
+            int64_t j = nb->idx[q];
+            if (j == i) continue;
+            double uj[3] = {0, 0, 0}, e[3] = {0, 0, 0}, w[3] = {0, 0, 0}, Hs[9];
+            for (int k = 0; k < dim; ++k) uj[k] = u[k * n + j];
+            minimg(dim, ui, uj, p->L, invL, e);
+            orc_gradw(dim, p->H, e, w);
+            orc_hessw(dim, p->H, e, Hs);
+            double Vj = p->m / rho[j];
+            double Mw[3] = {0, 0, 0}, Mte[3] = {0, 0, 0}, gw = 0.0, eMw = 0.0;
+            for (int a = 0; a < dim; ++a)
+                for (int b = 0; b < dim; ++b) {
+                    Mw[a] += Mb[a * dim + b] * w[b];
+                    Mte[b] += Mb[a * dim + b] * e[a];
+                }
+            for (int k = 0; k < dim; ++k) {
+                gw += gbar[k] * w[k];
+                eMw += e[k] * Mw[k];
+            }
+            double drj = rho[j] - rho[i];
+            for (int k = 0; k < dim; ++k) {
+                double hm = 0.0, hg = 0.0;
+                for (int b = 0; b < dim; ++b) {
+                    hm += Hs[k * dim + b] * Mte[b];
+                    hg += Hs[k * dim + b] * gbar[b];
+                }
+                double eb = -Vj * (Mw[k] + hm) + Vj * drj * hg;
+                gx[k * n + i] += eb;
+                gx[k * n + j] -= eb;
+            }
+            gr[j] += Vj * gw - (Vj / rho[j]) * (drj * gw - eMw);
+            gr[i] -= Vj * gw;
+        }
+    }
+    free(G);
+    free(Linv);
+    free(Gb);
 }
 
 /* Vector-Jacobian product of one step.  On entry (xb, vb, rb) hold the
@@ -874,7 +1111,7 @@ int orc_adjoint_sweep_sample(const orc_params* p, int64_t n, const double* x, co
                              const double* abar, const double* rbar, int64_t ns, const int64_t* sample,
                              double* gx /* dim*ns */, double* gv /* dim*ns */, double* gr /* ns */)
 {
-    if (!valid_params(p) || n < 0) return -1;
+    if (!valid_params(p) || p->renorm || n < 0) return -1;
     int dim = p->dim;
     double invL = 1.0 / p->L;
     double H2 = p->H * p->H;
