@@ -173,6 +173,21 @@ sph_status sph_set_integrator(sph_plan* plan, int32_t stages, const double* A, c
  * afterwards).  Host-side setting. */
 sph_status sph_set_symplectic(sph_plan* plan, int32_t reuse_last_substep);
 
+/* delta-diffusion with the renormalised density gradient (the full delta-SPH
+ * diffusion that Sec. 2.3 cites; the renormalisation of App. A.5).  With
+ * renormalised != 0 every evaluation of the update function first forms, per
+ * particle, G_i = L_i sum_j V_j (rho_j - rho_i) grad_i W_ij with
+ * L_i = [sum_j V_j (x_j - x_i) (x) grad_i W_ij]^-1 (exact inverse; a singular
+ * matrix gives G_i = 0), and adds
+ *     -delta H c0 sum_j V_j (G_i + G_j) . grad_i W_ij
+ * to drho_i/dt.  Applies to sph_rhs, sph_step, sph_step_adjoint and
+ * sph_rollout_backward under every integrator; the adjoint adds the term's
+ * vector-Jacobian product (two extra list passes).  0 returns to the
+ * Molteni-Colagrossi term alone (the default).  The first call with a non-zero
+ * value reserves three records per particle and so grows sph_workspace_size():
+ * make it before sph_bind (CAPACITY afterwards).  Host-side setting. */
+sph_status sph_set_diffusion(sph_plan* plan, int32_t renormalised);
+
 /* Neighbour-list reuse (Verlet lists; the paper keeps one list for short rollouts,
  * Sec. 4.1).  With rebuild_every = R > 1 (needs a skin in every simulation's
  * parameters), a step sorts and rebuilds its lists only when its index within the

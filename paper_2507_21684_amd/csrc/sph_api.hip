@@ -88,8 +88,11 @@ struct sph_plan {
     // symplectic Euler (uses the stage storage with two stages), optionally re-using the last
     // substep's rates as the next predictor's
     bool symplectic = false, symp_reuse = false, rate_tape = false;
+    // delta-diffusion with the renormalised density gradient (records reserved once)
+    bool renorm = false, renorm_reserved = false;
     size_t bytes_base = 0, state_block = 0;
     size_t o_rkU = 0, o_rkK = 0, o_rkUb = 0, o_rkB0 = 0, o_rkTape = 0, o_rkRate = 0;
+    size_t o_jdG = 0, o_jdL = 0, o_gbar = 0;
     int64_t N = 0;
     int64_t ncell = 0, nblk = 0;
     std::vector<sph_params> prm;
@@ -364,16 +367,40 @@ sph_status build_lists(sph_plan* P, int slot, hipStream_t st, bool exact = false
     return SPH_OK;
 }
 
+// Renormalised density gradient of the state sorted into L, with the lists of LL (and L_i
+// when `with_l`, for the adjoint).
+template <typename T, int D, int LPP>
+void launch_renorm(sph_plan* P, const SlotLayout& L, const SlotLayout& LL, hipStream_t st, bool with_l)
+{
+    const int64_t lanes = P->N * LPP;
+    ProfScope prof(P, st, SPH_KERN_OTHER);
+    k_renorm<T, D, LPP><<<grid_for(lanes, 256), 256, 0, st>>>(
+        P->N, P->width, wsp<int32_t>(P, LL.nbr), wsp<int32_t>(P, LL.cnt), wsp<vec4_t<T>>(P, L.jd0),
+        wsp<vec4_t<T>>(P, L.jd1), ws_state<T, D>(P, L.SA).rho, wsp<int32_t>(P, P->o_psim),
+        wsp<SimConst<T>>(P, P->o_simc), P->filter ? 1 : 0, wsp<vec4_t<T>>(P, P->o_jdG),
+        with_l ? wsp<vec4_t<T>>(P, P->o_jdL) : nullptr);
+}
+
 template <typename T, int D, int MODE, int LPP>
 void launch_sweep(sph_plan* P, const SlotLayout& L, const SlotLayout& LL, StatePtrs<T, D> dst, T* drho, T* acc,
                   T* rhosum, NextCells next, NextSlot<T> ns, hipStream_t st, ProfScope* prof)
 {
     const int64_t lanes = P->N * LPP;
-    launch_k(prof, k_sweep<T, D, MODE, LPP>, dim3(grid_for(lanes, 256)), dim3(256), st,
+    if (P->renorm) {
+        launch_k(prof, k_sweep<T, D, MODE, LPP, true>, dim3(grid_for(lanes, 256)), dim3(256), st,
+            P->N, P->width, wsp<int32_t>(P, LL.nbr), wsp<int32_t>(P, LL.cnt), wsp<vec4_t<T>>(P, L.jd0),
+            wsp<vec4_t<T>>(P, L.jd1), ws_state<T, D>(P, L.SA), dst, wsp<int32_t>(P, L.orig), drho, acc, rhosum,
+            wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc), wsp<int32_t>(P, P->o_status), next, ns,
+            P->filter ? 1 : 0, P->filter ? wsp<unsigned long long>(P, P->o_pairs) : nullptr,
+            (const vec4_t<T>*)wsp<vec4_t<T>>(P, P->o_jdG));
+        return;
+    }
+    launch_k(prof, k_sweep<T, D, MODE, LPP, false>, dim3(grid_for(lanes, 256)), dim3(256), st,
         P->N, P->width, wsp<int32_t>(P, LL.nbr), wsp<int32_t>(P, LL.cnt), wsp<vec4_t<T>>(P, L.jd0),
         wsp<vec4_t<T>>(P, L.jd1), ws_state<T, D>(P, L.SA), dst, wsp<int32_t>(P, L.orig), drho, acc, rhosum,
         wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc), wsp<int32_t>(P, P->o_status), next, ns,
-        P->filter ? 1 : 0, P->filter ? wsp<unsigned long long>(P, P->o_pairs) : nullptr);
+        P->filter ? 1 : 0, P->filter ? wsp<unsigned long long>(P, P->o_pairs) : nullptr,
+        (const vec4_t<T>*)nullptr);
 }
 
 // Forward sweep over the state in `slot` with the lists of slot list_of[slot].  MODE step
@@ -398,6 +425,14 @@ sph_status sweep(sph_plan* P, int slot, T* drho, T* acc, T* rhosum, hipStream_t 
         dst = ws_state<T, D>(P, N2.SA);
         ns = NextSlot<T>{wsp<vec4_t<T>>(P, N2.jd0), wsp<vec4_t<T>>(P, N2.jd1), wsp<int32_t>(P, N2.orig),
                          wsp<vec4_t<T>>(P, P->o_uref)};
+    }
+    if (P->renorm) {
+        switch (P->lpp_fwd) {
+        case 2: launch_renorm<T, D, 2>(P, L, LL, st, false); break;
+        case 8: launch_renorm<T, D, 8>(P, L, LL, st, false); break;
+        default: launch_renorm<T, D, 4>(P, L, LL, st, false); break;
+        }
+        LAUNCH_CHECK("renorm");
     }
     ProfScope prof(P, st, SPH_KERN_SWEEP, true);
     switch (P->lpp_fwd) {
@@ -425,11 +460,35 @@ void launch_adj(sph_plan* P, const SlotLayout& L, const SlotLayout& LL, StatePtr
                 bool vjp, ProfScope* prof)
 {
     const int64_t lanes = P->N * LPP;
-    launch_k(prof, k_adj_sweep<T, D, LPP>, dim3(grid_for(lanes, 256)), dim3(256), st,
+    if (P->renorm) {
+        launch_k(prof, k_adj_sweep<T, D, LPP, true>, dim3(grid_for(lanes, 256)), dim3(256), st,
+            P->N, P->width, wsp<int32_t>(P, LL.nbr), wsp<int32_t>(P, LL.cnt), wsp<vec4_t<T>>(P, L.jd0),
+            wsp<vec4_t<T>>(P, L.jd1), wsp<vec4_t<T>>(P, P->o_jdA), wsp<vec4_t<T>>(P, P->o_jdB),
+            wsp<int32_t>(P, L.orig), cot, wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc),
+            wsp<int32_t>(P, P->o_status), P->filter ? 1 : 0, vjp ? 1 : 0,
+            (const vec4_t<T>*)wsp<vec4_t<T>>(P, P->o_jdG), (const vec4_t<T>*)wsp<vec4_t<T>>(P, P->o_jdL),
+            wsp<vec4_t<T>>(P, P->o_gbar));
+        return;
+    }
+    launch_k(prof, k_adj_sweep<T, D, LPP, false>, dim3(grid_for(lanes, 256)), dim3(256), st,
         P->N, P->width, wsp<int32_t>(P, LL.nbr), wsp<int32_t>(P, LL.cnt), wsp<vec4_t<T>>(P, L.jd0),
         wsp<vec4_t<T>>(P, L.jd1), wsp<vec4_t<T>>(P, P->o_jdA), wsp<vec4_t<T>>(P, P->o_jdB), wsp<int32_t>(P, L.orig),
         cot, wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc), wsp<int32_t>(P, P->o_status),
-        P->filter ? 1 : 0, vjp ? 1 : 0);
+        P->filter ? 1 : 0, vjp ? 1 : 0, (const vec4_t<T>*)nullptr, (const vec4_t<T>*)nullptr,
+        (vec4_t<T>*)nullptr);
+}
+
+// Second pass of the renormalised diffusion's adjoint (after the adjoint sweep has written
+// gbar), added to cot.
+template <typename T, int D, int LPP>
+void launch_renorm_adj(sph_plan* P, const SlotLayout& L, const SlotLayout& LL, StatePtrs<T, D> cot, hipStream_t st)
+{
+    const int64_t lanes = P->N * LPP;
+    k_renorm_adj<T, D, LPP><<<grid_for(lanes, 256), 256, 0, st>>>(
+        P->N, P->width, wsp<int32_t>(P, LL.nbr), wsp<int32_t>(P, LL.cnt), wsp<vec4_t<T>>(P, L.jd0),
+        wsp<vec4_t<T>>(P, P->o_jdB), wsp<vec4_t<T>>(P, P->o_jdG), wsp<vec4_t<T>>(P, P->o_gbar),
+        wsp<int32_t>(P, L.orig), cot, wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc),
+        P->filter ? 1 : 0);
 }
 
 // Adjoint of the step that starts from the state in `slot` (sorted with its lists built).
@@ -447,14 +506,34 @@ sph_status adjoint(sph_plan* P, int slot, StatePtrs<T, D> cot, hipStream_t st, b
             wsp<vec4_t<T>>(P, P->o_jdB), wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc), vjp ? 1 : 0);
         LAUNCH_CHECK("adj_prologue");
     }
-    ProfScope prof(P, st, SPH_KERN_ADJOINT, true);
     const SlotLayout& LL = P->slot[P->list_of[slot]];
-    switch (P->lpp_adj) {
-    case 2: launch_adj<T, D, 2>(P, L, LL, cot, st, vjp, &prof); break;
-    case 8: launch_adj<T, D, 8>(P, L, LL, cot, st, vjp, &prof); break;
-    default: launch_adj<T, D, 4>(P, L, LL, cot, st, vjp, &prof); break;
+    if (P->renorm) {
+        // the step's renormalised gradients and L_i, recomputed from its sorted state
+        switch (P->lpp_adj) {
+        case 2: launch_renorm<T, D, 2>(P, L, LL, st, true); break;
+        case 8: launch_renorm<T, D, 8>(P, L, LL, st, true); break;
+        default: launch_renorm<T, D, 4>(P, L, LL, st, true); break;
+        }
+        LAUNCH_CHECK("renorm");
     }
-    LAUNCH_CHECK("adj_sweep");
+    {
+        ProfScope prof(P, st, SPH_KERN_ADJOINT, true);
+        switch (P->lpp_adj) {
+        case 2: launch_adj<T, D, 2>(P, L, LL, cot, st, vjp, &prof); break;
+        case 8: launch_adj<T, D, 8>(P, L, LL, cot, st, vjp, &prof); break;
+        default: launch_adj<T, D, 4>(P, L, LL, cot, st, vjp, &prof); break;
+        }
+        LAUNCH_CHECK("adj_sweep");
+    }
+    if (P->renorm) {
+        ProfScope prof(P, st, SPH_KERN_OTHER);
+        switch (P->lpp_adj) {
+        case 2: launch_renorm_adj<T, D, 2>(P, L, LL, cot, st); break;
+        case 8: launch_renorm_adj<T, D, 8>(P, L, LL, cot, st); break;
+        default: launch_renorm_adj<T, D, 4>(P, L, LL, cot, st); break;
+        }
+        LAUNCH_CHECK("renorm_adj");
+    }
     return SPH_OK;
 }
 
@@ -869,6 +948,7 @@ sph_status run_graphed(sph_plan* P, std::vector<uintptr_t> key, hipStream_t st, 
     key.push_back((uintptr_t)P->reuse);
     key.push_back((uintptr_t)P->rk_stages);
     key.push_back((uintptr_t)(P->symplectic ? 1 + (P->symp_reuse ? 1 : 0) : 0));
+    key.push_back((uintptr_t)(P->renorm ? 1 : 0));
     for (auto& g : P->gcache) {
         if (g.key == key) {
             g.used = ++P->gclock;
@@ -1201,14 +1281,29 @@ sph_status sph_set_tuning(sph_plan* plan, int32_t lanes_fwd, int32_t lanes_adj)
 
 namespace {
 
-// Stage states, stage rates, stage cotangents, the output cotangent and a state tape of
-// tape_depth blocks, after the plan's base workspace; with `rates`, also a tape of as many
-// rate blocks (the symplectic scheme's re-used rates).
-void reserve_stage_storage(sph_plan* P, bool rates)
+// The optional workspace regions after the plan's base workspace, in a fixed order, each
+// present once reserved: the renormalised-gradient records (G, L_i, gbar), then the stage
+// storage (stage states, rates and cotangents, the output cotangent and a state tape of
+// tape_depth blocks), then a tape of as many rate blocks (the symplectic scheme's re-used
+// rates).  Setters that reserve call it before the workspace is bound.
+void layout_extras(sph_plan* P)
 {
     size_t off = P->bytes_base;
     const size_t sb = P->state_block;
     const size_t depth = (size_t)std::max(1, P->tape_depth);
+    if (P->renorm_reserved) {
+        const size_t v4 = align_up(4 * tsize(P) * (size_t)P->N, 256);
+        P->o_jdG = off;
+        off += v4;
+        P->o_jdL = off;
+        off += 2 * v4;
+        P->o_gbar = off;
+        off += v4;
+    }
+    if (P->rk_reserved == 0) {
+        P->bytes = off;
+        return;
+    }
     P->o_rkU = off;
     off += kMaxStages * sb;
     P->o_rkK = off;
@@ -1219,18 +1314,36 @@ void reserve_stage_storage(sph_plan* P, bool rates)
     off += sb;
     P->o_rkTape = off;
     off += depth * sb;
-    if (rates || P->rate_tape) {
+    if (P->rate_tape) {
         P->o_rkRate = off;
         off += depth * sb;
-        P->rate_tape = true;
     }
     P->bytes = off;
+}
+
+void reserve_stage_storage(sph_plan* P, bool rates)
+{
     P->rk_reserved = kMaxStages;
+    if (rates) P->rate_tape = true;
+    layout_extras(P);
 }
 
 }  // namespace
 
 extern "C" {
+
+sph_status sph_set_diffusion(sph_plan* P, int32_t renormalised)
+{
+    if (!P) return fail(SPH_ERR_INVALID_ARG, "plan is null");
+    if (renormalised && !P->renorm_reserved) {
+        if (P->bound) return fail(SPH_ERR_CAPACITY, "renormalisation records were not reserved when the workspace was bound");
+        P->renorm_reserved = true;
+        layout_extras(P);
+    }
+    P->renorm = renormalised != 0;
+    P->clear_graphs();
+    return SPH_OK;
+}
 
 sph_status sph_set_symplectic(sph_plan* P, int32_t reuse_last_substep)
 {

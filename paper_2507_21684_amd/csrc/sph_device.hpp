@@ -776,16 +776,182 @@ constexpr int kModeStep = 0;  // integrate into dst (sorted order)
 constexpr int kModeRhs = 1;   // write drho, a, rho_sum to caller arrays (original order)
 constexpr int kPairsInFlight = 4;  // list positions each lane loads before computing them
 
+// ---------------------------------------------------------------- renormalised density gradient
+//
+// The corrected gradient of App. A.5 applied to the density:
+//   G_i = L_i g_i,  L_i = M_i^-1,  M_i = sum_j V_j (x_j - x_i) (x) grad_i W_ij,
+//   g_i = sum_j V_j (rho_j - rho_i) grad_i W_ij.
+// With grad_i W_ij = gF d (d = x_i - x_j) every pair adds -V_j gF d d^T to M_i (symmetric)
+// and V_j gF (rho_j - rho_i) d to g_i.  Same list traversal and eight canonical partial sums
+// as the sweeps; a singular M_i gives G_i = 0.  G (and the symmetric L when requested) are
+// written in sorted order: 2D L = (L00, L01, L11, 0); 3D L in two records
+// (L00, L01, L02, L11), (L12, L22, 0, 0).
+
+template <typename T, int DIM>
+struct RenormAcc {
+    T M[6];   // 2D: M00, M01, M11; 3D: M00, M01, M02, M11, M12, M22
+    T g[3];
+};
+
+template <typename T, int DIM>
+__device__ __forceinline__ bool inv_sym(const T* M, T* L)
+{
+    if (DIM == 2) {
+        const T det = M[0] * M[2] - M[1] * M[1];
+        if (!(det != T(0)) || !isfinite(det)) return false;
+        const T id = T(1) / det;
+        L[0] = M[2] * id;
+        L[1] = -M[1] * id;
+        L[2] = M[0] * id;
+        return true;
+    }
+    const T a = M[0], b = M[1], c = M[2], d = M[3], e = M[4], f = M[5];
+    const T c00 = d * f - e * e, c01 = c * e - b * f, c02 = b * e - c * d;
+    const T det = a * c00 + b * c01 + c * c02;
+    if (!(det != T(0)) || !isfinite(det)) return false;
+    const T id = T(1) / det;
+    L[0] = c00 * id;
+    L[1] = c01 * id;
+    L[2] = c02 * id;
+    L[3] = (a * f - c * c) * id;
+    L[4] = (b * c - a * e) * id;
+    L[5] = (a * d - b * b) * id;
+    return true;
+}
+
+// y = L x for the symmetric L stored as above.
+template <typename T, int DIM>
+__device__ __forceinline__ void sym_mul(const T* L, const T* x, T* y)
+{
+    if (DIM == 2) {
+        y[0] = L[0] * x[0] + L[1] * x[1];
+        y[1] = L[1] * x[0] + L[2] * x[1];
+        y[2] = T(0);
+    } else {
+        y[0] = L[0] * x[0] + L[1] * x[1] + L[2] * x[2];
+        y[1] = L[1] * x[0] + L[3] * x[1] + L[4] * x[2];
+        y[2] = L[2] * x[0] + L[4] * x[1] + L[5] * x[2];
+    }
+}
+
+template <typename T, int DIM, int LPP>
+__global__ __launch_bounds__(256) void k_renorm(int64_t N, int32_t width, const int32_t* __restrict__ nbr,
+                                                const int32_t* __restrict__ nbr_count,
+                                                const vec4_t<T>* __restrict__ jd0, const vec4_t<T>* __restrict__ jd1,
+                                                const T* __restrict__ rho3, const int32_t* __restrict__ psim,
+                                                const SimConst<T>* __restrict__ sims, int filter,
+                                                vec4_t<T>* __restrict__ G_out, vec4_t<T>* __restrict__ L_out)
+{
+    constexpr int NQ = kLeaves / LPP;
+    constexpr int U = kPairsInFlight;
+    constexpr int NM = DIM == 2 ? 3 : 6;
+    const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int64_t i = t / LPP;
+    const int r = (int)(t - i * LPP);
+    if (i >= N) return;
+    const SimConst<T>& S = sims[psim[i]];
+    const PairConst<T> c = pair_const(S);
+    T ui[3] = {0, 0, 0};
+    unpack_u<T, DIM>(jd0[i], ui);
+    const T rhoi = (DIM == 3) ? rho3[i] : jd1[i].z;
+    int n = nbr_count[i];
+    n = n < width ? n : width;
+    const int mcount = (n - r + LPP - 1) / LPP;
+    const int32_t* row = nbr + i * (int64_t)width;
+    RenormAcc<T, DIM> acc[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+#pragma unroll
+        for (int a = 0; a < 6; ++a) acc[q].M[a] = T(0);
+        acc[q].g[0] = acc[q].g[1] = acc[q].g[2] = T(0);
+    }
+    int jn[U];
+    load_entries<LPP, U>(row, r, 0, mcount, (int)i, jn);
+    for (int m0 = 0; m0 < mcount; m0 += U) {
+        vec4_t<T> a[U];
+        T rj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            a[u] = ldo(jd0, (uint32_t)jn[u]);
+            rj[u] = (DIM == 3) ? ldo(rho3, (uint32_t)jn[u]) : ldo(jd1, (uint32_t)jn[u]).z;
+        }
+        load_entries<LPP, U>(row, r, m0 + U, mcount, (int)i, jn);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (m0 + u >= mcount) continue;
+            T d[3] = {0, 0, 0};
+            const T r2 = r2_exact<T, DIM>(ui, a[u], c.L, c.invL, d);
+            if (filter && !(r2 < c.H2)) continue;
+            const T q = fast_sqrt(r2) * c.invH;
+            const T tt = T(1) - q;
+            const T t2 = tt * tt;
+            const T gF = c.kG * (T(-56.0 / 3.0) * (t2 * t2 * tt) * (T(1) + T(5) * q));
+            const T Vj = (DIM == 3) ? a[u].w : a[u].z;
+            const T f = Vj * gF;
+            RenormAcc<T, DIM>& A = acc[u % NQ];
+            if (DIM == 2) {
+                A.M[0] -= f * d[0] * d[0];
+                A.M[1] -= f * d[0] * d[1];
+                A.M[2] -= f * d[1] * d[1];
+            } else {
+                A.M[0] -= f * d[0] * d[0];
+                A.M[1] -= f * d[0] * d[1];
+                A.M[2] -= f * d[0] * d[2];
+                A.M[3] -= f * d[1] * d[1];
+                A.M[4] -= f * d[1] * d[2];
+                A.M[5] -= f * d[2] * d[2];
+            }
+            const T fr = f * (rj[u] - rhoi);
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) A.g[k] += fr * d[k];
+        }
+    }
+    T M[6], g[3] = {0, 0, 0}, tmp[NQ];
+#pragma unroll
+    for (int e = 0; e < NM; ++e) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) tmp[q] = acc[q].M[e];
+        M[e] = combine_leaves<LPP>(tmp);
+    }
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) tmp[q] = acc[q].g[k];
+        g[k] = combine_leaves<LPP>(tmp);
+    }
+    if (r != 0) return;
+    T L[6] = {0, 0, 0, 0, 0, 0}, G[3] = {0, 0, 0};
+    if (inv_sym<T, DIM>(M, L)) sym_mul<T, DIM>(L, g, G);
+    vec4_t<T> o;
+    o.x = G[0];
+    o.y = G[1];
+    o.z = G[2];
+    o.w = T(0);
+    G_out[i] = o;
+    if (L_out) {
+        vec4_t<T> l0, l1;
+        if (DIM == 2) {
+            l0.x = L[0]; l0.y = L[1]; l0.z = L[2]; l0.w = T(0);
+            L_out[i] = l0;
+        } else {
+            l0.x = L[0]; l0.y = L[1]; l0.z = L[2]; l0.w = L[3];
+            l1.x = L[4]; l1.y = L[5]; l1.z = T(0); l1.w = T(0);
+            L_out[2 * i] = l0;
+            L_out[2 * i + 1] = l1;
+        }
+    }
+}
+
 template <typename T, int DIM>
 struct FwdAcc {
     T ax[3];
-    T rdv, rdd, rs;
+    T rdv, rdd, rs, rdg;
 };
 
 // Per-particle sweep record of a neighbour (jd0, jd1, and rho in 3D).
 template <typename T, int DIM>
 struct FwdNbr {
-    vec4_t<T> a, b;
+    vec4_t<T> a, b, G;
     T rho;
 };
 
@@ -796,9 +962,9 @@ struct FwdNbr {
 // In 3D jd0 = (u, V), jd1 = (v, p V) and rho comes separately; in 2D jd0 = (u, V, p V) and
 // jd1 = (v, rho, 0).  d and r2 are the pair vector x_ij and its square; with keep false the
 // pair is computed but leaves acc unchanged (a select, not a branch).
-template <typename T, int DIM, bool RHOSUM>
+template <typename T, int DIM, bool RHOSUM, bool RENORM>
 __device__ __forceinline__ void fwd_pair(const PairConst<T>& c, const T* vi, T rhoi, T pi, const FwdNbr<T, DIM>& nb,
-                                         const T* d, T r2, bool keep, FwdAcc<T, DIM>& acc)
+                                         const T* Gi, const T* d, T r2, bool keep, FwdAcc<T, DIM>& acc)
 {
     T vj[3];
     T Vj, pVj, rhoj;
@@ -827,6 +993,14 @@ __device__ __forceinline__ void fwd_pair(const PairConst<T>& c, const T* vi, T r
     acc.rdv = keep ? acc.rdv + Vj * (gF * ue) : acc.rdv;
     acc.rdd = keep ? acc.rdd + Vj * (rhoi - rhoj) * (gF * r2 * inv) : acc.rdd;
     if (RHOSUM) acc.rs = keep ? acc.rs + t4 * t2 * (T(1) + q * (T(6) + q * T(35.0 / 3.0))) : acc.rs;
+    if (RENORM) {
+        // V_j (G_i + G_j) . grad_i W_ij of the renormalised diffusion
+        const T Gj[3] = {nb.G.x, nb.G.y, nb.G.z};
+        T sg = T(0);
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) sg += (Gi[k] + Gj[k]) * d[k];
+        acc.rdg = keep ? acc.rdg + Vj * (gF * sg) : acc.rdg;
+    }
 }
 
 // Cell assignment of the next step's sort, done by the sweep that produced the positions
@@ -852,7 +1026,7 @@ struct NextCells {
 // branches out of its instruction stream.  In 2D all wavefronts of a typical launch are
 // resident at once and each lane has few groups; there the per-pair branches, which skip the
 // tail positions that no lane of the wavefront holds, measured faster.
-template <typename T, int DIM, int MODE, int LPP>
+template <typename T, int DIM, int MODE, int LPP, bool RENORM>
 __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const int32_t* __restrict__ nbr,
                                                const int32_t* __restrict__ nbr_count,
                                                const vec4_t<T>* __restrict__ jd0, const vec4_t<T>* __restrict__ jd1,
@@ -862,7 +1036,8 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
                                                const int32_t* __restrict__ psim,
                                                const SimConst<T>* __restrict__ sims, int32_t* __restrict__ status,
                                                NextCells next, NextSlot<T> ns, int filter,
-                                               unsigned long long* __restrict__ pair_counter)
+                                               unsigned long long* __restrict__ pair_counter,
+                                               const vec4_t<T>* __restrict__ jdG)
 {
     constexpr int NQ = kLeaves / LPP;
     constexpr int U = kPairsInFlight;
@@ -881,6 +1056,13 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
     for (int k = 0; k < DIM; ++k) vi[k] = cur.v[k][i];
     const T rhoi = cur.rho[i];
     const T pi = tait(S, rhoi);
+    T Gi[3] = {0, 0, 0};
+    if (RENORM) {
+        const vec4_t<T> g = jdG[i];
+        Gi[0] = g.x;
+        Gi[1] = g.y;
+        Gi[2] = g.z;
+    }
     int n = nbr_count[i];
     n = n < width ? n : width;
     const int mcount = (n - r + LPP - 1) / LPP;
@@ -889,7 +1071,7 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         acc[q].ax[0] = acc[q].ax[1] = acc[q].ax[2] = T(0);
-        acc[q].rdv = acc[q].rdd = acc[q].rs = T(0);
+        acc[q].rdv = acc[q].rdd = acc[q].rs = acc[q].rdg = T(0);
     }
     constexpr bool kSelect = DIM == 3;
     int jn[U];
@@ -906,6 +1088,7 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
             nb[u].a = ldo(jd0, j);
             nb[u].b = ldo(jd1, j);
             nb[u].rho = (DIM == 3) ? ldo(cur.rho, j) : T(0);
+            if (RENORM) nb[u].G = ldo(jdG, j);
         }
         if (kSelect) load_entries_clamped<LPP, U>(row, width, r, m0 + U, mcount, (int)i, jn);
         else load_entries<LPP, U>(row, r, m0 + U, mcount, (int)i, jn);
@@ -917,7 +1100,7 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
             const bool keep = (m0 + u < mcount) && (!filter || r2 < c.H2);
             if (!kSelect && !keep) continue;
             accepted += (filter && keep && jj[u] != (int)i) ? 1 : 0;
-            fwd_pair<T, DIM, MODE == kModeRhs>(c, vi, rhoi, pi, nb[u], d, r2, keep, acc[u % NQ]);
+            fwd_pair<T, DIM, MODE == kModeRhs, RENORM>(c, vi, rhoi, pi, nb[u], Gi, d, r2, keep, acc[u % NQ]);
         }
     }
     T ax[3] = {0, 0, 0};
@@ -940,12 +1123,19 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
         for (int q = 0; q < NQ; ++q) tmp[q] = acc[q].rs;
         rs = combine_leaves<LPP>(tmp);
     }
+    T rdg = 0;
+    if (RENORM) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) tmp[q] = acc[q].rdg;
+        rdg = combine_leaves<LPP>(tmp);
+    }
     if (r == 0) {
     const T invrho = T(1) / rhoi;
     T a[3];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) a[k] = ax[k] * invrho;
-    const T drho = rhoi * rdv + S.cD * rdd;
+    // renormalised diffusion: -delta H c0 sum_j V_j (G_i + G_j) . grad_i W_ij, cD = 2 delta H c0
+    const T drho = RENORM ? rhoi * rdv + S.cD * rdd - T(0.5) * S.cD * rdg : rhoi * rdv + S.cD * rdd;
     if (MODE == kModeStep) {
         bool bad = !isfinite(drho);
         const T dt = S.dt;
@@ -1312,13 +1502,14 @@ template <typename T, int DIM>
 struct AdjAcc {
     T gx[3], gv[3];
     T gr;
+    T Gb[3];   // cotangent of the renormalised density gradient
 };
 
 // Per-particle adjoint record of a neighbour: jd0 = (u, V), jd1 = (v, p V), jdA = (abar, rbar)
 // (2D: (u, V, p V), (v, rho, 0), (abar, rbar, 0)), jdB = (rho, p, 1/rho, dp/drho).
 template <typename T>
 struct AdjNbr {
-    vec4_t<T> a, b, A, B;
+    vec4_t<T> a, b, A, B, G;
 };
 
 // Adjoint pair terms, gather form.  For particle k and a neighbour j != k: the partial
@@ -1327,9 +1518,14 @@ struct AdjNbr {
 // e = x_kj, G = gF e, the kernel Hessian Jg = gF I + hF e e^T, pi = (v_k - v_j).e / (r^2+eps H^2),
 // s = e.G / (r^2+eps H^2), these partials reduce to the closed forms below.  The self pair
 // contributes exactly zero.
-template <typename T, int DIM>
+//
+// With RENORM, the renormalised diffusion T_i = c sum_j V_j (G_i + G_j) . grad_i W_ij
+// (c = -delta H c0) adds, for q = rbar_k V_j - rbar_j V_k and s = G_k + G_j with the
+// gradients held fixed: gx += c q Jg s, Gbar += c q gF e, gr += (V_k / rho_k) c rbar_j gF s.e.
+template <typename T, int DIM, bool RENORM>
 __device__ __forceinline__ void adj_pair(const PairConst<T>& c, const T* uk, const T* vk, const T* ak, T rbk, T Vk,
-                                         T rhok, T pk, T irk, T dpk, const AdjNbr<T>& nb, AdjAcc<T, DIM>& acc)
+                                         T rhok, T pk, T irk, T dpk, const T* Gk, const AdjNbr<T>& nb,
+                                         AdjAcc<T, DIM>& acc)
 {
     T uj[3], vj[3], aj[3];
     T Vj, rbj;
@@ -1389,9 +1585,26 @@ __device__ __forceinline__ void adj_pair(const PairConst<T>& c, const T* uk, con
     const T phi2 = Vk * (-Qj * aGj + rbj * rhoj * uG + rbj * cD * (rhoj - rhok) * sij);
     acc.gr += Vj * (aGk * (-dpk - Qk) * irk + rbk * uG + rbk * cD * sij) - phi2 * irk +
               Vk * (aGj * dpk * irj - rbj * cD * sij);
+    if (RENORM) {
+        const T cr = T(-0.5) * cD;
+        const T Gj[3] = {nb.G.x, nb.G.y, nb.G.z};
+        T sv[3], es = T(0);
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            sv[k] = Gk[k] + Gj[k];
+            es += e[k] * sv[k];
+        }
+        const T qq = cr * (rbk * Vj - rbj * Vk);
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            acc.gx[k] += qq * (gF * sv[k] + hF * es * e[k]);
+            acc.Gb[k] += qq * gF * e[k];
+        }
+        acc.gr += Vk * irk * cr * rbj * gF * es;
+    }
 }
 
-template <typename T, int DIM, int LPP>
+template <typename T, int DIM, int LPP, bool RENORM>
 __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, const int32_t* __restrict__ nbr,
                                                    const int32_t* __restrict__ nbr_count,
                                                    const vec4_t<T>* __restrict__ jd0,
@@ -1401,7 +1614,8 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
                                                    const int32_t* __restrict__ orig, StatePtrs<T, DIM> cot,
                                                    const int32_t* __restrict__ psim,
                                                    const SimConst<T>* __restrict__ sims, int32_t* __restrict__ status,
-                                                   int filter, int vjp)
+                                                   int filter, int vjp, const vec4_t<T>* __restrict__ jdG,
+                                                   const vec4_t<T>* __restrict__ jdL, vec4_t<T>* __restrict__ gbar)
 {
     constexpr int NQ = kLeaves / LPP;
     constexpr int U = kPairsInFlight;
@@ -1429,6 +1643,13 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
     }
     const vec4_t<T> Bk = jdB[k];
     const T rhok = Bk.x, pk = Bk.y, irk = Bk.z, dpk = Bk.w;
+    T Gk[3] = {0, 0, 0};
+    if (RENORM) {
+        const vec4_t<T> g = jdG[k];
+        Gk[0] = g.x;
+        Gk[1] = g.y;
+        Gk[2] = g.z;
+    }
     int n = nbr_count[k];
     n = n < width ? n : width;
     const int mcount = (n - r + LPP - 1) / LPP;
@@ -1437,7 +1658,7 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) acc[q].gx[d] = acc[q].gv[d] = T(0);
+        for (int d = 0; d < 3; ++d) acc[q].gx[d] = acc[q].gv[d] = acc[q].Gb[d] = T(0);
         acc[q].gr = T(0);
     }
     int jn[U];
@@ -1451,6 +1672,7 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
             nb[u].b = ldo(jd1, j);
             nb[u].A = ldo(jdA, j);
             nb[u].B = ldo(jdB, j);
+            if (RENORM) nb[u].G = ldo(jdG, j);
         }
         load_entries<LPP, U>(row, r, m0 + U, mcount, (int)k, jn);
 #pragma unroll
@@ -1458,7 +1680,7 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
             if (m0 + u >= mcount) continue;
             T e_[3];
             if (filter && !(r2_exact<T, DIM>(uk, nb[u].a, c.L, c.invL, e_) < c.H2)) continue;
-            adj_pair<T, DIM>(c, uk, vk, ak, rbk, Vk, rhok, pk, irk, dpk, nb[u], acc[u % NQ]);
+            adj_pair<T, DIM, RENORM>(c, uk, vk, ak, rbk, Vk, rhok, pk, irk, dpk, Gk, nb[u], acc[u % NQ]);
         }
     }
     T gx[3] = {0, 0, 0}, gv[3] = {0, 0, 0};
@@ -1475,7 +1697,35 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
 #pragma unroll
     for (int q = 0; q < NQ; ++q) tmp[q] = acc[q].gr;
     const T gr = combine_leaves<LPP>(tmp);
+    T Gb[3] = {0, 0, 0};
+    if (RENORM) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) tmp[q] = acc[q].Gb[d];
+            Gb[d] = combine_leaves<LPP>(tmp);
+        }
+    }
     if (r != 0) return;
+    if (RENORM) {
+        // gbar_k = L_k^T Gbar_k (L symmetric), for the second renormalisation pass
+        T L[6] = {0, 0, 0, 0, 0, 0};
+        if (DIM == 2) {
+            const vec4_t<T> l0 = jdL[k];
+            L[0] = l0.x; L[1] = l0.y; L[2] = l0.z;
+        } else {
+            const vec4_t<T> l0 = jdL[2 * k], l1 = jdL[2 * k + 1];
+            L[0] = l0.x; L[1] = l0.y; L[2] = l0.z; L[3] = l0.w; L[4] = l1.x; L[5] = l1.y;
+        }
+        T gb[3];
+        sym_mul<T, DIM>(L, Gb, gb);
+        vec4_t<T> o4;
+        o4.x = gb[0];
+        o4.y = gb[1];
+        o4.z = gb[2];
+        o4.w = T(0);
+        gbar[k] = o4;
+    }
     const int o = orig[k];
     const T dt = S.dt;
     bool bad = !isfinite(gr);
@@ -1495,6 +1745,116 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
     }
     cot.rho[o] = vjp ? gr : cot.rho[o] + gr;
     if (bad) atomicOr(&status[s], kFlagNonfinite);
+}
+
+// Second pass of the renormalised diffusion's adjoint: the cotangents of the moment sums
+// M_i, g_i (Mbar_i = -gbar_i G_i^T, gbar_i = L_i Gbar_i from the adjoint sweep) carried to
+// positions and densities, gathered over each particle's own sums and its neighbours':
+//   own (e = x_k - x_j, w = gF e, Jg v = gF v + hF (e.v) e):
+//     xbar_k += V_j [gbar_k (G_k.w) + Jg G_k (gbar_k.e)] + V_j (rho_j - rho_k) Jg gbar_k
+//     rbar_k -= V_j (gbar_k.w)
+//   neighbour's:
+//     xbar_k += V_k [gbar_j (G_j.w) + Jg G_j (gbar_j.e)] - V_k (rho_k - rho_j) Jg gbar_j
+//     rbar_k += -V_k (gbar_j.w) + (V_k / rho_k) [(rho_k - rho_j)(gbar_j.w) - (e.gbar_j)(G_j.w)]
+// added to the cotangents (original order).  Same list traversal and partial sums.
+template <typename T, int DIM, int LPP>
+__global__ __launch_bounds__(256) void k_renorm_adj(int64_t N, int32_t width, const int32_t* __restrict__ nbr,
+                                                    const int32_t* __restrict__ nbr_count,
+                                                    const vec4_t<T>* __restrict__ jd0, const vec4_t<T>* __restrict__ jdB,
+                                                    const vec4_t<T>* __restrict__ jdG,
+                                                    const vec4_t<T>* __restrict__ gbar,
+                                                    const int32_t* __restrict__ orig, StatePtrs<T, DIM> cot,
+                                                    const int32_t* __restrict__ psim,
+                                                    const SimConst<T>* __restrict__ sims, int filter)
+{
+    constexpr int NQ = kLeaves / LPP;
+    constexpr int U = kPairsInFlight;
+    const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int64_t k = t / LPP;
+    const int r = (int)(t - k * LPP);
+    if (k >= N) return;
+    const SimConst<T>& S = sims[psim[k]];
+    const PairConst<T> c = pair_const(S);
+    const vec4_t<T> a0 = jd0[k];
+    T uk[3] = {0, 0, 0};
+    unpack_u<T, DIM>(a0, uk);
+    const T Vk = (DIM == 3) ? a0.w : a0.z;
+    const T rhok = jdB[k].x;
+    const vec4_t<T> g4 = jdG[k], b4 = gbar[k];
+    const T Gk[3] = {g4.x, g4.y, g4.z}, bk[3] = {b4.x, b4.y, b4.z};
+    int n = nbr_count[k];
+    n = n < width ? n : width;
+    const int mcount = (n - r + LPP - 1) / LPP;
+    const int32_t* row = nbr + k * (int64_t)width;
+    T ax[NQ][3], ar[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) ax[q][0] = ax[q][1] = ax[q][2] = ar[q] = T(0);
+    int jn[U];
+    load_entries<LPP, U>(row, r, 0, mcount, (int)k, jn);
+    for (int m0 = 0; m0 < mcount; m0 += U) {
+        vec4_t<T> na[U], nB[U], nG[U], nb[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t j = (uint32_t)jn[u];
+            na[u] = ldo(jd0, j);
+            nB[u] = ldo(jdB, j);
+            nG[u] = ldo(jdG, j);
+            nb[u] = ldo(gbar, j);
+        }
+        load_entries<LPP, U>(row, r, m0 + U, mcount, (int)k, jn);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (m0 + u >= mcount) continue;
+            T e[3] = {0, 0, 0};
+            const T r2 = r2_exact<T, DIM>(uk, na[u], c.L, c.invL, e);
+            if (filter && !(r2 < c.H2)) continue;
+            const T q = fast_sqrt(r2) * c.invH;
+            const T tt = T(1) - q;
+            const T t2 = tt * tt;
+            const T t4 = t2 * t2;
+            const T gF = c.kG * (T(-56.0 / 3.0) * t4 * tt * (T(1) + T(5) * q));
+            const T hF = c.kH * t4;
+            const T Vj = (DIM == 3) ? na[u].w : na[u].z;
+            const T rhoj = nB[u].x;
+            const T Gj[3] = {nG[u].x, nG[u].y, nG[u].z}, bj[3] = {nb[u].x, nb[u].y, nb[u].z};
+            T bke = 0, bje = 0, Gke = 0, Gje = 0;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                Gke += Gk[d] * e[d];
+                bke += bk[d] * e[d];
+                Gje += Gj[d] * e[d];
+                bje += bj[d] * e[d];
+            }
+            const T Gkw = gF * Gke, Gjw = gF * Gje, bkw = gF * bke, bjw = gF * bje;
+            const T drk = rhoj - rhok;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                // Jg v = gF v + hF (e.v) e
+                const T JGk = gF * Gk[d] + hF * Gke * e[d];
+                const T Jbk = gF * bk[d] + hF * bke * e[d];
+                const T JGj = gF * Gj[d] + hF * Gje * e[d];
+                const T Jbj = gF * bj[d] + hF * bje * e[d];
+                ax[u % NQ][d] += Vj * (bk[d] * Gkw + JGk * bke) + Vj * drk * Jbk +
+                                 Vk * (bj[d] * Gjw + JGj * bje) + Vk * drk * Jbj;
+            }
+            ar[u % NQ] += -Vj * bkw - Vk * bjw + (Vk / rhok) * (-drk * bjw - bje * Gjw);
+        }
+    }
+    T gx[3] = {0, 0, 0}, tmp[NQ];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) tmp[q] = ax[q][d];
+        gx[d] = combine_leaves<LPP>(tmp);
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) tmp[q] = ar[q];
+    const T gr = combine_leaves<LPP>(tmp);
+    if (r != 0) return;
+    const int o = orig[k];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) cot.x[d][o] += gx[d];
+    cot.rho[o] += gr;
 }
 
 // ---------------------------------------------------------------- neighbour export (CSR, original indices)

@@ -68,6 +68,8 @@ def lib():
         L.sph_set_integrator.restype = st
         L.sph_set_integrator.argtypes = [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double)]
+        L.sph_set_diffusion.restype = st
+        L.sph_set_diffusion.argtypes = [_VP, ctypes.c_int32]
         L.sph_set_symplectic.restype = st
         L.sph_set_symplectic.argtypes = [_VP, ctypes.c_int32]
         L.sph_set_reuse.restype = st
@@ -123,7 +125,7 @@ def exported_symbols() -> List[str]:
             "sph_build_cells", "sph_neighbors", "sph_rhs", "sph_step", "sph_step_adjoint", "sph_poll",
             "sph_pair_count", "sph_profile_enable", "sph_profile_read", "sph_last_error", "sph_set_tuning",
             "sph_get_tuning", "sph_rollout_backward", "sph_set_graphs", "sph_density_adjoint", "sph_set_reuse",
-            "sph_set_integrator", "sph_set_symplectic"]
+            "sph_set_integrator", "sph_set_symplectic", "sph_set_diffusion"]
 
 
 KERNEL_CLASSES = ["sort", "build", "sweep", "adjoint", "other"]
@@ -204,7 +206,7 @@ class Plan:
 
     def __init__(self, sims: Sequence[dict], counts: Sequence[int], dtype: str = "f32",
                  max_neighbors: int = 0, tape_depth: int = 8, device: Optional[torch.device] = None,
-                 stream=None, skin=0.0, rebuild_every: int = 1, integrator=None):
+                 stream=None, skin=0.0, rebuild_every: int = 1, integrator=None, renormalised_diffusion: bool = False):
         L = lib()
         self.dtype = dtype
         self.torch_dtype = torch.float64 if dtype == "f64" else torch.float32
@@ -215,12 +217,15 @@ class Plan:
         cnt = (ctypes.c_int64 * n)(*[int(c) for c in counts])
         h = _VP()
         _check(L.sph_plan_create(arr, n, cnt, int(max_neighbors), int(tape_depth), ctypes.byref(h)))
-        if integrator is not None:
-            try:
+        try:
+            if integrator is not None:
                 _set_integrator(h, integrator)   # before the workspace is sized
-            except Exception:
-                L.sph_plan_destroy(h)
-                raise
+            if renormalised_diffusion:
+                _check(L.sph_set_diffusion(h, 1))
+        except Exception:
+            L.sph_plan_destroy(h)
+            raise
+        self.renormalised_diffusion = bool(renormalised_diffusion)
         self.integrator = integrator or "semi_implicit_euler"
         self.tape_depth = int(tape_depth)
         self.skins = skins

@@ -187,3 +187,37 @@ def test_symplectic_setting_reserves_a_rate_tape():
     assert sizes["symp"] - sizes["rk"] >= 4 * block
     assert sizes["symp_after_rk"] == sizes["symp"]
     assert L.lib().sph_set_symplectic(None, 0) != 0
+
+
+def test_diffusion_setting_reserves_records_in_any_order():
+    """sph_set_diffusion and the integrator settings reserve disjoint regions whatever the order."""
+    import ctypes
+    from paper_2507_21684_amd.inputs import SimSpec
+    spec = SimSpec(2, 32)
+    arr = (L.SphParams * 1)(L.make_params(spec.params(), "f32"))
+    cnt = (ctypes.c_int64 * 1)(spec.n)
+
+    def size_after(steps):
+        h = L._VP()
+        assert L.lib().sph_plan_create(arr, 1, cnt, 0, 4, ctypes.byref(h)) == 0
+        for st in steps:
+            if st == "renorm":
+                assert L.lib().sph_set_diffusion(h, 1) == 0
+            elif st == "plain":
+                assert L.lib().sph_set_diffusion(h, 0) == 0
+            else:
+                L._set_integrator(h, st)
+        sz = ctypes.c_size_t()
+        L.lib().sph_workspace_size(h, ctypes.byref(sz))
+        L.lib().sph_plan_destroy(h)
+        return sz.value
+
+    base = size_after([])
+    rn = size_after(["renorm"])
+    assert rn - base >= 4 * 16 * spec.n                      # G, two L records and gbar per particle
+    assert size_after(["plain"]) == base                     # the default reserves nothing
+    assert size_after(["renorm", "plain", "renorm"]) == rn
+    a = size_after(["renorm", "symplectic_euler_reuse"])
+    b = size_after(["symplectic_euler_reuse", "renorm"])
+    assert a == b == size_after(["symplectic_euler"]) + (rn - base)
+    assert L.lib().sph_set_diffusion(None, 1) != 0
