@@ -416,6 +416,27 @@ def bench_symplectic(dev, reps=3):
     return out
 
 
+def bench_renorm(dev, wl, x0, v0, r0, skin, R, lanes, ms_plain, pairs, reps=3):
+    """The default job with the renormalised delta-diffusion (one extra list pass per right-hand
+    side, two per adjoint step) on the same list settings and lanes as the plain job."""
+    import torch
+    from paper_2507_21684_amd.lib import Plan
+    plan = Plan([s.params() for s in wl.sims], [s.n for s in wl.sims], wl.dtype, tape_depth=wl.ckpt_every,
+                device=dev, skin=skin, rebuild_every=R, renormalised_diffusion=True)
+    plan.set_tuning(*lanes)
+    run_job(plan, x0, v0, r0, wl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        run_job(plan, x0, v0, r0, wl)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    assert all(plan.poll() == 0)
+    return {"workload": wl.name + "_renormalised_diffusion", "ms_per_job": round(t * 1e3, 3),
+            "value": round(pairs / t, 1), "unit": "pair interactions/s",
+            "cost_vs_plain_diffusion": round(t * 1e3 / ms_plain, 3)}
+
+
 def log(msg):
     """Progress line on stderr (the JSON result is the only line on stdout)."""
     print("[bench] " + msg, file=sys.stderr, flush=True)
@@ -578,10 +599,13 @@ def main():
         log("batched workload")
         batched = bench_batched(dev, max(1, min(args.steps, 3)))
 
-    dens = None
+    dens = renorm = None
     if args.workload == "tgv2d_64k_f32":
         log("density backward benchmark")
         dens = bench_density_backward(dev)
+        log("renormalised diffusion job")
+        renorm = bench_renorm(dev, wl, x0, v0, r0, list_skin, list_rebuild, lanes, 1e3 * elapsed / args.steps,
+                              p_fwd + p_adj)
 
     rk4 = symp = None
     if args.workload == "tgv2d_64k_f32":
@@ -607,7 +631,8 @@ def main():
                       "lanes_per_particle": list(lanes), "list_skin": list_skin,
                       "list_rebuild_every": list_rebuild},
            "roofline": roof, "kernel_ms_per_job": breakdown, "cpu_baseline": cpu, "batched": batched, "serving": served,
-           "density_backward": dens, "rk4": rk4, "symplectic": symp}
+           "density_backward": dens, "rk4": rk4, "symplectic": symp,
+           "renormalised_diffusion": renorm}
     print(json.dumps(out), flush=True)
 
 
