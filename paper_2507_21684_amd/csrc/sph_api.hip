@@ -103,6 +103,10 @@ struct sph_plan {
     size_t o_simc = 0, o_psim = 0, o_cell_sim = 0, o_blk_coord = 0, o_blk_rank = 0;
     size_t o_cell_count = 0, o_cell_start = 0, o_part = 0, o_cell_of = 0, o_slot_of = 0, o_tmp = 0;
     size_t o_SB = 0, o_jdA = 0, o_jdB = 0, o_status = 0, o_part64 = 0, o_pairs = 0, o_ticket = 0, o_uref = 0;
+    // two buffers of adjoint prologue records; adj_buf is the one in use, and adj_ready the tape
+    // slot whose records an adjoint sweep has already written there (-1: none)
+    size_t o_jdA2 = 0, o_jdB2 = 0;
+    int adj_buf = 0, adj_ready = -1;
     std::vector<SlotLayout> slot;
     int64_t nparts = 0, nparts64 = 0;
     size_t bytes = 0;
@@ -455,27 +459,30 @@ sph_status unsort_from(sph_plan* P, StatePtrs<T, D> src, int slot, StatePtrs<T, 
     return SPH_OK;
 }
 
+size_t jdA_off(const sph_plan* P, int buf) { return buf ? P->o_jdA2 : P->o_jdA; }
+size_t jdB_off(const sph_plan* P, int buf) { return buf ? P->o_jdB2 : P->o_jdB; }
+
 template <typename T, int D, int LPP>
 void launch_adj(sph_plan* P, const SlotLayout& L, const SlotLayout& LL, StatePtrs<T, D> cot, hipStream_t st,
-                bool vjp, ProfScope* prof)
+                bool vjp, ProfScope* prof, NextAdj<T> na)
 {
     const int64_t lanes = P->N * LPP;
     if (P->renorm) {
         launch_k(prof, k_adj_sweep<T, D, LPP, true>, dim3(grid_for(lanes, 256)), dim3(256), st,
             P->N, P->width, wsp<int32_t>(P, LL.nbr), wsp<int32_t>(P, LL.cnt), wsp<vec4_t<T>>(P, L.jd0),
-            wsp<vec4_t<T>>(P, L.jd1), wsp<vec4_t<T>>(P, P->o_jdA), wsp<vec4_t<T>>(P, P->o_jdB),
-            wsp<int32_t>(P, L.orig), cot, wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc),
-            wsp<int32_t>(P, P->o_status), P->filter ? 1 : 0, vjp ? 1 : 0,
+            wsp<vec4_t<T>>(P, L.jd1), wsp<vec4_t<T>>(P, jdA_off(P, P->adj_buf)),
+            wsp<vec4_t<T>>(P, jdB_off(P, P->adj_buf)), wsp<int32_t>(P, L.orig), cot, wsp<int32_t>(P, P->o_psim),
+            wsp<SimConst<T>>(P, P->o_simc), wsp<int32_t>(P, P->o_status), P->filter ? 1 : 0, vjp ? 1 : 0,
             (const vec4_t<T>*)wsp<vec4_t<T>>(P, P->o_jdG), (const vec4_t<T>*)wsp<vec4_t<T>>(P, P->o_jdL),
-            wsp<vec4_t<T>>(P, P->o_gbar));
+            wsp<vec4_t<T>>(P, P->o_gbar), na);
         return;
     }
     launch_k(prof, k_adj_sweep<T, D, LPP, false>, dim3(grid_for(lanes, 256)), dim3(256), st,
         P->N, P->width, wsp<int32_t>(P, LL.nbr), wsp<int32_t>(P, LL.cnt), wsp<vec4_t<T>>(P, L.jd0),
-        wsp<vec4_t<T>>(P, L.jd1), wsp<vec4_t<T>>(P, P->o_jdA), wsp<vec4_t<T>>(P, P->o_jdB), wsp<int32_t>(P, L.orig),
-        cot, wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc), wsp<int32_t>(P, P->o_status),
-        P->filter ? 1 : 0, vjp ? 1 : 0, (const vec4_t<T>*)nullptr, (const vec4_t<T>*)nullptr,
-        (vec4_t<T>*)nullptr);
+        wsp<vec4_t<T>>(P, L.jd1), wsp<vec4_t<T>>(P, jdA_off(P, P->adj_buf)),
+        wsp<vec4_t<T>>(P, jdB_off(P, P->adj_buf)), wsp<int32_t>(P, L.orig), cot, wsp<int32_t>(P, P->o_psim),
+        wsp<SimConst<T>>(P, P->o_simc), wsp<int32_t>(P, P->o_status), P->filter ? 1 : 0, vjp ? 1 : 0,
+        (const vec4_t<T>*)nullptr, (const vec4_t<T>*)nullptr, (vec4_t<T>*)nullptr, na);
 }
 
 // Second pass of the renormalised diffusion's adjoint (after the adjoint sweep has written
@@ -486,7 +493,7 @@ void launch_renorm_adj(sph_plan* P, const SlotLayout& L, const SlotLayout& LL, S
     const int64_t lanes = P->N * LPP;
     k_renorm_adj<T, D, LPP><<<grid_for(lanes, 256), 256, 0, st>>>(
         P->N, P->width, wsp<int32_t>(P, LL.nbr), wsp<int32_t>(P, LL.cnt), wsp<vec4_t<T>>(P, L.jd0),
-        wsp<vec4_t<T>>(P, P->o_jdB), wsp<vec4_t<T>>(P, P->o_jdG), wsp<vec4_t<T>>(P, P->o_gbar),
+        wsp<vec4_t<T>>(P, jdB_off(P, P->adj_buf)), wsp<vec4_t<T>>(P, P->o_jdG), wsp<vec4_t<T>>(P, P->o_gbar),
         wsp<int32_t>(P, L.orig), cot, wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc),
         P->filter ? 1 : 0);
 }
@@ -494,18 +501,29 @@ void launch_renorm_adj(sph_plan* P, const SlotLayout& L, const SlotLayout& LL, S
 // Adjoint of the step that starts from the state in `slot` (sorted with its lists built).
 // With vjp, the update function's VJP instead: cot holds the cotangents (kx, ka, krho) of
 // (v, a, drho/dt) on entry and (xbar, vbar, rhobar) on exit.
+// With next_slot >= 0 (a tape slot sharing this slot's particle order, whose adjoint runs next),
+// the sweep also writes that step's prologue records into the other buffer, and the next call
+// skips its prologue.
 template <typename T, int D>
-sph_status adjoint(sph_plan* P, int slot, StatePtrs<T, D> cot, hipStream_t st, bool vjp = false)
+sph_status adjoint(sph_plan* P, int slot, StatePtrs<T, D> cot, hipStream_t st, bool vjp = false,
+                   int next_slot = -1)
 {
     if (P->N == 0) return SPH_OK;
     const SlotLayout& L = P->slot[slot];
-    {
+    if (P->adj_ready != slot) {
         ProfScope prof(P, st, SPH_KERN_OTHER);
         k_adj_prologue<T, D><<<grid_for(P->N, 256), 256, 0, st>>>(
-            P->N, wsp<int32_t>(P, L.orig), cot, ws_state<T, D>(P, L.SA), wsp<vec4_t<T>>(P, P->o_jdA),
-            wsp<vec4_t<T>>(P, P->o_jdB), wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc), vjp ? 1 : 0);
+            P->N, wsp<int32_t>(P, L.orig), cot, ws_state<T, D>(P, L.SA), wsp<vec4_t<T>>(P, jdA_off(P, P->adj_buf)),
+            wsp<vec4_t<T>>(P, jdB_off(P, P->adj_buf)), wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc),
+            vjp ? 1 : 0);
         LAUNCH_CHECK("adj_prologue");
     }
+    P->adj_ready = -1;
+    const bool fuse = next_slot >= 0 && !vjp && !P->renorm;
+    NextAdj<T> na{nullptr, nullptr, nullptr};
+    if (fuse)
+        na = NextAdj<T>{wsp<vec4_t<T>>(P, jdA_off(P, 1 - P->adj_buf)), wsp<vec4_t<T>>(P, jdB_off(P, 1 - P->adj_buf)),
+                        ws_state<T, D>(P, P->slot[next_slot].SA).rho};
     const SlotLayout& LL = P->slot[P->list_of[slot]];
     if (P->renorm) {
         // the step's renormalised gradients and L_i, recomputed from its sorted state
@@ -519,9 +537,9 @@ sph_status adjoint(sph_plan* P, int slot, StatePtrs<T, D> cot, hipStream_t st, b
     {
         ProfScope prof(P, st, SPH_KERN_ADJOINT, true);
         switch (P->lpp_adj) {
-        case 2: launch_adj<T, D, 2>(P, L, LL, cot, st, vjp, &prof); break;
-        case 8: launch_adj<T, D, 8>(P, L, LL, cot, st, vjp, &prof); break;
-        default: launch_adj<T, D, 4>(P, L, LL, cot, st, vjp, &prof); break;
+        case 2: launch_adj<T, D, 2>(P, L, LL, cot, st, vjp, &prof, na); break;
+        case 8: launch_adj<T, D, 8>(P, L, LL, cot, st, vjp, &prof, na); break;
+        default: launch_adj<T, D, 4>(P, L, LL, cot, st, vjp, &prof, na); break;
         }
         LAUNCH_CHECK("adj_sweep");
     }
@@ -533,6 +551,10 @@ sph_status adjoint(sph_plan* P, int slot, StatePtrs<T, D> cot, hipStream_t st, b
         default: launch_renorm_adj<T, D, 4>(P, L, LL, cot, st); break;
         }
         LAUNCH_CHECK("renorm_adj");
+    }
+    if (fuse) {
+        P->adj_buf = 1 - P->adj_buf;
+        P->adj_ready = next_slot;
     }
     return SPH_OK;
 }
@@ -929,7 +951,13 @@ sph_status do_rollout_backward(sph_plan* P, const sph_state* ckpt, int32_t nstep
         const int32_t len = std::min(every, nsteps - seg * every);
         int last = 0;
         RC_TRY((run_steps<T, D>(P, user_state<T, D>(&ckpt[seg]), len, true, false, nullptr, 1, &last, st)));
-        for (int32_t t = len - 1; t >= 0; --t) RC_TRY((adjoint<T, D>(P, t, c, st)));
+        P->adj_buf = 0;
+        P->adj_ready = -1;
+        for (int32_t t = len - 1; t >= 0; --t) {
+            // the step before shares this state's particle order when no sort happened in between
+            const int next = (t > 0 && P->list_of[t] == P->list_of[t - 1]) ? t - 1 : -1;
+            RC_TRY((adjoint<T, D>(P, t, c, st, false, next)));
+        }
     }
     return SPH_OK;
 }
@@ -1226,6 +1254,8 @@ sph_status sph_plan_create(const sph_params* sims, int32_t nsims, const int64_t*
     P->o_SB = take(T * N * (2 * d + 1));
     P->o_jdA = take(V4 * N);
     P->o_jdB = take(V4 * N);
+    P->o_jdA2 = take(V4 * N);
+    P->o_jdB2 = take(V4 * N);
     P->o_status = take(4 * (size_t)nsims);
     P->o_part64 = take(8 * ((size_t)P->nparts64 + 1) + 8 * (N + 1));
     P->o_pairs = take(8 * (size_t)kPairSlots * kPairStride);
@@ -1515,6 +1545,7 @@ sph_status sph_step_adjoint(sph_plan* P, const sph_state* s_n, sph_state* cot, v
     RC_TRY(check_bound(P));
     RC_TRY(check_state(P, s_n, "state"));
     RC_TRY(check_state(P, cot, "cotangent"));
+    P->adj_ready = -1;
     return DISPATCH(P, do_step_adjoint, P, s_n, cot, (hipStream_t)stream);
 }
 
@@ -1544,6 +1575,7 @@ sph_status sph_rollout_backward(sph_plan* P, const sph_state* ckpt, int32_t nste
         return fail(SPH_ERR_INVALID_ARG, "ckpt_every must be a multiple of the list reuse interval");
     const int32_t nseg = nsteps > 0 ? (nsteps + ckpt_every - 1) / ckpt_every : 0;
     for (int32_t k = 0; k < nseg; ++k) RC_TRY(check_state(P, &ckpt[k], "checkpoint slot"));
+    P->adj_ready = -1;
     std::vector<uintptr_t> key = {2u, (uintptr_t)nsteps, (uintptr_t)ckpt_every};
     key_state(key, cot);
     for (int32_t k = 0; k < nseg; ++k) key_state(key, &ckpt[k]);

@@ -1498,6 +1498,16 @@ __global__ __launch_bounds__(256) void k_adj_prologue(int64_t N, const int32_t* 
     jdB[q] = b;
 }
 
+// What the adjoint sweep of step t prepares for the adjoint of step t - 1 when both states share
+// the particle order (a step within one list-reuse interval): the prologue records of step t - 1
+// at the same sorted index, from the cotangents the sweep has just formed (null jdA: none).
+template <typename T>
+struct NextAdj {
+    vec4_t<T>* jdA;
+    vec4_t<T>* jdB;
+    const T* rho;   // densities of state t - 1, sorted order
+};
+
 template <typename T, int DIM>
 struct AdjAcc {
     T gx[3], gv[3];
@@ -1615,7 +1625,8 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
                                                    const int32_t* __restrict__ psim,
                                                    const SimConst<T>* __restrict__ sims, int32_t* __restrict__ status,
                                                    int filter, int vjp, const vec4_t<T>* __restrict__ jdG,
-                                                   const vec4_t<T>* __restrict__ jdL, vec4_t<T>* __restrict__ gbar)
+                                                   const vec4_t<T>* __restrict__ jdL, vec4_t<T>* __restrict__ gbar,
+                                                   NextAdj<T> na)
 {
     constexpr int NQ = kLeaves / LPP;
     constexpr int U = kPairsInFlight;
@@ -1729,22 +1740,47 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
     const int o = orig[k];
     const T dt = S.dt;
     bool bad = !isfinite(gr);
+    T xn[3] = {0, 0, 0}, vn[3] = {0, 0, 0};
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
         const T xb = cot.x[d][o];
         const T vb = cot.v[d][o];
         if (vjp) {
             // (xbar, vbar, rhobar) = (J_x^T, kx + J_v^T, J_rho^T): dx/dt = v adds kx to vbar
-            cot.x[d][o] = gx[d];
-            cot.v[d][o] = xb + gv[d];
+            xn[d] = gx[d];
+            vn[d] = xb + gv[d];
         } else {
-            cot.x[d][o] = xb + gx[d];
-            cot.v[d][o] = vb + dt * xb + gv[d];
+            xn[d] = xb + gx[d];
+            vn[d] = vb + dt * xb + gv[d];
         }
+        cot.x[d][o] = xn[d];
+        cot.v[d][o] = vn[d];
         bad = bad || !isfinite(gx[d]) || !isfinite(gv[d]);
     }
-    cot.rho[o] = vjp ? gr : cot.rho[o] + gr;
+    const T rn = vjp ? gr : cot.rho[o] + gr;
+    cot.rho[o] = rn;
     if (bad) atomicOr(&status[s], kFlagNonfinite);
+    if (na.jdA) {
+        // the prologue of the previous step's adjoint (same arithmetic as k_adj_prologue)
+        T ab[3] = {0, 0, 0};
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) ab[d] = dt * (vn[d] + dt * xn[d]);
+        const T rb = dt * rn;
+        vec4_t<T> a;
+        if (DIM == 3) {
+            a.x = ab[0]; a.y = ab[1]; a.z = ab[2]; a.w = rb;
+        } else {
+            a.x = ab[0]; a.y = ab[1]; a.z = rb; a.w = T(0);
+        }
+        na.jdA[k] = a;
+        const T rho = na.rho[k];
+        vec4_t<T> b;
+        b.x = rho;
+        b.y = tait(S, rho);
+        b.z = T(1) / rho;
+        b.w = tait_slope(S, rho);
+        na.jdB[k] = b;
+    }
 }
 
 // Second pass of the renormalised diffusion's adjoint: the cotangents of the moment sums
