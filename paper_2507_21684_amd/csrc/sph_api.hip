@@ -683,6 +683,28 @@ sph_status lincomb(sph_plan* P, StatePtrs<T, D> out, StatePtrs<T, D> base, doubl
     return SPH_OK;
 }
 
+// Puts a stage state w (original order) into slot 0 with neighbour lists for its sweeps.  The
+// first stage of a step (`first`) sorts and builds; with a skin, later stages keep the first
+// stage's particle order and lists (k_repack), the sweeps filtering them to r < H, which the
+// skin covers as long as no particle moved more than half of it since the build (checked).
+template <typename T, int D>
+sph_status stage_into_slot0(sph_plan* P, StatePtrs<T, D> w, bool first, hipStream_t st)
+{
+    if (first || !P->filter) {
+        RC_TRY((sort_into<T, D>(P, w, nullptr, 0, st)));
+        return build_lists<T, D>(P, 0, st);
+    }
+    if (P->N == 0) return SPH_OK;
+    const SlotLayout& L = P->slot[0];
+    ProfScope prof(P, st, SPH_KERN_SORT);
+    k_repack<T, D><<<grid_for(P->N, 256), 256, 0, st>>>(
+        P->N, wsp<int32_t>(P, L.orig), w, ws_state<T, D>(P, L.SA), wsp<vec4_t<T>>(P, L.jd0), wsp<vec4_t<T>>(P, L.jd1),
+        wsp<vec4_t<T>>(P, P->o_uref), wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc),
+        wsp<int32_t>(P, P->o_status));
+    LAUNCH_CHECK("repack");
+    return SPH_OK;
+}
+
 // Stage states and rates of one Runge-Kutta step from u (original order): u_i = u + dt
 // sum_{j<i} A_ij k_j (u_0 = u itself), k_i = f(u_i) = (v_i, a(u_i), drho/dt(u_i)), each rate
 // from a sort, a list build and a right-hand-side sweep of the stage state.  The x-rate of
@@ -705,8 +727,7 @@ sph_status rk_stages(sph_plan* P, StatePtrs<T, D> u, StatePtrs<T, D>* U, StatePt
             RC_TRY((lincomb<T, D>(P, U[i], u, 1.0, false, n, c, Ks, true, st)));
         }
         K[i] = rk_block<T, D>(P, P->o_rkK, i);
-        RC_TRY((sort_into<T, D>(P, U[i], nullptr, 0, st)));
-        RC_TRY((build_lists<T, D>(P, 0, st)));
+        RC_TRY((stage_into_slot0<T, D>(P, U[i], i == 0, st)));
         RC_TRY((sweep<T, D, kModeRhs>(P, 0, K[i].rho, K[i].v[0], nullptr, st)));
         for (int k = 0; k < 3; ++k) K[i].x[k] = U[i].v[k];
     }
@@ -753,8 +774,8 @@ sph_status rk_step_adjoint(sph_plan* P, StatePtrs<T, D> u, StatePtrs<T, D> cot, 
                 Ks[n++] = Ub[l];
             }
         RC_TRY((lincomb<T, D>(P, Ub[i], B0, P->rk_b[i], true, n, c, Ks, true, st)));
-        RC_TRY((sort_into<T, D>(P, U[i], nullptr, 0, st)));
-        RC_TRY((build_lists<T, D>(P, 0, st)));
+        // the stages' lists are those rk_stages left in slot 0 (the first stage's, with a skin)
+        RC_TRY((stage_into_slot0<T, D>(P, U[i], !P->filter, st)));
         RC_TRY((adjoint<T, D>(P, 0, Ub[i], st, true)));
     }
     double ones[kMaxStages] = {1.0, 1.0, 1.0, 1.0};
@@ -765,10 +786,9 @@ sph_status rk_step_adjoint(sph_plan* P, StatePtrs<T, D> u, StatePtrs<T, D> cot, 
 
 // Rates (., a, D) = f(w) into r (original order) from a sort, a list build and a sweep of w.
 template <typename T, int D>
-sph_status rates_at(sph_plan* P, StatePtrs<T, D> w, StatePtrs<T, D> r, hipStream_t st)
+sph_status rates_at(sph_plan* P, StatePtrs<T, D> w, StatePtrs<T, D> r, bool first, hipStream_t st)
 {
-    RC_TRY((sort_into<T, D>(P, w, nullptr, 0, st)));
-    RC_TRY((build_lists<T, D>(P, 0, st)));
+    RC_TRY((stage_into_slot0<T, D>(P, w, first, st)));
     return sweep<T, D, kModeRhs>(P, 0, r.rho, r.v[0], nullptr, st);
 }
 
@@ -793,12 +813,13 @@ sph_status symp_stages(sph_plan* P, StatePtrs<T, D> u, bool fresh, StatePtrs<T, 
     r1 = rk_block<T, D>(P, P->o_rkK, 0);
     r2 = rk_block<T, D>(P, P->o_rkK, 1);
     uh = rk_block<T, D>(P, P->o_rkU, 1);
-    if (fresh) RC_TRY((rates_at<T, D>(P, u, r1, st)));
+    if (fresh) RC_TRY((rates_at<T, D>(P, u, r1, true, st)));
     StatePtrs<T, D> k1 = r1;
     for (int k = 0; k < 3; ++k) k1.x[k] = u.v[k];  // the predictor's x-rate is v
     const double half = 0.5;
     RC_TRY((lincomb<T, D>(P, uh, u, 1.0, false, 1, &half, &k1, true, st)));
-    return rates_at<T, D>(P, uh, r2, st);
+    // with a fresh predictor the step's lists are u's, which the predictor state can keep
+    return rates_at<T, D>(P, uh, r2, !fresh, st);
 }
 
 // One step of u in place.  With re-use the corrector's rates are copied to block 0 for the
@@ -841,8 +862,7 @@ sph_status symp_step_adjoint(sph_plan* P, StatePtrs<T, D> u, StatePtrs<T, D> cot
     RC_TRY((lincomb<T, D>(P, b0, b0, 1.0, false, 1, &one, &ubh, false, st)));
     RC_TRY((lincomb<T, D>(P, ubh, ubh, 0.5, true, 0, nullptr, nullptr, false, st)));  // kb1 = h ubar_h
     if (fresh) {
-        RC_TRY((sort_into<T, D>(P, u, nullptr, 0, st)));
-        RC_TRY((build_lists<T, D>(P, 0, st)));
+        RC_TRY((stage_into_slot0<T, D>(P, u, !P->filter, st)));
         RC_TRY((adjoint<T, D>(P, 0, ubh, st, true)));
         return lincomb<T, D>(P, cot, b0, 1.0, false, 1, &one, &ubh, false, st);
     }

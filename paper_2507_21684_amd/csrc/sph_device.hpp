@@ -503,6 +503,57 @@ __global__ __launch_bounds__(256) void k_order_gather(int64_t N, const int32_t* 
     if (uref) uref[d] = a;  // the positions the lists were built from (list reuse)
 }
 
+// A state in original order gathered into the particle order of a slot that is already sorted
+// and has lists (a later stage of a multistage step, with the lists of the step's first stage):
+// the sorted state and the packed records as k_order_gather writes them, and the displacement
+// since the lists were built checked against half the skin.
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_repack(int64_t N, const int32_t* __restrict__ orig, StatePtrs<T, DIM> src,
+                                                StatePtrs<T, DIM> dst, vec4_t<T>* __restrict__ jd0,
+                                                vec4_t<T>* __restrict__ jd1, const vec4_t<T>* __restrict__ uref,
+                                                const int32_t* __restrict__ psim,
+                                                const SimConst<T>* __restrict__ sims, int32_t* __restrict__ status)
+{
+    int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= N) return;
+    const int s = psim[d];
+    const SimConst<T>& S = sims[s];
+    const int p = orig[d];
+    T x[3] = {0, 0, 0}, v[3] = {0, 0, 0}, u[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        x[k] = src.x[k][p];
+        v[k] = src.v[k][p];
+        dst.x[k][d] = x[k];
+        dst.v[k][d] = v[k];
+        u[k] = wrap_pos(isfinite(x[k]) ? x[k] : T(0), S.L, S.invL);
+    }
+    const T rho = src.rho[p];
+    dst.rho[d] = rho;
+    const T V = S.m / rho;
+    const T pV = tait(S, rho) * V;
+    vec4_t<T> a, b;
+    if (DIM == 3) {
+        a.x = u[0]; a.y = u[1]; a.z = u[2]; a.w = V;
+        b.x = v[0]; b.y = v[1]; b.z = v[2]; b.w = pV;
+    } else {
+        a.x = u[0]; a.y = u[1]; a.z = V; a.w = pV;
+        b.x = v[0]; b.y = v[1]; b.z = rho; b.w = T(0);
+    }
+    jd0[d] = a;
+    jd1[d] = b;
+    const vec4_t<T> ref = uref[d];
+    const T rr[3] = {ref.x, ref.y, ref.z};
+    T d2 = T(0);
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        T dk = u[k] - rr[k];
+        dk -= S.L * rint(dk * S.invL);
+        d2 += dk * dk;
+    }
+    if (!(d2 <= S.disp2)) atomicOr(&status[s], kFlagSkin);
+}
+
 template <typename T, int DIM>
 __device__ __forceinline__ void unpack_u(const vec4_t<T>& a, T* u)
 {

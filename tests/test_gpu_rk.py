@@ -105,3 +105,42 @@ def test_rk_batch_invariance():
         for k in range(3):
             np.testing.assert_array_equal(out[k][..., off:off + s.n], ref[k])
         off += s.n
+
+
+@pytest.mark.parametrize("scheme,dtype,dim,side", [("rk4", "f64", 2, 24), ("midpoint", "f32", 2, 40),
+                                                   ("rk4", "f32", 3, 14)])
+def test_rk_stage_list_reuse_parity(orc, scheme, dtype, dim, side):
+    """With a skin, later stages keep the first stage's lists (filtered to r < H): same results."""
+    spec = SimSpec(dim, side)
+    x, v, rho = _state(spec, 3, dtype)
+    plan = _plan([spec], dtype, scheme, skin=0.1)
+    g = _gpu([x, v, rho], dtype)
+    plan.step(*g, 3)
+    assert np.all(plan.poll() == 0)
+    xr, vr, rr = orc.step_rk(orc.Params(**spec.params()), x, v, rho, 3, scheme)
+    gx, gv, gr = [t.cpu().numpy().astype(np.float64) for t in g]
+    tol_r, tol_v, tol_x = (1e-10, 1e-9, 1e-9) if dtype == "f64" else (1e-5, 1e-4, 1e-4)
+    assert np.abs(gr / rr - 1).max() <= tol_r
+    err = np.sqrt(((gv - vr) ** 2).sum(axis=0)).max() / np.sqrt((vr ** 2).sum(axis=0)).max()
+    assert err <= tol_v
+    assert np.abs(gx - xr).max() <= tol_x * spec.dx
+    # and the step VJP on the reused lists
+    rng = np.random.default_rng(4)
+    c = [rng.normal(size=a.shape).astype(a.dtype) for a in (x, v, rho)]
+    cg = _gpu(c, dtype)
+    plan.step_adjoint(*_gpu([x, v, rho], dtype), *cg)
+    ref = orc.step_rk_adjoint(orc.Params(**spec.params()), x, v, rho, *c, scheme)
+    tol = 1e-9 if dtype == "f64" else 1e-3
+    for got, want in zip(cg, ref):
+        got = got.cpu().numpy().astype(np.float64)
+        assert np.abs(got - want).max() <= tol * np.abs(want).max()
+
+
+def test_rk_stage_reuse_flags_a_skin_too_small():
+    spec = SimSpec(2, 24)
+    x, v, rho = _state(spec, 5, "f32")
+    plan = _plan([spec], "f32", "rk4", skin=0.002)
+    g = _gpu([x, v, rho], "f32")
+    plan.step(*g, 2)
+    from paper_2507_21684_amd.lib import FLAG_SKIN
+    assert np.all(plan.poll() & FLAG_SKIN)

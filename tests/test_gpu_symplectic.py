@@ -135,3 +135,29 @@ def test_symplectic_batch_invariance_and_graphs():
             for k in range(3):
                 np.testing.assert_array_equal(out[k][..., off:off + s.n], ref[k])
             off += s.n
+
+
+@pytest.mark.parametrize("reuse,dtype", [(False, "f64"), (True, "f32")])
+def test_symplectic_with_a_skin(orc, reuse, dtype):
+    """With a skin the predictor state keeps the step's lists when the step evaluated f(u)."""
+    from paper_2507_21684_amd.rollout import rollout
+    spec = SimSpec(2, 24)
+    x, v, rho = _state(spec, 6, dtype)
+    plan = _plan([spec], dtype, reuse, tape_depth=3, skin=0.1)
+    gx0, gv0, gr0 = _gpu([x, v, rho], dtype)
+    for t in (gx0, gv0, gr0):
+        t.requires_grad_(True)
+    xT, vT, rT = rollout(plan, gx0, gv0, gr0, 6, 3)
+    (vT.double() ** 2).sum().backward()
+    assert np.all(plan.poll() == 0)
+    p = orc.Params(**spec.params())
+    xr, vr, rr, _ = orc.step_symplectic(p, x, v, rho, 6, reuse, 3)
+    tol_v = 1e-9 if dtype == "f64" else 1e-4
+    vg = vT.detach().cpu().numpy().astype(np.float64)
+    assert np.sqrt(((vg - vr) ** 2).sum(axis=0)).max() <= tol_v * np.sqrt((vr ** 2).sum(axis=0)).max()
+    cx, cv, cr = orc.rollout_symplectic_adjoint(p, x, v, rho, 6, np.zeros(x.shape), 2.0 * vr, np.zeros(rho.shape),
+                                                reuse, 3)
+    tol = 1e-9 if dtype == "f64" else 1e-3
+    for got, want in ((gx0.grad, cx), (gv0.grad, cv), (gr0.grad, cr)):
+        got = got.cpu().numpy().astype(np.float64)
+        assert np.abs(got - want).max() <= tol * np.abs(want).max()
