@@ -230,6 +230,58 @@ def test_full_size_rhs_sampled(orc, dim, side):
     assert np.all(plan.poll() == 0)
 
 
+# The bench's tuned launch configuration of the two full-size workloads: list skin, rebuild
+# interval and lanes per particle (forward, adjoint).
+BENCH_CONFIGS = [(2, 256, 0.26, 8, (4, 4)), (3, 64, 0.13, 4, (8, 8))]
+
+
+@pytest.mark.parametrize("dim,side,skin,R,lanes", BENCH_CONFIGS)
+def test_full_size_bench_config_sampled(orc, dim, side, skin, R, lanes):
+    """Full sizes in the bench's launch configuration: a step on reused, filtered lists and a step
+    adjoint, checked on sampled particles against the oracle's brute-force sums."""
+    spec = SimSpec(dim, side)
+    x, v, rho = [a.astype(np.float32) for a in make_state(spec, 0)]     # the bench's inputs
+    plan = _plan([spec], "f32", skin=skin, rebuild_every=R, tape_depth=8)
+    plan.set_tuning(*lanes)
+    # one call of R - 1 steps builds lists at its first step and reuses them after: its last step
+    # (from the state after R - 2 steps, reproduced bitwise by a call of R - 2 steps) is a
+    # reused-list step
+    a = _to_gpu([x, v, rho], "f32")
+    plan.step(*a, R - 2)
+    b = _to_gpu([x, v, rho], "f32")
+    plan.step(*b, R - 1)
+    assert np.all(plan.poll() == 0)
+    s0 = [t.cpu().numpy().astype(np.float64) for t in a]
+    s1 = [t.cpu().numpy().astype(np.float64) for t in b]
+    sample = np.random.default_rng(5).choice(spec.n, size=64, replace=False)
+    p = _oparams(orc, spec)
+    dt = p.dt
+    d_r, a_r, _ = orc.rhs_sample(p, *s0, sample)
+    v_ref = s0[1][:, sample] + dt * a_r
+    r_ref = s0[2][sample] + dt * d_r
+    x_ref = s0[0][:, sample] + dt * v_ref
+    eps = float(np.finfo(np.float32).eps)
+    # bound: the rates' tolerance over one step plus FP32 rounding of the stored state
+    assert np.abs(s1[1][:, sample] - v_ref).max() <= dt * 1e-4 * np.abs(a_r).max() + 4 * eps * np.abs(v_ref).max()
+    assert np.abs(s1[2][sample] - r_ref).max() <= dt * 1e-4 * np.abs(d_r).max() + 4 * eps * np.abs(r_ref).max()
+    assert np.abs(s1[0][:, sample] - x_ref).max() <= dt * dt * 1e-4 * np.abs(a_r).max() + 4 * eps * np.abs(x_ref).max()
+    # the step adjoint from the same state: its pair-sweep part against the oracle's sampled sums
+    rng = np.random.default_rng(6)
+    cx, cv, cr = (rng.normal(size=x.shape).astype(np.float32), rng.normal(size=v.shape).astype(np.float32),
+                  rng.normal(size=rho.shape).astype(np.float32))
+    c = _to_gpu([cx, cv, cr], "f32")
+    plan.step_adjoint(*_to_gpu([t.astype(np.float32) for t in s0], "f32"), *c)
+    vt = cv.astype(np.float64) + dt * cx.astype(np.float64)
+    gx_r, gv_r, gr_r = orc.adjoint_sweep_sample(p, *s0, dt * vt, dt * cr.astype(np.float64), sample)
+    got = [t.cpu().numpy().astype(np.float64) for t in c]
+    sx = got[0][:, sample] - cx.astype(np.float64)[:, sample]
+    sv = got[1][:, sample] - vt[:, sample]
+    sr = got[2][sample] - cr.astype(np.float64)[sample]
+    for g_, r_ in ((sx, gx_r), (sv, gv_r), (sr, gr_r)):
+        assert np.abs(g_ - r_).max() <= 1e-3 * np.abs(r_).max()
+    assert np.all(plan.poll() == 0)
+
+
 @pytest.mark.parametrize("dim,side", [(2, 40), (3, 14)])
 def test_lanes_per_particle_bitwise(dim, side):
     """The sweeps give bitwise identical results for 2, 4 and 8 lanes per particle."""
