@@ -215,8 +215,9 @@ def roofline(prof, dom, wl, per_state, reps, dim, n_particles, lanes=(4, 4)):
     achieved = flops_per_launch / mean_launch_s / 1e12
     peak = PEAK_TFLOPS[wl.dtype]
     tdt = "float" if wl.dtype == "f32" else "double"
-    sym = ("sph::k_sweep<%s,%d,0,%d>" % (tdt, dim, lanes[0]) if dom == "sweep"
-           else "sph::k_adj_sweep<%s,%d,%d>" % (tdt, dim, lanes[1]))
+    # the kernels of the plain delta-diffusion (the last template argument is the renormalised one)
+    sym = ("sph::k_sweep<%s,%d,0,%d,false>" % (tdt, dim, lanes[0]) if dom == "sweep"
+           else "sph::k_adj_sweep<%s,%d,%d,false>" % (tdt, dim, lanes[1]))
     traffic = measured_traffic(wl.name, sym)
     out = {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
            "frac": round(achieved / peak, 4), "traffic": traffic, "mean_launch_us": round(mean_launch_s * 1e6, 2),
