@@ -114,6 +114,10 @@ def lib():
         L.orc_rollout_symplectic_adjoint.restype = ctypes.c_int
         L.orc_rollout_symplectic_adjoint.argtypes = [_P, ctypes.c_int64, _D, _D, _D, ctypes.c_int32, ctypes.c_int32,
                                                      ctypes.c_int32, _D, _D, _D]
+        L.orc_shift.restype = ctypes.c_int
+        L.orc_shift.argtypes = [_P, ctypes.c_int64, _D, _D, ctypes.c_double, _D]
+        L.orc_shift_vjp.restype = ctypes.c_int
+        L.orc_shift_vjp.argtypes = [_P, ctypes.c_int64, _D, _D, ctypes.c_double, _D, _D, _D]
         L.orc_renorm_gradient.restype = ctypes.c_int
         L.orc_renorm_gradient.argtypes = [_P, ctypes.c_int64, _D, _D, _D, _D]
         L.orc_density_adjoint.restype = ctypes.c_int
@@ -367,6 +371,28 @@ def rollout_symplectic_adjoint(p: Params, x, v, rho, nsteps: int, xb, vb, rb, re
     if rc != 0:
         raise ValueError("oracle rollout_symplectic_adjoint rejected its input")
     return xb, vb, rb
+
+
+def shift(p: Params, x, rho, beta: float):
+    """Particle shift dr = -beta H^2 sum_j [1 + 0.2 (W_ij / W(dx))^4] V_j grad_i W_ij (dim x n)."""
+    x, rho = _f64(x), _f64(rho)
+    n = rho.shape[0]
+    dr = np.zeros((p.dim, n))
+    pc = p.c()
+    if lib().orc_shift(ctypes.byref(pc), n, _d(x), _d(rho), float(beta), _d(dr)) != 0:
+        raise ValueError("oracle shift rejected its input")
+    return dr
+
+
+def shift_vjp(p: Params, x, rho, beta: float, xb):
+    """(J_x^T xb, J_rho^T xb) of the shift, for cotangents xb of the shifted positions."""
+    x, rho, xb = _f64(x), _f64(rho), _f64(xb)
+    n = rho.shape[0]
+    gx, gr = np.zeros((p.dim, n)), np.zeros(n)
+    pc = p.c()
+    if lib().orc_shift_vjp(ctypes.byref(pc), n, _d(x), _d(rho), float(beta), _d(xb), _d(gx), _d(gr)) != 0:
+        raise ValueError("oracle shift_vjp rejected its input")
+    return gx, gr
 
 
 def renorm_gradient(p: Params, x, rho, A):

@@ -44,6 +44,8 @@
  *   - The vector-Jacobian product of the summation density alone (the
  *     backward benchmark of Sec. 4.1: summation density after a step,
  *     gradient with respect to the initial positions).
+ *   - Explicit particle shifting as a post-processing step (Sec. 3.4,
+ *     App. C; the delta-plus form) and its vector-Jacobian product.
  *   - DualSPHysics' symplectic Euler (Sec. 3.4, App. C), optionally with
  *     the last substep's rates re-used as the next step's first substep,
  *     and its vector-Jacobian products for one step and for a rollout.
@@ -1561,6 +1563,115 @@ int orc_rollout_symplectic_adjoint(const orc_params* p, int64_t n, const double*
     free(r2);
     free(cb);
     free(cb_prev);
+    return 0;
+}
+
+/* ---------------------------------------------------------------- particle shifting
+ *
+ * Explicit particle shifting, applied as a post-processing step to a state
+ * (Sec. 3.4 and App. C place it at the end of a time step; the paper cites the
+ * delta-plus scheme of Sun et al. without printing it).  The published form:
+ *   dr_i = -beta H^2 sum_j [1 + R (W_ij / W(dx))^4] V_j grad_i W_ij,
+ * R = 0.2, dx = (m / rho0)^(1/d) the initial spacing, V_j = m / rho_j, and
+ * beta (the scheme's CFL Ma) a parameter; x <- x + dr, velocities and
+ * densities unchanged.  With V_j = V the shift is a descent step on
+ *   E = sum_i sum_j V [W_ij + R W_ij^5 / (5 W(dx)^4)].
+ */
+#define ORC_SHIFT_R 0.2
+
+static double shift_w0(const orc_params* p)
+{
+    double dx = pow(p->m / p->rho0, 1.0 / p->dim);
+    double e[3] = {dx, 0.0, 0.0};
+    return orc_w(p->dim, p->H, e);
+}
+
+/* dr (dim*n) for the state (x, rho). */
+int orc_shift(const orc_params* p, int64_t n, const double* x, const double* rho, double beta, double* dr)
+{
+    if (!valid_params(p) || n < 0) return -1;
+    int dim = p->dim;
+    double invL = 1.0 / p->L, w0 = shift_w0(p), c = -beta * p->H * p->H;
+    double* u = (double*)malloc(sizeof(double) * (size_t)dim * (size_t)(n > 0 ? n : 1));
+    wrap_all(p, n, x, u);
+    nblist nb;
+    build_lists(dim, n, x, p->L, p->H, 0, 0, &nb);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        double ui[3] = {0, 0, 0}, s[3] = {0, 0, 0};
+        for (int k = 0; k < dim; ++k) ui[k] = u[k * n + i];
+        for (int64_t q = nb.off[i]; q < nb.off[i + 1]; ++q) {
+            int64_t j = nb.idx[q];
+            if (j == i) continue;
+            double uj[3] = {0, 0, 0}, e[3] = {0, 0, 0}, w[3] = {0, 0, 0};
+            for (int k = 0; k < dim; ++k) uj[k] = u[k * n + j];
+            minimg(dim, ui, uj, p->L, invL, e);
+            orc_gradw(dim, p->H, e, w);
+            double rW = orc_w(dim, p->H, e) / w0;
+            double phi = 1.0 + ORC_SHIFT_R * rW * rW * rW * rW;
+            double Vj = p->m / rho[j];
+            for (int k = 0; k < dim; ++k) s[k] += phi * Vj * w[k];
+        }
+        for (int k = 0; k < dim; ++k) dr[k * n + i] = c * s[k];
+    }
+    nblist_free(&nb);
+    free(u);
+    return 0;
+}
+
+/* Vector-Jacobian product of x' = x + dr(x, rho) for cotangents xb of x':
+ * gx = J_x^T xb and gr = J_rho^T xb are written (the identity part, xb itself,
+ * is the caller's).  Scatter form over the lists: with h(r) = phi(r) g(r),
+ * grad_i W_ij = g e (e = x_i - x_j), dr_i += c V_j h e, c = -beta H^2:
+ *   d(h e)/de = h I + (h'(r) / r) e e^T,
+ *   x_i += c V_j D^T xb_i,  x_j -= c V_j D^T xb_i,
+ *   rho_j += -(V_j / rho_j) c h (e . xb_i). */
+int orc_shift_vjp(const orc_params* p, int64_t n, const double* x, const double* rho, double beta,
+                  const double* xb, double* gx, double* gr)
+{
+    if (!valid_params(p) || n < 0) return -1;
+    int dim = p->dim;
+    double invL = 1.0 / p->L, w0 = shift_w0(p), c = -beta * p->H * p->H;
+    double* u = (double*)malloc(sizeof(double) * (size_t)dim * (size_t)(n > 0 ? n : 1));
+    wrap_all(p, n, x, u);
+    nblist nb;
+    build_lists(dim, n, x, p->L, p->H, 0, 0, &nb);
+    for (int64_t e0 = 0; e0 < (int64_t)dim * n; ++e0) gx[e0] = 0.0;
+    for (int64_t i = 0; i < n; ++i) gr[i] = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double ui[3] = {0, 0, 0}, xbi[3] = {0, 0, 0};
+        for (int k = 0; k < dim; ++k) {
+            ui[k] = u[k * n + i];
+            xbi[k] = xb[k * n + i];
+        }
+        for (int64_t q = nb.off[i]; q < nb.off[i + 1]; ++q) {
+            int64_t j = nb.idx[q];
+            if (j == i) continue;
+            double uj[3] = {0, 0, 0}, e[3] = {0, 0, 0}, w[3] = {0, 0, 0}, Hs[9];
+            for (int k = 0; k < dim; ++k) uj[k] = u[k * n + j];
+            minimg(dim, ui, uj, p->L, invL, e);
+            orc_gradw(dim, p->H, e, w);
+            orc_hessw(dim, p->H, e, Hs);
+            double Wr = orc_w(dim, p->H, e), rW = Wr / w0;
+            double phi = 1.0 + ORC_SHIFT_R * rW * rW * rW * rW;
+            /* d phi / de = 4 R (W/w0)^3 grad W / w0 */
+            double dphi = 4.0 * ORC_SHIFT_R * rW * rW * rW / w0;
+            double Vj = p->m / rho[j];
+            /* the shift term t = phi(e) w(e); dt/de = phi Hess + w (dphi w)^T */
+            double wx = 0.0;
+            for (int k = 0; k < dim; ++k) wx += w[k] * xbi[k];
+            for (int a = 0; a < dim; ++a) {
+                double g = 0.0;
+                for (int b = 0; b < dim; ++b) g += phi * Hs[b * dim + a] * xbi[b];
+                g += dphi * w[a] * wx;
+                gx[a * n + i] += c * Vj * g;
+                gx[a * n + j] -= c * Vj * g;
+            }
+            gr[j] += -(Vj / rho[j]) * c * phi * wx;
+        }
+    }
+    nblist_free(&nb);
+    free(u);
     return 0;
 }
 
