@@ -188,6 +188,22 @@ sph_status sph_set_symplectic(sph_plan* plan, int32_t reuse_last_substep);
  * make it before sph_bind (CAPACITY afterwards).  Host-side setting. */
 sph_status sph_set_diffusion(sph_plan* plan, int32_t renormalised);
 
+/* Explicit particle shifting, the post-processing step Sec. 3.4 and App. C
+ * apply at the end of a time step (the delta-plus form the paper cites):
+ *     dr_i = -beta H^2 sum_j [1 + 0.2 (W_ij / W(dx))^4] V_j grad_i W_ij,
+ * V_j = m / rho_j, dx = (m / rho0)^(1/dim) the initial spacing; x <- x + dr in
+ * place (device state, original order; velocities and densities unchanged).
+ * beta is the scheme's CFL Ma (dimensionless).  Sorts the state and builds its
+ * lists (the plan's skin and lanes apply).  Compose it with sph_step calls of
+ * one step to shift after every step.  INVALID_ARG for a non-finite beta. */
+sph_status sph_shift(sph_plan* plan, sph_state* state, double beta, void* stream);
+
+/* Vector-Jacobian product of sph_shift at `state` (the state before the shift):
+ * cot holds the cotangents of the shifted state on entry and those of `state`
+ * on exit (positions gain J_x^T xbar, densities J_rho^T xbar; velocities are
+ * unchanged).  The state is not modified. */
+sph_status sph_shift_adjoint(sph_plan* plan, const sph_state* state, sph_state* cot, double beta, void* stream);
+
 /* Neighbour-list reuse (Verlet lists; the paper keeps one list for short rollouts,
  * Sec. 4.1).  With rebuild_every = R > 1 (needs a skin in every simulation's
  * parameters), a step sorts and rebuilds its lists only when its index within the

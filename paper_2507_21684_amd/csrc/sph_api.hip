@@ -239,6 +239,14 @@ void fill_simconst(const sph_plan* P, std::vector<unsigned char>& out)
             const double half = 0.5 * q.skin * q.support;
             c.disp2 = (T)(half * half);
         }
+        {
+            // 1 / W(dx) at the initial spacing dx = (m / rho0)^(1/d), for particle shifting
+            const double dx = std::pow(q.mass / q.rho0, 1.0 / d), qq = dx / q.support;
+            const double t = 1.0 - qq;
+            const double w = qq < 1.0 ? t * t * t * t * t * t * (1.0 + 6.0 * qq + (35.0 / 3.0) * qq * qq) : 0.0;
+            const double W = cd / std::pow(q.support, d) * w;
+            c.invW0 = W > 0.0 ? (T)(1.0 / W) : T(0);
+        }
         c.invH = (T)(1.0 / q.support);
         c.cinv = (T)((double)h.nc / q.box);
         c.m = (T)q.mass;
@@ -592,6 +600,65 @@ sph_status check_bound(const sph_plan* P)
 #define DISPATCH(P, FN, ...)                                                       \
     ((P)->dtype == SPH_F32 ? ((P)->dim == 2 ? FN<float, 2>(__VA_ARGS__) : FN<float, 3>(__VA_ARGS__)) \
                            : ((P)->dim == 2 ? FN<double, 2>(__VA_ARGS__) : FN<double, 3>(__VA_ARGS__)))
+
+// Particle shifting of a state in place, and its vector-Jacobian product, each on the state's
+// own sort and lists.
+template <typename T, int D, int LPP>
+void launch_shift(sph_plan* P, StatePtrs<T, D> st_user, T beta, hipStream_t st)
+{
+    const SlotLayout& L = P->slot[0];
+    k_shift<T, D, LPP><<<grid_for(P->N * LPP, 256), 256, 0, st>>>(
+        P->N, P->width, wsp<int32_t>(P, L.nbr), wsp<int32_t>(P, L.cnt), wsp<vec4_t<T>>(P, L.jd0),
+        wsp<int32_t>(P, L.orig), wsp<int32_t>(P, P->o_psim), wsp<SimConst<T>>(P, P->o_simc), P->filter ? 1 : 0, beta,
+        st_user);
+}
+
+template <typename T, int D, int LPP>
+void launch_shift_adj(sph_plan* P, StatePtrs<T, D> cot, T beta, hipStream_t st)
+{
+    const SlotLayout& L = P->slot[0];
+    k_shift_adj<T, D, LPP><<<grid_for(P->N * LPP, 256), 256, 0, st>>>(
+        P->N, P->width, wsp<int32_t>(P, L.nbr), wsp<int32_t>(P, L.cnt), wsp<vec4_t<T>>(P, L.jd0),
+        wsp<vec4_t<T>>(P, P->o_jdA), ws_state<T, D>(P, L.SA).rho, wsp<int32_t>(P, L.orig), wsp<int32_t>(P, P->o_psim),
+        wsp<SimConst<T>>(P, P->o_simc), P->filter ? 1 : 0, beta, cot);
+}
+
+template <typename T, int D>
+sph_status do_shift(sph_plan* P, sph_state* s, double beta, hipStream_t st)
+{
+    if (P->N == 0) return SPH_OK;
+    StatePtrs<T, D> u = user_state<T, D>(s);
+    RC_TRY((sort_into<T, D>(P, u, nullptr, 0, st)));
+    RC_TRY((build_lists<T, D>(P, 0, st)));
+    ProfScope prof(P, st, SPH_KERN_OTHER);
+    switch (P->lpp_fwd) {
+    case 2: launch_shift<T, D, 2>(P, u, (T)beta, st); break;
+    case 8: launch_shift<T, D, 8>(P, u, (T)beta, st); break;
+    default: launch_shift<T, D, 4>(P, u, (T)beta, st); break;
+    }
+    LAUNCH_CHECK("shift");
+    return SPH_OK;
+}
+
+template <typename T, int D>
+sph_status do_shift_adjoint(sph_plan* P, const sph_state* s, sph_state* cot, double beta, hipStream_t st)
+{
+    if (P->N == 0) return SPH_OK;
+    RC_TRY((sort_into<T, D>(P, user_state<T, D>(s), nullptr, 0, st)));
+    RC_TRY((build_lists<T, D>(P, 0, st)));
+    StatePtrs<T, D> c = user_state<T, D>(cot);
+    ProfScope prof(P, st, SPH_KERN_OTHER);
+    k_pack_xbar<T, D><<<grid_for(P->N, 256), 256, 0, st>>>(P->N, c, wsp<int32_t>(P, P->slot[0].orig),
+                                                           wsp<vec4_t<T>>(P, P->o_jdA));
+    LAUNCH_CHECK("pack_xbar");
+    switch (P->lpp_adj) {
+    case 2: launch_shift_adj<T, D, 2>(P, c, (T)beta, st); break;
+    case 8: launch_shift_adj<T, D, 8>(P, c, (T)beta, st); break;
+    default: launch_shift_adj<T, D, 4>(P, c, (T)beta, st); break;
+    }
+    LAUNCH_CHECK("shift_adj");
+    return SPH_OK;
+}
 
 template <typename T, int D>
 sph_status do_build_cells(sph_plan* P, const sph_state* s, hipStream_t st)
@@ -1580,6 +1647,23 @@ sph_status sph_density_adjoint(sph_plan* P, const sph_state* s, const void* rho_
                            : do_density_adjoint<float, 3>(P, s, (const float*)rho_sum_bar, (float*)x_bar, st);
     return P->dim == 2 ? do_density_adjoint<double, 2>(P, s, (const double*)rho_sum_bar, (double*)x_bar, st)
                        : do_density_adjoint<double, 3>(P, s, (const double*)rho_sum_bar, (double*)x_bar, st);
+}
+
+sph_status sph_shift(sph_plan* P, sph_state* s, double beta, void* stream)
+{
+    RC_TRY(check_bound(P));
+    RC_TRY(check_state(P, s, "state"));
+    if (!std::isfinite(beta)) return fail(SPH_ERR_INVALID_ARG, "beta must be finite");
+    return DISPATCH(P, do_shift, P, s, beta, (hipStream_t)stream);
+}
+
+sph_status sph_shift_adjoint(sph_plan* P, const sph_state* s, sph_state* cot, double beta, void* stream)
+{
+    RC_TRY(check_bound(P));
+    RC_TRY(check_state(P, s, "state"));
+    RC_TRY(check_state(P, cot, "cotangent"));
+    if (!std::isfinite(beta)) return fail(SPH_ERR_INVALID_ARG, "beta must be finite");
+    return DISPATCH(P, do_shift_adjoint, P, s, cot, beta, (hipStream_t)stream);
 }
 
 sph_status sph_rollout_backward(sph_plan* P, const sph_state* ckpt, int32_t nsteps, int32_t ckpt_every,

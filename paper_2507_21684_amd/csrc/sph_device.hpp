@@ -44,6 +44,7 @@ struct SimConst {
     T Bt;       // rho0 c0^2 / 7
     T HL2;      // (H (1 + skin))^2: list radius squared (= H2 without a skin)
     T disp2;    // (skin H / 2)^2: largest squared displacement a reused list allows
+    T invW0;    // 1 / W(dx), dx = (m / rho0)^(1/dim) the initial spacing (particle shifting)
     int64_t p0, n;      // packed particle range
     int32_t cell0;      // first global cell slot
     int32_t blk0;       // first global cell block
@@ -1942,6 +1943,190 @@ __global__ __launch_bounds__(256) void k_renorm_adj(int64_t N, int32_t width, co
 #pragma unroll
     for (int d = 0; d < DIM; ++d) cot.x[d][o] += gx[d];
     cot.rho[o] += gr;
+}
+
+// ---------------------------------------------------------------- particle shifting
+//
+// dr_i = -beta H^2 sum_j phi_ij V_j grad_i W_ij, phi = 1 + R (W_ij / W(dx))^4, R = 0.2 (the
+// delta-plus form; a post-processing step on a state, x <- x + dr).  Same list traversal and
+// partial sums as the sweeps; x is updated in original order.
+constexpr double kShiftR = 0.2;
+
+template <typename T, int DIM, int LPP>
+__global__ __launch_bounds__(256) void k_shift(int64_t N, int32_t width, const int32_t* __restrict__ nbr,
+                                               const int32_t* __restrict__ nbr_count,
+                                               const vec4_t<T>* __restrict__ jd0, const int32_t* __restrict__ orig,
+                                               const int32_t* __restrict__ psim,
+                                               const SimConst<T>* __restrict__ sims, int filter, T beta,
+                                               StatePtrs<T, DIM> state)
+{
+    constexpr int NQ = kLeaves / LPP;
+    constexpr int U = kPairsInFlight;
+    const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int64_t i = t / LPP;
+    const int r = (int)(t - i * LPP);
+    if (i >= N) return;
+    const SimConst<T>& S = sims[psim[i]];
+    const PairConst<T> c = pair_const(S);
+    T ui[3] = {0, 0, 0};
+    unpack_u<T, DIM>(jd0[i], ui);
+    int n = nbr_count[i];
+    n = n < width ? n : width;
+    const int mcount = (n - r + LPP - 1) / LPP;
+    const int32_t* row = nbr + i * (int64_t)width;
+    T acc[NQ][3];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q][0] = acc[q][1] = acc[q][2] = T(0);
+    int jn[U];
+    load_entries<LPP, U>(row, r, 0, mcount, (int)i, jn);
+    for (int m0 = 0; m0 < mcount; m0 += U) {
+        vec4_t<T> a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) a[u] = ldo(jd0, (uint32_t)jn[u]);
+        load_entries<LPP, U>(row, r, m0 + U, mcount, (int)i, jn);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (m0 + u >= mcount) continue;
+            T d[3] = {0, 0, 0};
+            const T r2 = r2_exact<T, DIM>(ui, a[u], c.L, c.invL, d);
+            if (filter && !(r2 < c.H2)) continue;
+            const T q = fast_sqrt(r2) * c.invH;
+            const T tt = T(1) - q;
+            const T t2 = tt * tt;
+            const T t4 = t2 * t2;
+            const T gF = c.kG * (T(-56.0 / 3.0) * t4 * tt * (T(1) + T(5) * q));
+            const T wr = S.kW * t4 * t2 * (T(1) + q * (T(6) + q * T(35.0 / 3.0))) * S.invW0;   // W / W(dx)
+            const T w2 = wr * wr;
+            const T phi = T(1) + T(kShiftR) * w2 * w2;
+            const T f = phi * ((DIM == 3) ? a[u].w : a[u].z) * gF;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) acc[u % NQ][k] += f * d[k];
+        }
+    }
+    T sum[3] = {0, 0, 0}, tmp[NQ];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) tmp[q] = acc[q][k];
+        sum[k] = combine_leaves<LPP>(tmp);
+    }
+    if (r != 0) return;
+    const int o = orig[i];
+    const T cs = -beta * S.H2;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) state.x[k][o] += cs * sum[k];
+}
+
+// The position cotangents in sorted order, one record per particle, for k_shift_adj.
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_pack_xbar(int64_t N, StatePtrs<T, DIM> cot, const int32_t* __restrict__ orig,
+                                                   vec4_t<T>* __restrict__ xs)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const int o = orig[k];
+    vec4_t<T> a;
+    a.x = cot.x[0][o];
+    a.y = cot.x[1][o];
+    a.z = (DIM == 3) ? cot.x[2][o] : T(0);
+    a.w = T(0);
+    xs[k] = a;
+}
+
+// Vector-Jacobian product of the shift for cotangents xb of the shifted positions (xs: xb in
+// sorted order, one record per particle).  With D(e) = phi Jg + dphi (gF e)(gF e)^T the
+// derivative of phi(e) grad W(e), dphi = 4 R (W / W(dx))^3 / W(dx), c = -beta H^2:
+//   xbar_k += c sum_j D(e_kj) (V_j xb_k - V_k xb_j)
+//   rbar_k += (V_k / rho_k) c sum_j phi gF (e_kj . xb_j)
+// added to the cotangents (original order); velocities do not enter.
+template <typename T, int DIM, int LPP>
+__global__ __launch_bounds__(256) void k_shift_adj(int64_t N, int32_t width, const int32_t* __restrict__ nbr,
+                                                   const int32_t* __restrict__ nbr_count,
+                                                   const vec4_t<T>* __restrict__ jd0,
+                                                   const vec4_t<T>* __restrict__ xs, const T* __restrict__ rho_s,
+                                                   const int32_t* __restrict__ orig, const int32_t* __restrict__ psim,
+                                                   const SimConst<T>* __restrict__ sims, int filter, T beta,
+                                                   StatePtrs<T, DIM> cot)
+{
+    constexpr int NQ = kLeaves / LPP;
+    constexpr int U = kPairsInFlight;
+    const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    const int64_t k = t / LPP;
+    const int r = (int)(t - k * LPP);
+    if (k >= N) return;
+    const SimConst<T>& S = sims[psim[k]];
+    const PairConst<T> c = pair_const(S);
+    const vec4_t<T> a0 = jd0[k];
+    T uk[3] = {0, 0, 0};
+    unpack_u<T, DIM>(a0, uk);
+    const T Vk = (DIM == 3) ? a0.w : a0.z;
+    const vec4_t<T> xk4 = xs[k];
+    const T xbk[3] = {xk4.x, xk4.y, xk4.z};
+    int n = nbr_count[k];
+    n = n < width ? n : width;
+    const int mcount = (n - r + LPP - 1) / LPP;
+    const int32_t* row = nbr + k * (int64_t)width;
+    T ax[NQ][3], ar[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) ax[q][0] = ax[q][1] = ax[q][2] = ar[q] = T(0);
+    int jn[U];
+    load_entries<LPP, U>(row, r, 0, mcount, (int)k, jn);
+    for (int m0 = 0; m0 < mcount; m0 += U) {
+        vec4_t<T> a[U], b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            a[u] = ldo(jd0, (uint32_t)jn[u]);
+            b[u] = ldo(xs, (uint32_t)jn[u]);
+        }
+        load_entries<LPP, U>(row, r, m0 + U, mcount, (int)k, jn);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (m0 + u >= mcount) continue;
+            T e[3] = {0, 0, 0};
+            const T r2 = r2_exact<T, DIM>(uk, a[u], c.L, c.invL, e);
+            if (filter && !(r2 < c.H2)) continue;
+            const T q = fast_sqrt(r2) * c.invH;
+            const T tt = T(1) - q;
+            const T t2 = tt * tt;
+            const T t4 = t2 * t2;
+            const T gF = c.kG * (T(-56.0 / 3.0) * t4 * tt * (T(1) + T(5) * q));
+            const T hF = c.kH * t4;
+            const T wr = S.kW * t4 * t2 * (T(1) + q * (T(6) + q * T(35.0 / 3.0))) * S.invW0;
+            const T w2 = wr * wr;
+            const T phi = T(1) + T(kShiftR) * w2 * w2;
+            const T dphi = T(4.0 * kShiftR) * w2 * wr * S.invW0;
+            const T Vj = (DIM == 3) ? a[u].w : a[u].z;
+            const T xbj[3] = {b[u].x, b[u].y, b[u].z};
+            // z = V_j xb_k - V_k xb_j;  D z = phi (gF z + hF (e.z) e) + dphi gF^2 (e.z) e
+            T z[3], ez = T(0), exj = T(0);
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                z[d] = Vj * xbk[d] - Vk * xbj[d];
+                ez += e[d] * z[d];
+                exj += e[d] * xbj[d];
+            }
+            const T ce = phi * hF * ez + dphi * gF * gF * ez;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) ax[u % NQ][d] += phi * gF * z[d] + ce * e[d];
+            ar[u % NQ] += phi * gF * exj;
+        }
+    }
+    T gx[3] = {0, 0, 0}, tmp[NQ];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) tmp[q] = ax[q][d];
+        gx[d] = combine_leaves<LPP>(tmp);
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) tmp[q] = ar[q];
+    const T gr = combine_leaves<LPP>(tmp);
+    if (r != 0) return;
+    const int o = orig[k];
+    const T cs = -beta * S.H2;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) cot.x[d][o] += cs * gx[d];
+    cot.rho[o] += cs * (Vk / rho_s[k]) * gr;
 }
 
 // ---------------------------------------------------------------- neighbour export (CSR, original indices)

@@ -68,6 +68,11 @@ def lib():
         L.sph_set_integrator.restype = st
         L.sph_set_integrator.argtypes = [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double)]
+        L.sph_shift.restype = st
+        L.sph_shift.argtypes = [_VP, ctypes.POINTER(SphState), ctypes.c_double, _VP]
+        L.sph_shift_adjoint.restype = st
+        L.sph_shift_adjoint.argtypes = [_VP, ctypes.POINTER(SphState), ctypes.POINTER(SphState), ctypes.c_double,
+                                        _VP]
         L.sph_set_diffusion.restype = st
         L.sph_set_diffusion.argtypes = [_VP, ctypes.c_int32]
         L.sph_set_symplectic.restype = st
@@ -125,7 +130,8 @@ def exported_symbols() -> List[str]:
             "sph_build_cells", "sph_neighbors", "sph_rhs", "sph_step", "sph_step_adjoint", "sph_poll",
             "sph_pair_count", "sph_profile_enable", "sph_profile_read", "sph_last_error", "sph_set_tuning",
             "sph_get_tuning", "sph_rollout_backward", "sph_set_graphs", "sph_density_adjoint", "sph_set_reuse",
-            "sph_set_integrator", "sph_set_symplectic", "sph_set_diffusion"]
+            "sph_set_integrator", "sph_set_symplectic", "sph_set_diffusion", "sph_shift",
+            "sph_shift_adjoint"]
 
 
 KERNEL_CLASSES = ["sort", "build", "sweep", "adjoint", "other"]
@@ -314,6 +320,17 @@ class Plan:
                 raise ValueError("need %d checkpoint slots" % need)
             cp = (SphState * max(need, 1))(*[self.state(*c) for c in ckpt[:need]])
         _check(lib().sph_step(self._h, ctypes.byref(s), int(nsteps), cp, int(ckpt_every), _stream_ptr(stream)))
+
+    def shift(self, x, v, rho, beta: float, stream=None):
+        """Particle shifting of (x, v, rho) in place (x only)."""
+        s = self.state(x, v, rho)
+        _check(lib().sph_shift(self._h, ctypes.byref(s), float(beta), _stream_ptr(stream)))
+
+    def shift_adjoint(self, x, v, rho, gx, gv, grho, beta: float, stream=None):
+        """Cotangents of the shifted state (gx, gv, grho) -> those of (x, v, rho), in place."""
+        s = self.state(x, v, rho)
+        c = self.state(gx, gv, grho)
+        _check(lib().sph_shift_adjoint(self._h, ctypes.byref(s), ctypes.byref(c), float(beta), _stream_ptr(stream)))
 
     def step_adjoint(self, x, v, rho, gx, gv, grho, stream=None):
         """Map the output cotangents (gx, gv, grho) of one step started at (x, v, rho) to its inputs, in place."""

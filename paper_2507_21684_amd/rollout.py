@@ -77,3 +77,30 @@ class SPHDensitySum(torch.autograd.Function):
 def density_sum(plan: Plan, x, v, rho) -> torch.Tensor:
     """Differentiable summation density of all simulations of `plan` (original order)."""
     return SPHDensitySum.apply(x, v, rho, plan)
+
+
+class SPHShift(torch.autograd.Function):
+    """(x, v, rho) -> (x + dr, v, rho): particle shifting as a differentiable post-processing step
+    (`sph_shift` / `sph_shift_adjoint`)."""
+
+    @staticmethod
+    def forward(ctx, x: torch.Tensor, v: torch.Tensor, rho: torch.Tensor, plan: Plan, beta: float):
+        xs = x.detach().clone()
+        plan.shift(xs, v.detach(), rho.detach(), beta)
+        ctx.plan, ctx.beta = plan, float(beta)
+        ctx.save_for_backward(x.detach(), v.detach(), rho.detach())
+        return xs, v.detach().clone(), rho.detach().clone()
+
+    @staticmethod
+    def backward(ctx, gx, gv, grho):
+        x, v, rho = ctx.saved_tensors
+        cx = gx.detach().clone().contiguous() if gx is not None else torch.zeros_like(x)
+        cv = gv.detach().clone().contiguous() if gv is not None else torch.zeros_like(v)
+        cr = grho.detach().clone().contiguous() if grho is not None else torch.zeros_like(rho)
+        ctx.plan.shift_adjoint(x, v, rho, cx, cv, cr, ctx.beta)
+        return cx, cv, cr, None, None
+
+
+def shift(plan: Plan, x, v, rho, beta: float) -> Tuple[torch.Tensor, ...]:
+    """Differentiable particle shift of all simulations of `plan`."""
+    return SPHShift.apply(x, v, rho, plan, beta)
