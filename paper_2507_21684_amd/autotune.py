@@ -31,7 +31,7 @@ import torch
 from .lib import Plan
 
 LANE_CHOICES = (2, 4, 8)
-REBUILD_CHOICES = (1, 4, 8)
+REBUILD_CHOICES = (1, 2, 4, 8)
 SKIN_MARGIN = 1.3
 
 

@@ -569,6 +569,9 @@ __device__ __forceinline__ void unpack_u(const vec4_t<T>& a, T* u)
 // wavefronts' integer atomics do not serialise on a single address.
 constexpr int kPairSlots = 512;
 constexpr int kPairStride = 16;
+// Candidates (of the stencil of one cell) whose stencil cell is looked up in a byte table;
+// later ones, in dense clusters only, search the prefix sums.
+constexpr int kCandTable = 2048;
 
 // One wavefront per cell.  The candidates of the cell's particles are the particles of the
 // (2 sub + 1)^dim stencil cells, taken in lexicographic order of the cell offset (the
@@ -596,6 +599,7 @@ __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ c
     __shared__ int32_t uc_first[128];
     __shared__ int32_t uc_pref[129];
     __shared__ int32_t uc_code[128];
+    __shared__ uint8_t uc_of[kCandTable];  // stencil cell of each of the first kCandTable candidates
 
     const int gc = xcd_remap(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x;
@@ -629,11 +633,14 @@ __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ c
             count = cell_start[id + 1] - first;
         }
         const int inc = wave_incl_scan(count);
+        const int beg = carry + inc - count;
         if (u < 128) {
             uc_first[u] = first;
-            uc_pref[u] = carry + inc - count;
+            uc_pref[u] = beg;
             uc_code[u] = code;
         }
+        const int end = (beg + count < kCandTable) ? beg + count : kCandTable;
+        for (int m = beg; m < end; ++m) uc_of[m] = uint8_t(u);
         carry += __shfl(inc, 63, 64);
     }
     const int M = carry;
@@ -642,21 +649,26 @@ __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ c
 
     // candidate m of the stream: sorted index, position and periodic shift
     auto fetch = [&](int m, int& j, vec4_t<T>& u, int& code) {
-        int lo = 0, hi = ncu - 1;  // last stencil cell whose prefix is <= m
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (uc_pref[mid] <= m) lo = mid;
-            else hi = mid - 1;
+        int lo;  // the stencil cell holding candidate m: the last one whose prefix is <= m
+        if (m < kCandTable) {
+            lo = uc_of[m];
+        } else {
+            lo = 0;
+            int hi = ncu - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (uc_pref[mid] <= m) lo = mid;
+                else hi = mid - 1;
+            }
         }
         j = uc_first[lo] + (m - uc_pref[lo]);
         code = uc_code[lo];
         u = jd0[j];
     };
 
-    const unsigned long long below = (1ull << lane) - 1ull;
     int pairs_acc = 0;
     for (int pb = 0; pb < n; pb += 64) {
-        const int nb = (n - pb < 64) ? n - pb : 64;
+        const int nb = __builtin_amdgcn_readfirstlane((n - pb < 64) ? n - pb : 64);
         __syncthreads();
         if (lane < nb) pu[lane] = jd0[i0 + pb + lane];
         __syncthreads();
@@ -674,15 +686,21 @@ __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ c
             sh[1] = T(((coden >> (kStencilIdBits + 2)) & 3) - 1) * S.L;
             sh[2] = T(((coden >> (kStencilIdBits + 4)) & 3) - 1) * S.L;
             if (c0 + 64 + lane < M) fetch(c0 + 64 + lane, jn, un, coden);  // next chunk in flight
+            const unsigned long long vmask = __ballot(valid);
             for (int p = 0; p < nb; ++p) {
                 T ui[3] = {T(0), T(0), T(0)};
                 unpack_u<T, DIM>(pu[p], ui);
-                const bool ok = valid && dist2_exact<T, DIM>(ui, uj, sh) < R2;
-                const unsigned long long mask = __ballot(ok);
+                const bool inr = dist2_exact<T, DIM>(ui, uj, sh) < R2;
+                const unsigned long long mask = __ballot(inr) & vmask;
+                const bool ok = valid & inr;
                 const int base = __builtin_amdgcn_readlane(cnt, p);
-                const int pos = base + __popcll(mask & below);
-                if (ok && pos < width) nbr[(int64_t)(i0 + pb + p) * width + pos] = jc;
-                if (lane == p) cnt = base + __popcll(mask);
+                // base plus the accepted lanes below this one
+                const unsigned pos = __builtin_amdgcn_mbcnt_hi(
+                    unsigned(mask >> 32), __builtin_amdgcn_mbcnt_lo(unsigned(mask), unsigned(base)));
+                int32_t* row = nbr + (int64_t)(i0 + pb + p) * width;
+                if (ok && pos < unsigned(width)) row[pos] = jc;
+                const int total = base + __popcll(mask);
+                cnt = (lane == p) ? total : cnt;  // lane p keeps p's count
             }
         }
         if (lane < nb) {
