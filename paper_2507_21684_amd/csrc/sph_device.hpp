@@ -1115,7 +1115,7 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
     const int64_t t = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const int64_t i = t / LPP;
     const int r = (int)(t - i * LPP);
-    int accepted = 0;  // pairs j != i kept by the filter (lists with a skin)
+    int accepted = 0;  // entries kept by the filter (lists with a skin), less the self entry
     if (i < N) {
     const int s = psim[i];
     const SimConst<T>& S = sims[s];
@@ -1137,6 +1137,8 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
     n = n < width ? n : width;
     const int mcount = (n - r + LPP - 1) / LPP;
     const int32_t* row = nbr + i * (int64_t)width;
+    // every list holds its particle once, at r2 = 0, which the filter keeps
+    if (r == 0 && n > 0) accepted = -1;
     FwdAcc<T, DIM> acc[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -1169,7 +1171,7 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
             const T r2 = r2_exact<T, DIM>(ui, nb[u].a, c.L, c.invL, d);
             const bool keep = (m0 + u < mcount) && (!filter || r2 < c.H2);
             if (!kSelect && !keep) continue;
-            accepted += (filter && keep && jj[u] != (int)i) ? 1 : 0;
+            accepted += keep ? 1 : 0;
             fwd_pair<T, DIM, MODE == kModeRhs, RENORM>(c, vi, rhoi, pi, nb[u], Gi, d, r2, keep, acc[u % NQ]);
         }
     }

@@ -59,6 +59,7 @@ class Job:
     finished: float = math.nan
     error: int = 0                             # device status word if the request failed
     vtime: float = 0.0                         # estimated device time received so far
+    large: bool = False                        # served one at a time, in admission order
 
     @property
     def dim(self) -> int:
@@ -84,6 +85,20 @@ class Scheduler:
     not held at the pace of the largest one, and the largest one still gets its share.  A request
     admitted mid-way starts at the current smallest virtual time.
 
+    Fair sharing alone stretches the largest requests: they share the device with every request
+    that arrives during their long lives, and with each other, which sets the tail of the latency
+    distribution.  Two rules bound that stretch:
+    * A request whose estimated cost exceeds `large_factor` times the mean estimated cost of the
+      requests admitted so far is large.  Large requests take part in the sharing one at a time,
+      in admission order (the others wait with their virtual time unchanged), so several large
+      requests do not all finish at the end of their combined work; small ones still share the
+      device with the one that runs.
+    * A request that has waited longer than a grace period gains priority: its sharing key is
+      vtime - age_weight * (age - grace), with the age converted to estimated device time (by
+      the ratio of the estimated to the measured time of the ticks so far) and the grace equal
+      to `age_after` mean estimated costs.  Small requests finish well within the grace.
+    With large_factor = 0 and age_weight = 0 the scheduler is plain cost-fair sharing.
+
     The engine supplies footprint(req), segment_cost(job, n), admit(job), forward(jobs, n),
     backward(jobs, n), finish(jobs) and sync(); sync() ends a tick and may return {rid: status}
     for requests whose device status reports a failure (non-finite values, list overflow):
@@ -92,8 +107,9 @@ class Scheduler:
     """
 
     def __init__(self, engine, ckpt_every: int = 8, budget_bytes: int = 64 << 30,
-                 clock: Optional[Callable[[], float]] = None, quantum: float = 2e-3,
-                 progress: Optional[Callable[[str], None]] = None, progress_every: float = 10.0):
+                 clock: Optional[Callable[[], float]] = None, quantum: float = 5e-3,
+                 progress: Optional[Callable[[str], None]] = None, progress_every: float = 10.0,
+                 large_factor: float = 5.0, age_weight: float = 0.5, age_after: float = 16.0):
         if ckpt_every < 1:
             raise ValueError("ckpt_every must be >= 1")
         self.engine = engine
@@ -101,6 +117,13 @@ class Scheduler:
         self.budget = int(budget_bytes)
         self.clock_fn = clock if clock is not None else time.perf_counter
         self.quantum = float(quantum)
+        self.age_weight = float(age_weight)
+        self.age_after = float(age_after)
+        self.large_factor = float(large_factor)
+        self.est_total = 0.0        # estimated device time of the ticks run so far
+        self.wall_total = 0.0       # their measured time
+        self.cost_sum = 0.0         # estimated cost of the requests admitted so far
+        self.admitted_count = 0
         self.now = 0.0
         self.used = 0
         self.peak_used = 0
@@ -108,6 +131,16 @@ class Scheduler:
         self.batch_sizes: List[int] = []
         self.progress = progress
         self.progress_every = progress_every
+
+    def _request_cost(self, j: Job) -> float:
+        """Estimated device time of a whole request: all its forward and backward steps."""
+        phase = j.phase
+        j.phase = "fwd"
+        c = self.engine.segment_cost(j, j.req.steps)
+        j.phase = "bwd"
+        c += self.engine.segment_cost(j, j.req.steps)
+        j.phase = phase
+        return c
 
     def _groups(self, jobs: Sequence[Job]) -> Dict[Tuple[str, int, int], List[Job]]:
         groups: Dict[Tuple[str, int, int], List[Job]] = {}
@@ -140,16 +173,32 @@ class Scheduler:
                 self.peak_used = max(self.peak_used, self.used)
                 j.admitted = self.now
                 j.vtime = vmin
+                rc = self._request_cost(j)
+                self.cost_sum += rc
+                self.admitted_count += 1
+                j.large = self.large_factor > 0 and rc > self.large_factor * self.cost_sum / self.admitted_count
                 active.append(j)
-            vmin = min(j.vtime for j in active)
-            runnable = [j for j in active if j.vtime <= vmin + self.quantum]
+            rate = self.est_total / self.wall_total if self.wall_total > 0 else 1.0
+            grace = self.age_after * self.cost_sum / max(1, self.admitted_count)
+            key = {id(j): j.vtime - self.age_weight * max(0.0, rate * (self.now - j.admitted) - grace)
+                   for j in active}
+            large = [j for j in active if j.large]
+            if len(large) > 1:
+                first = min(large, key=lambda j: (j.admitted, j.req.rid))
+                cand = [j for j in active if not j.large or j is first]
+            else:
+                cand = active
+            kmin = min(key[id(j)] for j in cand)
+            runnable = [j for j in cand if key[id(j)] <= kmin + self.quantum]
             t0 = self.clock_fn()
             for j in [j for j in runnable if j.state is None and j.phase == "fwd" and j.pos == 0]:
                 self.engine.admit(j)
             groups = self._groups(runnable)
             for (phase, _, n), jobs in sorted(groups.items(), key=lambda kv: kv[0]):
                 for j in jobs:
-                    j.vtime += self.engine.segment_cost(j, n)
+                    c = self.engine.segment_cost(j, n)
+                    j.vtime += c
+                    self.est_total += c
                 if phase == "fwd":
                     self.engine.forward(jobs, n)
                     for j in jobs:
@@ -168,6 +217,7 @@ class Scheduler:
                 if j.req.rid in failed:
                     j.error = int(failed[j.req.rid])
                     j.phase = "done"
+            self.wall_total += self.clock_fn() - t0
             self.now += self.clock_fn() - t0
             self.ticks += 1
             self.batch_sizes.append(len(runnable))
@@ -369,10 +419,11 @@ class GpuEngine:
 
 def serve(trace: Sequence[Request], dtype: str = "f32", ckpt_every: int = 8, budget_bytes: int = 64 << 30,
           device=None, tuned: bool = True, progress: Optional[Callable[[str], None]] = None,
-          quantum: float = 2e-3, reuse: int = 8):
-    """Serve `trace` with continuous batching; returns (scheduler, engine, finished jobs)."""
+          quantum: float = 5e-3, reuse: int = 8, **policy):
+    """Serve `trace` with continuous batching; returns (scheduler, engine, finished jobs).
+    `policy` holds the Scheduler's sharing options."""
     eng = GpuEngine(dtype, ckpt_every, device, tuned, reuse)
-    sch = Scheduler(eng, ckpt_every, budget_bytes, quantum=quantum, progress=progress)
+    sch = Scheduler(eng, ckpt_every, budget_bytes, quantum=quantum, progress=progress, **policy)
     done = sch.run(trace)
     return sch, eng, done
 

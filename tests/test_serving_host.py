@@ -210,3 +210,58 @@ def test_rebuild_intervals_divide_the_checkpoint_interval():
     for K in range(1, 17):
         for R in rebuild_intervals(K).values():
             assert K % R == 0
+
+
+def _latencies(trace, **kw):
+    clock = FakeClock()
+    eng = RecordingEngine(clock)
+    sch = Scheduler(eng, 8, 1 << 40, clock=clock, quantum=1e-3, **kw)
+    done = {j.req.rid: j for j in sch.run(trace)}
+    return {rid: j.finished - j.req.arrival for rid, j in done.items()}, eng
+
+
+def test_aging_is_inactive_within_the_grace():
+    # every request finishes within a few mean costs: aging changes nothing
+    trace = small_trace(count=12, rate=20.0)
+    lat_fair, eng_fair = _latencies(trace, age_weight=0.0, large_factor=0.0)
+    lat_aged, eng_aged = _latencies(trace, age_weight=2.0, age_after=50.0, large_factor=0.0)
+    assert eng_fair.calls == eng_aged.calls
+    assert lat_fair == lat_aged
+
+
+def test_aging_bounds_the_stretch_of_an_old_large_request():
+    # a large request under a steady stream of small ones: fair sharing stretches it, aging
+    # gives it a growing share once it has waited past the grace, and the small requests still
+    # finish far sooner than it does
+    rng = np.random.default_rng(3)
+    trace = [Request(0, 0.0, SimSpec(3, 40), 0, 64)]
+    t = 0.0
+    for k in range(1, 200):
+        t += rng.exponential(0.15)
+        trace.append(Request(k, t, SimSpec(2, 24), k, 32))
+    lat_fair, _ = _latencies(trace, age_weight=0.0, large_factor=0.0)
+    lat_aged, _ = _latencies(trace, age_weight=2.0, age_after=8.0, large_factor=0.0)
+    assert lat_aged[0] < 0.8 * lat_fair[0]
+    small = [lat_aged[k] for k in range(1, 200)]
+    assert np.median(small) < 0.1 * lat_aged[0]
+
+
+def test_large_requests_share_one_at_a_time_in_admission_order():
+    # three large requests among small ones: each large one runs alone among the large ones, in
+    # admission order, so the first finishes long before the last instead of all at the end
+    trace = [Request(k, 0.001 * k, SimSpec(2, 16), k, 16) for k in range(20)]
+    trace += [Request(20 + k, 0.02 + 0.001 * k, SimSpec(3, 40), 20 + k, 64) for k in range(3)]
+    lat, eng = _latencies(trace, large_factor=3.0, age_weight=0.0)
+    fin = [lat[20 + k] + 0.02 + 0.001 * k for k in range(3)]
+    assert fin[0] < fin[1] < fin[2]
+    assert fin[0] < 0.5 * fin[2]
+    for c in eng.calls:                       # never two large requests in one tick
+        assert sum(1 for rid in c[1] if rid >= 20) <= 1
+    ticks = {}
+    for i, c in enumerate(eng.calls):
+        for rid in c[1]:
+            ticks.setdefault(rid, []).append(i)
+    assert max(ticks[20]) < min(ticks[21]) and max(ticks[21]) < min(ticks[22])
+    lat_fair, _ = _latencies(trace, large_factor=0.0, age_weight=0.0)
+    fin_fair = [lat_fair[20 + k] + 0.02 + 0.001 * k for k in range(3)]
+    assert fin_fair[0] > 0.8 * fin_fair[2]      # fair sharing: all three end together
