@@ -443,6 +443,50 @@ def bench_renorm(dev, wl, x0, v0, r0, skin, R, lanes, ms_plain, pairs, reps=3):
             "cost_vs_plain_diffusion": round(t * 1e3 / ms_plain, 3)}
 
 
+def bench_shift(dev, wl, x0, v0, r0, lanes, pairs_per_state, reps=20, beta=0.02):
+    """Particle shifting of the default initial state and its VJP, beside one plain step of the
+    same state.  Each call sorts the state, builds its exact lists and runs the shift sweep (and
+    the VJP its adjoint sweep); the step is a one-step call, which also sorts and builds.  Every
+    call starts from a fresh copy of the initial state (copied outside the timed region); beta =
+    0.02 is CFL 0.2 times the Mach number 0.1 of the Taylor-Green flow.  Median over `reps`
+    calls, events on the stream the library launches on."""
+    import numpy as np
+    import torch
+    from paper_2507_21684_amd.lib import Plan
+    plan = Plan([s.params() for s in wl.sims], [s.n for s in wl.sims], wl.dtype, tape_depth=1, device=dev)
+    plan.set_tuning(*lanes)
+
+    def fresh():
+        return (x0.clone(), v0.clone(), r0.clone(), torch.ones_like(x0), torch.ones_like(v0), torch.ones_like(r0))
+
+    calls = {"shift": lambda a: plan.shift(a[0], a[1], a[2], beta),
+             "shift_adjoint": lambda a: plan.shift_adjoint(a[0], a[1], a[2], a[3], a[4], a[5], beta),
+             "step": lambda a: plan.step(a[0], a[1], a[2], 1)}
+    out = {}
+    for name, fn in calls.items():
+        fn(fresh())
+        times = []
+        for _ in range(reps):
+            args = fresh()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn(args)
+            b.record()
+            b.synchronize()
+            times.append(a.elapsed_time(b))
+        out[name] = float(np.median(times))
+        status = plan.poll()
+        assert all(status == 0), "%s: device status %s" % (name, status)
+    return {"workload": wl.name + "_shift", "beta": beta, "shift_ms": round(out["shift"], 4),
+            "shift_adjoint_ms": round(out["shift_adjoint"], 4), "step_ms": round(out["step"], 4),
+            "pair_interactions_per_call": int(pairs_per_state),
+            "shift_value": round(pairs_per_state / (out["shift"] * 1e-3), 1),
+            "shift_adjoint_value": round(pairs_per_state / (out["shift_adjoint"] * 1e-3), 1),
+            "unit": "pair interactions/s",
+            "note": "each call sorts and builds exact lists of its state; step = one sph_step call of 1 step; "
+                    "pairs per call = the job's mean pairs per state"}
+
+
 def log(msg):
     """Progress line on stderr (the JSON result is the only line on stdout)."""
     print("[bench] " + msg, file=sys.stderr, flush=True)
@@ -613,8 +657,10 @@ def main():
         renorm = bench_renorm(dev, wl, x0, v0, r0, list_skin, list_rebuild, lanes, 1e3 * elapsed / args.steps,
                               p_fwd + p_adj)
 
-    rk4 = symp = None
+    rk4 = symp = shift = None
     if args.workload == "tgv2d_64k_f32":
+        log("particle shifting")
+        shift = bench_shift(dev, wl, x0, v0, r0, lanes, p_fwd / wl.steps)
         log("RK4 job")
         rk4 = bench_rk4(dev)
         log("symplectic Euler jobs")
@@ -638,7 +684,7 @@ def main():
                       "list_rebuild_every": list_rebuild},
            "roofline": roof, "kernel_ms_per_job": breakdown, "cpu_baseline": cpu, "batched": batched, "serving": served,
            "density_backward": dens, "rk4": rk4, "symplectic": symp,
-           "renormalised_diffusion": renorm}
+           "renormalised_diffusion": renorm, "shift": shift}
     print(json.dumps(out), flush=True)
 
 
