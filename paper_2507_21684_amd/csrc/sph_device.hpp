@@ -578,7 +578,8 @@ constexpr int kCandTable = 2048;
 // precomputed stencil table lists them in that order), each cell's particles in sorted order
 // (= original index inside a cell), which is the canonical list order.  The candidate stream
 // is cut into chunks of 64; lane l holds candidate 64 c + l of chunk c in registers (the next
-// chunk's gather is issued before the current chunk is tested), and the cell's particles,
+// chunk's gather is issued before the current chunk is tested; a candidate's stencil cell comes
+// from a byte table in LDS, or a search of the prefix sums past it), and the cell's particles,
 // staged in LDS, are taken one after the other with the same address in every lane.  For
 // particle p one round tests all 64 candidates of the chunk; the ballot of the accepted ones
 // gives each its rank, so the round appends a contiguous run to p's row, in candidate order.
