@@ -289,20 +289,6 @@ __device__ __forceinline__ I block_excl_scan(I v, I* smem /* >= 5 */, I* total)
     return off + inc - v;
 }
 
-template <typename I>
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const I* __restrict__ in, int64_t n, I* __restrict__ part)
-{
-    __shared__ I smem[8];
-    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    I s = 0;
-#pragma unroll
-    for (int k = 0; k < kScanItems; ++k)
-        if (base + k < n) s += in[base + k];
-    I tot;
-    block_excl_scan<I>(s, smem, &tot);
-    if (threadIdx.x == 0) part[blockIdx.x] = tot;
-}
-
 // Tile sums, and the workgroup that finishes last (atomic ticket; no waiting on other
 // workgroups) turns them into exclusive tile offsets, part[np] = grand total, and resets the
 // ticket for the next scan.
@@ -348,67 +334,6 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce_last(const I* __re
         part[np] = carry;
         *ticket = 0u;
     }
-}
-
-// one workgroup: exclusive scan of part[0..np), part[np] = grand total
-template <typename I>
-__global__ __launch_bounds__(1024) void k_scan_top(I* __restrict__ part, int64_t np)
-{
-    __shared__ I smem[16];
-    __shared__ I carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int64_t b = 0; b < np; b += blockDim.x) {
-        int64_t i = b + threadIdx.x;
-        I v = (i < np) ? part[i] : I(0);
-        I tot;
-        I ex = block_excl_scan<I>(v, smem, &tot);
-        I c = carry;
-        if (i < np) part[i] = c + ex;
-        __syncthreads();
-        if (threadIdx.x == 0) carry = c + tot;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[np] = carry;
-}
-
-// One workgroup scans everything (for up to a few tens of thousands of elements this is one
-// launch instead of three): out[i] = exclusive prefix of in, out[n] = total, `in` optionally
-// zeroed.  Each pass covers 1024 threads x 16 consecutive elements.
-template <typename I>
-__global__ __launch_bounds__(1024) void k_scan_single(I* __restrict__ in, int64_t n, I* __restrict__ out, int zero_in)
-{
-    constexpr int kItems = 16;
-    __shared__ I smem[16];
-    __shared__ I carry_s;
-    if (threadIdx.x == 0) carry_s = 0;
-    __syncthreads();
-    for (int64_t b = 0; b < n; b += (int64_t)blockDim.x * kItems) {
-        const int64_t base = b + (int64_t)threadIdx.x * kItems;
-        I v[kItems];
-        I sum = 0;
-#pragma unroll
-        for (int k = 0; k < kItems; ++k) {
-            v[k] = (base + k < n) ? in[base + k] : I(0);
-            sum += v[k];
-        }
-        I tot;
-        I ex = block_excl_scan<I>(sum, smem, &tot);
-        const I carry = carry_s;
-        ex += carry;
-#pragma unroll
-        for (int k = 0; k < kItems; ++k) {
-            if (base + k < n) {
-                out[base + k] = ex;
-                if (zero_in) in[base + k] = 0;
-            }
-            ex += v[k];
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) carry_s = carry + tot;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[n] = carry_s;
 }
 
 // out[i] = exclusive prefix of in; out[n] = total; optionally zero `in` afterwards
