@@ -92,8 +92,7 @@ class Scheduler:
       requests admitted so far is large.  Large requests take part in the sharing one at a time,
       in admission order (the others wait with their virtual time unchanged), so several large
       requests do not all finish at the end of their combined work; small ones still share the
-      device with the one that runs.  A waiting large request's virtual time keeps up with the
-      others', so that it shares the device from the moment it is first.
+      device with the one that runs.
     * A request that has waited longer than a grace period gains priority: its sharing key is
       vtime - age_weight * (age - grace), with the age converted to estimated device time (by
       the ratio of the estimated to the measured time of the ticks so far) and the grace equal
@@ -187,12 +186,6 @@ class Scheduler:
             if len(large) > 1:
                 first = min(large, key=lambda j: (j.admitted, j.req.rid))
                 cand = [j for j in active if not j.large or j is first]
-                # a waiting large request keeps up with the sharing (as if admitted now) so that
-                # it does not run alone to make up the time it waited once it is first
-                vc = min(j.vtime for j in cand)
-                for j in large:
-                    if j is not first:
-                        j.vtime = max(j.vtime, vc)
             else:
                 cand = active
             kmin = min(key[id(j)] for j in cand)
