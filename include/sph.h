@@ -334,9 +334,11 @@ sph_status sph_density_adjoint(sph_plan* plan, const sph_state* s, const void* r
  * and clear them.  SYNCHRONOUS. */
 sph_status sph_poll(sph_plan* plan, int32_t* per_sim_status, void* stream);
 
-/* Number of directed neighbour pairs (i, j), j != i, found by the neighbour-list builds
- * since the last call (host out-parameter), then reset.  This is the unit of the pair
- * interaction rate.  SYNCHRONOUS. */
+/* Number of directed neighbour pairs (i, j), j != i, with r < H, counted since the last
+ * call (host out-parameter), then reset: by the neighbour-list builds for exact lists, or,
+ * when the plan's lists carry a skin, by the forward sweeps that filter them (one count per
+ * right-hand-side evaluation either way).  This is the unit of the pair interaction rate.
+ * SYNCHRONOUS. */
 sph_status sph_pair_count(sph_plan* plan, int64_t* pairs, void* stream);
 
 /* Kernel classes timed by the profiler. */
