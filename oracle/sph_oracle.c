@@ -49,6 +49,12 @@
  *   - DualSPHysics' symplectic Euler (Sec. 3.4, App. C), optionally with
  *     the last substep's rates re-used as the next step's first substep,
  *     and its vector-Jacobian products for one step and for a rollout.
+ *   - Explicit Runge-Kutta steps from a Butcher tableau (Sec. 3.4, the
+ *     multistage integrators) and their vector-Jacobian products.
+ *   - The full delta-SPH diffusion with the renormalised density gradient
+ *     <grad rho>_i = L_i sum_j V_j (rho_j - rho_i) grad_i W_ij,
+ *     L_i = [sum_j V_j (x_j - x_i) (x) grad_i W_ij]^-1 (App. A.5, renormalised
+ *     gradient; Sec. 2.3 cites the scheme), and its vector-Jacobian product.
  *
  * Readings taken where the paper is silent or garbled are listed in the
  * project's design notes; the ones that change arithmetic are: the minus
