@@ -487,6 +487,32 @@ def bench_shift(dev, wl, x0, v0, r0, lanes, pairs_per_state, reps=20, beta=0.02)
                     "pairs per call = the job's mean pairs per state"}
 
 
+def bench_export(dev, wl, x0, v0, r0, reps=20):
+    """The neighbour export (sph_neighbors) of the default initial state: a sort, an exact list
+    build and the CSR export over original indices (offsets int64[N+1], entries int32), one
+    synchronous call (it returns the entry count to the host).  Median wall time over `reps`
+    calls after a warm-up call; the bytes are the CSR written."""
+    import numpy as np
+    import torch
+    from paper_2507_21684_amd.lib import Plan
+    plan = Plan([s.params() for s in wl.sims], [s.n for s in wl.sims], wl.dtype, tape_depth=1, device=dev)
+    off, nbr = plan.neighbors(x0, v0, r0)
+    total = int(nbr.numel())
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.neighbors(x0, v0, r0)
+        times.append(time.perf_counter() - t0)
+    assert all(plan.poll() == 0)
+    t = float(np.median(times))
+    n = int(sum(s.n for s in wl.sims))
+    nbytes = 8 * (n + 1) + 4 * total
+    return {"workload": wl.name + "_neighbor_export", "entries": total, "pairs": total - n,
+            "ms_per_call": round(t * 1e3, 4), "csr_bytes": nbytes, "csr_gbs": round(nbytes / t / 1e9, 1),
+            "note": "one synchronous sph_neighbors call: sort, exact list build, CSR export; wall time"}
+
+
 def log(msg):
     """Progress line on stderr (the JSON result is the only line on stdout)."""
     print("[bench] " + msg, file=sys.stderr, flush=True)
@@ -657,8 +683,10 @@ def main():
         renorm = bench_renorm(dev, wl, x0, v0, r0, list_skin, list_rebuild, lanes, 1e3 * elapsed / args.steps,
                               p_fwd + p_adj)
 
-    rk4 = symp = shift = None
+    rk4 = symp = shift = export = None
     if args.workload == "tgv2d_64k_f32":
+        log("neighbour export")
+        export = bench_export(dev, wl, x0, v0, r0)
         log("particle shifting")
         shift = bench_shift(dev, wl, x0, v0, r0, lanes, p_fwd / wl.steps)
         log("RK4 job")
@@ -684,7 +712,7 @@ def main():
                       "list_rebuild_every": list_rebuild},
            "roofline": roof, "kernel_ms_per_job": breakdown, "cpu_baseline": cpu, "batched": batched, "serving": served,
            "density_backward": dens, "rk4": rk4, "symplectic": symp,
-           "renormalised_diffusion": renorm, "shift": shift}
+           "renormalised_diffusion": renorm, "shift": shift, "neighbor_export": export}
     print(json.dumps(out), flush=True)
 
 
