@@ -378,7 +378,7 @@ class Plan:
         return int(a.value), int(b.value)
 
     def pair_count(self, stream=None) -> int:
-        """Directed neighbour pairs (j != i) found by list builds since the last call."""
+        """Directed neighbour pairs (j != i, r < H) counted since the last call, then reset."""
         v = ctypes.c_int64()
         _check(lib().sph_pair_count(self._h, ctypes.byref(v), _stream_ptr(stream)))
         return int(v.value)
