@@ -72,8 +72,13 @@ typedef int32_t sph_status;
 
 /* Parameters of one simulation (Sec. 2.3 governing equations, App. A.1 kernel,
  * Sec. 3.4 fixed time step).  "support" is the kernel support radius H, the
- * distance at which the Wendland-C4 kernel vanishes; the paper calls it h
- * (App. A.1) and so it also enters dt, delta*H*c0 and alpha*H*c0. */
+ * distance at which the Wendland-C4 kernel vanishes; the paper stores the
+ * support under the name h (App. A.1), and H is what enters delta*H*c0 and
+ * alpha*H*c0.  The time step is the caller's `dt`: the workloads of this
+ * library take dt = 0.25 h / c0 with the smoothing length h = H / 2, i.e.
+ * dt = 0.125 H / c0 (the acoustic condition of Sec. 3.4 read with the
+ * literature's H / h = 2 of App. A.1; with h = H the Taylor-Green flows blow
+ * up within about a hundred steps). */
 typedef struct sph_params {
     int32_t dim;      /* 2 or 3 */
     int32_t dtype;    /* SPH_F32 or SPH_F64; equal for every simulation of a plan */
@@ -142,9 +147,14 @@ sph_status sph_get_tuning(const sph_plan* plan, int32_t* lanes_fwd, int32_t* lan
  * the tableau A (host, stages x stages, row-major, strictly lower triangular)
  * and weights b (host, stages) for the state u = (x, v, rho) with
  * du/dt = f(u) = (v, a(u), drho/dt(u)):
- *     u_i = u + dt sum_{j<i} A_ij k_i,  k_i = f(u_i),  u' = u + dt sum_i b_i k_i,
- * every stage with its own sort and neighbour lists (a reuse interval applies
- * to the semi-implicit Euler step only).  sph_step, sph_step_adjoint and
+ *     u_i = u + dt sum_{j<i} A_ij k_j,  k_i = f(u_i),  u' = u + dt sum_i b_i k_i.
+ * Without a list skin every stage sorts its state and builds its own neighbour
+ * lists.  With a skin in the plan's parameters only the first stage of a step
+ * sorts and builds; the later stages are gathered into its particle order, use
+ * its lists filtered to r < H (so every stage still evaluates exactly its own
+ * pair set), and set SPH_FLAG_SKIN when a particle moved more than half the
+ * skin since the build.  The reuse interval of sph_set_reuse applies to the
+ * semi-implicit Euler step only.  sph_step, sph_step_adjoint and
  * sph_rollout_backward then use the scheme; the adjoint reverses the stages
  * over the update function's VJP.  The first call with stages > 0 reserves the
  * stage storage and so grows sph_workspace_size(): make it before sph_bind
@@ -158,7 +168,10 @@ sph_status sph_set_integrator(sph_plan* plan, int32_t stages, const double* A, c
  *     predictor  u_h = (x + h v, v + h a1, rho + h D1),  (a1, D1) = f(u),
  *     corrector  (a2, D2) = f(u_h),  v' = v + dt a2,  x' = x_h + h v',
  *                rho' = rho (2 - e) / (2 + e),  e = -dt D2 / rho_h,
- * each evaluation of f with its own sort and neighbour lists.  With
+ * each evaluation of f with its own sort and neighbour lists; with a list
+ * skin, a corrector that follows an evaluation of f(u) in the same step keeps
+ * that evaluation's particle order and lists (filtered to r < H, displacement
+ * checked against half the skin as for Runge-Kutta stages).  With
  * reuse_last_substep != 0, the predictor takes the previous step's corrector
  * rates (a2, D2) instead of evaluating f(u) (the modified scheme of Sec. 3.4 /
  * App. C that re-uses the last substep's update values): one evaluation of f
@@ -262,7 +275,9 @@ sph_status sph_build_cells(sph_plan* plan, const sph_state* s, void* stream);
  * int32[capacity]) the entries.  *total (host) receives the number of
  * entries.  SYNCHRONOUS (waits on stream).  Returns CAPACITY, writing only
  * offsets and *total, when total > capacity; returns CAPACITY too when a
- * particle has more than max_neighbors neighbours. */
+ * particle has more than max_neighbors neighbours.  That overflow is this
+ * call's own: it is neither taken from nor added to the status words that
+ * sph_poll() reads (a non-finite position found by the sort still is). */
 sph_status sph_neighbors(sph_plan* plan, const sph_state* s, int64_t* offsets, int32_t* nbr,
                          int64_t capacity, int64_t* total, void* stream);
 

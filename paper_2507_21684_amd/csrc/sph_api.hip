@@ -103,6 +103,9 @@ struct sph_plan {
     size_t o_simc = 0, o_psim = 0, o_cell_sim = 0, o_blk_coord = 0, o_blk_rank = 0;
     size_t o_cell_count = 0, o_cell_start = 0, o_part = 0, o_cell_of = 0, o_slot_of = 0, o_tmp = 0;
     size_t o_SB = 0, o_jdA = 0, o_jdB = 0, o_status = 0, o_part64 = 0, o_pairs = 0, o_ticket = 0, o_uref = 0;
+    // status words of the neighbour export's own list build, kept apart from the plan's status
+    // words (an overflow there is returned by sph_neighbors, not left for sph_poll)
+    size_t o_status_x = 0;
     // two buffers of adjoint prologue records; adj_buf is the one in use, and adj_ready the tape
     // slot whose records an adjoint sweep has already written there (-1: none)
     size_t o_jdA2 = 0, o_jdB2 = 0;
@@ -363,9 +366,10 @@ sph_status sort_into(sph_plan* P, StatePtrs<T, D> src, const int32_t* orig_in, i
 // With a skin the pairs are counted by the forward sweeps, which filter them; without one,
 // here.
 template <typename T, int D>
-sph_status build_lists(sph_plan* P, int slot, hipStream_t st, bool exact = false)
+sph_status build_lists(sph_plan* P, int slot, hipStream_t st, bool exact = false, int32_t* status = nullptr)
 {
     if (P->N == 0 || P->ncell == 0) return SPH_OK;
+    if (!status) status = wsp<int32_t>(P, P->o_status);
     const SlotLayout& L = P->slot[slot];
     P->list_of[slot] = slot;
     ProfScope prof(P, st, SPH_KERN_BUILD, true);
@@ -373,7 +377,7 @@ sph_status build_lists(sph_plan* P, int slot, hipStream_t st, bool exact = false
         wsp<int32_t>(P, P->o_cell_sim), wsp<int32_t>(P, P->o_blk_coord), wsp<int32_t>(P, P->o_blk_rank),
         wsp<SimConst<T>>(P, P->o_simc),
         wsp<int32_t>(P, P->o_cell_start), wsp<vec4_t<T>>(P, L.jd0), P->width,
-        wsp<int32_t>(P, L.nbr), wsp<int32_t>(P, L.cnt), wsp<int32_t>(P, P->o_status),
+        wsp<int32_t>(P, L.nbr), wsp<int32_t>(P, L.cnt), status,
         P->filter ? nullptr : wsp<unsigned long long>(P, P->o_pairs), exact ? 1 : 0);
     LAUNCH_CHECK("build_list");
     return SPH_OK;
@@ -1147,7 +1151,12 @@ sph_status do_neighbors(sph_plan* P, const sph_state* s, int64_t* offsets, int32
                         int64_t* total, hipStream_t st)
 {
     RC_TRY((sort_into<T, D>(P, user_state<T, D>(s), nullptr, 0, st)));
-    RC_TRY((build_lists<T, D>(P, 0, st, true)));
+    // this build's overflow goes to private status words, cleared first: status bits left by
+    // earlier calls neither fail the export nor get the export's overflow added to them
+    int32_t* xstat = wsp<int32_t>(P, P->o_status_x);
+    k_fill<int32_t><<<grid_for(P->nsims, 256), 256, 0, st>>>(xstat, P->nsims, 0);
+    LAUNCH_CHECK("fill");
+    RC_TRY((build_lists<T, D>(P, 0, st, true, xstat)));
     const int64_t N = P->N;
     const SlotLayout& L = P->slot[0];
     const int32_t* orig = wsp<int32_t>(P, L.orig);
@@ -1161,8 +1170,7 @@ sph_status do_neighbors(sph_plan* P, const sph_state* s, int64_t* offsets, int32
     int64_t tot = 0;
     HIP_TRY(hipMemcpyAsync(&tot, offsets + N, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     std::vector<int32_t> stat(P->nsims, 0);
-    HIP_TRY(hipMemcpyAsync(stat.data(), wsp<int32_t>(P, P->o_status), sizeof(int32_t) * P->nsims,
-                           hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(stat.data(), xstat, sizeof(int32_t) * P->nsims, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     *total = tot;
     for (int s2 = 0; s2 < P->nsims; ++s2)
@@ -1344,6 +1352,7 @@ sph_status sph_plan_create(const sph_params* sims, int32_t nsims, const int64_t*
     P->o_jdA2 = take(V4 * N);
     P->o_jdB2 = take(V4 * N);
     P->o_status = take(4 * (size_t)nsims);
+    P->o_status_x = take(4 * (size_t)nsims);
     P->o_part64 = take(8 * ((size_t)P->nparts64 + 1) + 8 * (N + 1));
     P->o_pairs = take(8 * (size_t)kPairSlots * kPairStride);
     P->o_ticket = take(4);

@@ -15,7 +15,20 @@ from typing import Optional, Tuple
 
 import torch
 
-from .lib import Plan
+from .lib import FLAG_NONFINITE, Plan, SphError
+
+ERR_CAPACITY, ERR_NONFINITE = -3, -4
+
+
+def check_status(plan: Plan, what: str) -> None:
+    """Read (and clear) the plan's device status words; raise SphError if any simulation reports
+    a non-finite value, a neighbour-list overflow or a particle that outran its list skin.
+    Synchronises the stream."""
+    st = plan.poll()
+    bad = [(k, int(w)) for k, w in enumerate(st) if w]
+    if bad:
+        code = ERR_NONFINITE if any(w & FLAG_NONFINITE for _, w in bad) else ERR_CAPACITY
+        raise SphError(code, "%s: device status of (simulation, flags): %s" % (what, bad[:8]))
 
 
 class SPHRollout(torch.autograd.Function):
@@ -23,14 +36,16 @@ class SPHRollout(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, x0: torch.Tensor, v0: torch.Tensor, rho0: torch.Tensor, plan: Plan, nsteps: int,
-                ckpt_every: int):
+                ckpt_every: int, check: bool = True):
         K = max(1, int(ckpt_every))
         nseg = math.ceil(nsteps / K) if nsteps > 0 else 0
         x, v, rho = x0.detach().clone(), v0.detach().clone(), rho0.detach().clone()
         ckpts = [plan.empty_state() for _ in range(nseg)]
         if nsteps > 0:
             plan.step(x, v, rho, nsteps, ckpts, K)
-        ctx.plan, ctx.nsteps, ctx.K, ctx.nseg = plan, int(nsteps), K, nseg
+            if check:
+                check_status(plan, "rollout forward")
+        ctx.plan, ctx.nsteps, ctx.K, ctx.nseg, ctx.check = plan, int(nsteps), K, nseg, bool(check)
         flat = [t for c in ckpts for t in c]
         ctx.save_for_backward(*flat)
         return x, v, rho
@@ -46,12 +61,17 @@ class SPHRollout(torch.autograd.Function):
         cr = grho.detach().clone().contiguous() if grho is not None else torch.zeros_like(ref[2])
         if ctx.nsteps > 0:
             plan.rollout_backward(ckpts, ctx.nsteps, ctx.K, cx, cv, cr)
-        return cx, cv, cr, None, None, None
+            if ctx.check:
+                check_status(plan, "rollout backward")
+        return cx, cv, cr, None, None, None, None
 
 
-def rollout(plan: Plan, x0, v0, rho0, nsteps: int, ckpt_every: int = 8) -> Tuple[torch.Tensor, ...]:
-    """Differentiable T-step rollout of all simulations of `plan`."""
-    return SPHRollout.apply(x0, v0, rho0, plan, nsteps, ckpt_every)
+def rollout(plan: Plan, x0, v0, rho0, nsteps: int, ckpt_every: int = 8, check: bool = True) -> Tuple[torch.Tensor, ...]:
+    """Differentiable T-step rollout of all simulations of `plan`.  With `check` (default) the
+    forward and the backward each end by reading the device status words and raise SphError if a
+    simulation went non-finite, overflowed its neighbour lists or outran its list skin (a
+    synchronisation each); check=False leaves the status words for the caller's own poll()."""
+    return SPHRollout.apply(x0, v0, rho0, plan, nsteps, ckpt_every, check)
 
 
 class SPHDensitySum(torch.autograd.Function):

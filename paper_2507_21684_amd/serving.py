@@ -60,6 +60,7 @@ class Job:
     error: int = 0                             # device status word if the request failed
     vtime: float = 0.0                         # estimated device time received so far
     large: bool = False                        # served one at a time, in admission order
+    promoted: bool = False                     # a large request whose turn has come
 
     @property
     def dim(self) -> int:
@@ -90,9 +91,10 @@ class Scheduler:
     distribution.  Two rules bound that stretch:
     * A request whose estimated cost exceeds `large_factor` times the mean estimated cost of the
       requests admitted so far is large.  Large requests take part in the sharing one at a time,
-      in admission order (the others wait with their virtual time unchanged), so several large
-      requests do not all finish at the end of their combined work; small ones still share the
-      device with the one that runs.
+      in admission order, so several large requests do not all finish at the end of their
+      combined work; small ones still share the device with the one that runs.  A waiting large
+      request is left out of the smallest virtual time that newcomers start from, and when its
+      turn comes it starts from the smallest virtual time of the others.
     * A request that has waited longer than a grace period gains priority: its sharing key is
       vtime - age_weight * (age - grace), with the age converted to estimated device time (by
       the ratio of the estimated to the measured time of the ticks so far) and the grace equal
@@ -142,6 +144,24 @@ class Scheduler:
         j.phase = phase
         return c
 
+    @staticmethod
+    def _sharing(active: Sequence[Job]) -> List[Job]:
+        """The requests that share the device now: every small one and the first large one (by
+        admission).  A large request that becomes first after waiting starts from the smallest
+        virtual time of the others, so it joins the sharing instead of running alone until its
+        frozen virtual time catches up."""
+        large = [j for j in active if j.large]
+        if not large:
+            return list(active)
+        first = min(large, key=lambda j: (j.admitted, j.req.rid))
+        cand = [j for j in active if not j.large or j is first]
+        if not first.promoted:
+            first.promoted = True
+            others = [j.vtime for j in cand if j is not first]
+            if others:
+                first.vtime = max(first.vtime, min(others))
+        return cand
+
     def _groups(self, jobs: Sequence[Job]) -> Dict[Tuple[str, int, int], List[Job]]:
         groups: Dict[Tuple[str, int, int], List[Job]] = {}
         for j in jobs:
@@ -166,7 +186,10 @@ class Scheduler:
             if not queue and not active:
                 self.now = max(self.now, pending[0].arrival)
                 continue
-            vmin = min((j.vtime for j in active), default=0.0)
+            # new requests start at the smallest virtual time among the requests that may run
+            # now: a large request waiting for its turn keeps a frozen, lower virtual time and
+            # is left out, so that newcomers do not start below the running set and run alone
+            vmin = min((j.vtime for j in self._sharing(active)), default=0.0)
             while queue and (self.used + queue[0].footprint <= self.budget or not active):
                 j = queue.popleft()
                 self.used += j.footprint
@@ -182,12 +205,7 @@ class Scheduler:
             grace = self.age_after * self.cost_sum / max(1, self.admitted_count)
             key = {id(j): j.vtime - self.age_weight * max(0.0, rate * (self.now - j.admitted) - grace)
                    for j in active}
-            large = [j for j in active if j.large]
-            if len(large) > 1:
-                first = min(large, key=lambda j: (j.admitted, j.req.rid))
-                cand = [j for j in active if not j.large or j is first]
-            else:
-                cand = active
+            cand = self._sharing(active)
             kmin = min(key[id(j)] for j in cand)
             runnable = [j for j in cand if key[id(j)] <= kmin + self.quantum]
             t0 = self.clock_fn()

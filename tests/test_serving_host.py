@@ -265,3 +265,46 @@ def test_large_requests_share_one_at_a_time_in_admission_order():
     lat_fair, _ = _latencies(trace, large_factor=0.0, age_weight=0.0)
     fin_fair = [lat_fair[20 + k] + 0.02 + 0.001 * k for k in range(3)]
     assert fin_fair[0] > 0.8 * fin_fair[2]      # fair sharing: all three end together
+
+
+def _tick_gaps(eng, rid, t_from=None):
+    """Largest number of consecutive ticks (group calls) without `rid` while it was active."""
+    idx = [i for i, c in enumerate(eng.calls) if rid in c[1]]
+    return max(b - a - 1 for a, b in zip(idx, idx[1:])) if len(idx) > 1 else 0
+
+
+def test_newcomers_do_not_freeze_the_running_set_while_a_large_request_waits():
+    # two large requests (the second waits for the first) and a small request in flight; small
+    # requests that arrive later start at the running set's smallest virtual time, not at the
+    # frozen one of the waiting large request, so the in-flight small request keeps getting
+    # ticks; and the second large request, when its turn comes, shares the device too
+    trace = [Request(k, 0.0001 * k, SimSpec(2, 16), k, 16) for k in range(8)]
+    trace += [Request(8, 0.001, SimSpec(2, 16), 8, 48), Request(9, 0.002, SimSpec(3, 40), 9, 64),
+              Request(10, 0.003, SimSpec(3, 40), 10, 64)]
+    t = 0.3
+    for k in range(11, 60):
+        trace.append(Request(k, t, SimSpec(2, 16), k, 32))
+        t += 0.04 if k < 40 else 1.0
+    clock = FakeClock()
+    eng = RecordingEngine(clock)
+    starts = []
+    fwd, bwd = eng.forward, eng.backward
+    eng.forward = lambda jobs, n: (starts.append(clock.t), fwd(jobs, n))
+    eng.backward = lambda jobs, n: (starts.append(clock.t), bwd(jobs, n))
+    sch = Scheduler(eng, 8, 1 << 40, clock=clock, quantum=1e-3, large_factor=3.0, age_weight=0.0)
+    done = {j.req.rid: j for j in sch.run(trace)}
+    assert sorted(done) == list(range(60))
+    assert done[9].large and done[10].large and not done[8].large
+    # the in-flight small request is never left out for more than a handful of group calls
+    assert _tick_gaps(eng, 8) <= 4
+    # once the first large request is done, the second does not run alone while small requests
+    # that arrived meanwhile wait (at most the one call in which they are admitted)
+    end9 = max(i for i, c in enumerate(eng.calls) if 9 in c[1])
+    alone = longest = 0
+    for i in range(end9 + 1, len(eng.calls)):
+        t = starts[i]
+        waiting = [k for k in range(11, 60) if done[k].admitted <= t < done[k].finished]
+        alone = alone + 1 if eng.calls[i][1] == [10] and waiting else 0
+        longest = max(longest, alone)
+    assert any(done[k].finished > done[9].finished for k in range(11, 60))
+    assert longest <= 2
