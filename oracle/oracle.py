@@ -130,6 +130,9 @@ def lib():
         L.orc_rollout.restype = ctypes.c_int
         L.orc_rollout.argtypes = [_P, ctypes.c_int64, _D, _D, _D, ctypes.c_int32, ctypes.c_int32,
                                   _D, _D, _D, _D, _D, _D, _D]
+        L.orc_neighbors_adaptive.restype = ctypes.c_int64
+        L.orc_neighbors_adaptive.argtypes = [ctypes.c_int, ctypes.c_int64, _D, ctypes.c_double, _D, ctypes.c_int,
+                                             ctypes.c_int, _I64, _I32, ctypes.c_int64, _D]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_set_num_threads.restype = None
         L.orc_set_num_threads.argtypes = [ctypes.c_int]
@@ -202,6 +205,27 @@ def neighbors(x, L: float, H: float, prec: str = "f64", brute: bool = False):
                                  idx.ctypes.data_as(_I32), total)
     assert total2 == total
     return off, idx[:total]
+
+
+def neighbors_adaptive(x, L: float, h, prec: str = "f64", brute: bool = False):
+    """Neighbour lists with per-particle supports h (n values): the search radius
+    s_k = max(h_k, max{h_i : r_ik < h_i}), then the pairs r_ij < max(h_i, h_j) found by searching
+    with s_i.  Returns (offsets int64[n+1], idx int32, s float64[n]); rows ascending, self
+    included; predicates in the working precision as for neighbors()."""
+    x, h = _f64(x), _f64(h)
+    dim, n = x.shape
+    off = np.zeros(n + 1, dtype=np.int64)
+    s = np.zeros(n)
+    p = 1 if prec == "f32" else 0
+    total = lib().orc_neighbors_adaptive(dim, n, _d(x), L, _d(h), p, int(brute), off.ctypes.data_as(_I64), None, 0,
+                                         _d(s))
+    if total < 0:
+        raise ValueError("oracle adaptive neighbour search rejected its input")
+    idx = np.zeros(max(total, 1), dtype=np.int32)
+    total2 = lib().orc_neighbors_adaptive(dim, n, _d(x), L, _d(h), p, int(brute), off.ctypes.data_as(_I64),
+                                          idx.ctypes.data_as(_I32), total, _d(s))
+    assert total2 == total
+    return off, idx[:total], s
 
 
 # ---------------------------------------------------------------- physics

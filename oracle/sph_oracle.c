@@ -51,6 +51,10 @@
  *     and its vector-Jacobian products for one step and for a rollout.
  *   - Explicit Runge-Kutta steps from a Butcher tableau (Sec. 3.4, the
  *     multistage integrators) and their vector-Jacobian products.
+ *   - Neighbour search with per-particle support radii h_i: a search radius
+ *     s_k = max(h_k, max{h_i : |x_ik| < h_i}) (the atomic-maximum step), then
+ *     the super-symmetric set |x_ij| < max(h_i, h_j) found by searching with s_i
+ *     (Sec. 3.2 "Ensuring symmetric interactions", App. B).
  *   - The full delta-SPH diffusion with the renormalised density gradient
  *     <grad rho>_i = L_i sum_j V_j (rho_j - rho_i) grad_i W_ij,
  *     L_i = [sum_j V_j (x_j - x_i) (x) grad_i W_ij]^-1 (App. A.5, renormalised
@@ -1679,6 +1683,148 @@ int orc_shift_vjp(const orc_params* p, int64_t n, const double* x, const double*
     nblist_free(&nb);
     free(u);
     return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Neighbour search with per-particle support radii (Sec. 3.2,         */
+/* "Ensuring symmetric interactions"; App. B, the search-radius step)  */
+/* ------------------------------------------------------------------ */
+
+/* Each particle i carries its own support h_i.  Steps, in the paper's order:
+ *   1. search radius: s_k starts at h_k and is raised to h_i for every particle
+ *      i that has k as a neighbour under its own support (r_ik < h_i); written
+ *      here as the definition s_k = max(h_k, max{h_i : r_ik < h_i}), gathered
+ *      per k (the paper's atomic maximum reaches the same value in any order);
+ *   2. neighbourhood construction: particle i searches with s_i and keeps the
+ *      pairs of the super-symmetric set, r_ij < max(h_i, h_j).
+ * Every pair with r_ij < max(h_i, h_j) is found by the search of step 2: if
+ * h_i >= h_j it lies within h_i <= s_i, else i is a neighbour of j under h_j and
+ * step 1 raised s_i to at least h_j.  Predicates as for a uniform support:
+ * strict r^2 < h^2 with h^2 = h * h rounded once, on wrapped positions, in the
+ * working precision (prec 1: positions and supports first rounded to float).
+ * Candidates come from a bucket grid of cells of side >= 1.01 max_i h_i (or all
+ * particles when brute != 0).  Rows ascending, self included.  s (n values) is
+ * written when non-null.  Returns the total number of entries (offsets always
+ * written, nbr when cap >= total), or -1 on bad input (h_i <= 0, non-finite h_i,
+ * or 2 max h_i >= L). */
+int64_t orc_neighbors_adaptive(int dim, int64_t n, const double* x, double L, const double* h, int prec,
+                               int brute, int64_t* offsets, int32_t* nbr, int64_t cap, double* s_out)
+{
+    if ((dim != 2 && dim != 3) || n < 0) return -1;
+    double hmax = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(h[i] > 0.0) || !isfinite(h[i])) return -1;
+        if (h[i] > hmax) hmax = h[i];
+    }
+    if (n > 0 && !(2.0 * hmax < L)) return -1;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    double* u = (double*)malloc(sizeof(double) * (size_t)dim * nn);
+    float* uf = (float*)malloc(sizeof(float) * (size_t)dim * nn);
+    double* hh = (double*)malloc(sizeof(double) * nn);   /* h_i in the working precision */
+    double* sr = (double*)malloc(sizeof(double) * nn);   /* search radius s_i */
+    double invL = 1.0 / L;
+    float Lf = (float)L, invLf = 1.0f / Lf;
+    for (int64_t i = 0; i < n; ++i) {
+        hh[i] = prec == 1 ? (double)(float)h[i] : h[i];
+        for (int k = 0; k < dim; ++k) {
+            if (prec == 1) {
+                uf[k * n + i] = wrap_f32((float)x[k * n + i], Lf, invLf);
+                u[k * n + i] = (double)uf[k * n + i];
+            } else {
+                u[k * n + i] = wrap_f64(x[k * n + i], L, invL);
+            }
+        }
+    }
+    grid g;
+    grid_build(&g, dim, n, u, L, hmax > 0.0 ? hmax : 0.25 * L, brute);
+
+    /* r_ij^2 < rad^2 in the working precision */
+#define ORC_WITHIN(i_, j_, rad_)                                                           \
+    (prec == 1 ? within_f32(dim, fi_##i_, fj_##j_, Lf, invLf, (float)(rad_) * (float)(rad_)) \
+               : within_f64(dim, di_##i_, dj_##j_, L, invL, (rad_) * (rad_)))
+
+    /* step 1: search radii */
+#pragma omp parallel
+    {
+        int32_t* buf = (int32_t*)malloc(sizeof(int32_t) * nn);
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t k = 0; k < n; ++k) {
+            float fi_a[3] = {0, 0, 0}, fj_b[3] = {0, 0, 0};
+            double di_a[3] = {0, 0, 0}, dj_b[3] = {0, 0, 0};
+            for (int c = 0; c < dim; ++c) {
+                fj_b[c] = uf[c * n + k];
+                dj_b[c] = u[c * n + k];
+            }
+            double sk = hh[k];
+            int64_t nc = grid_candidates(&g, k, buf);
+            for (int64_t a = 0; a < nc; ++a) {
+                int64_t i = buf[a];
+                for (int c = 0; c < dim; ++c) {
+                    fi_a[c] = uf[c * n + i];
+                    di_a[c] = u[c * n + i];
+                }
+                /* is k a neighbour of i under i's own support? */
+                if (ORC_WITHIN(a, b, hh[i]) && hh[i] > sk) sk = hh[i];
+            }
+            sr[k] = sk;
+        }
+        free(buf);
+    }
+
+    /* step 2: search with s_i, keep r_ij < max(h_i, h_j) */
+    int64_t* cnt = (int64_t*)calloc(nn, sizeof(int64_t));
+    offsets[0] = 0;
+    int64_t total = 0;
+    int32_t* idx = NULL;
+    for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1) {
+            for (int64_t i = 0; i < n; ++i) offsets[i + 1] = offsets[i] + cnt[i];
+            total = offsets[n];
+            idx = (int32_t*)malloc(sizeof(int32_t) * (size_t)(total > 0 ? total : 1));
+        }
+#pragma omp parallel
+        {
+            int32_t* buf = (int32_t*)malloc(sizeof(int32_t) * nn);
+#pragma omp for schedule(dynamic, 64)
+            for (int64_t i = 0; i < n; ++i) {
+                float fi_a[3] = {0, 0, 0}, fj_b[3] = {0, 0, 0};
+                double di_a[3] = {0, 0, 0}, dj_b[3] = {0, 0, 0};
+                for (int c = 0; c < dim; ++c) {
+                    fi_a[c] = uf[c * n + i];
+                    di_a[c] = u[c * n + i];
+                }
+                int64_t nc = grid_candidates(&g, i, buf);
+                int64_t c0 = 0, base = pass == 1 ? offsets[i] : 0;
+                for (int64_t a = 0; a < nc; ++a) {
+                    int64_t j = buf[a];
+                    for (int c = 0; c < dim; ++c) {
+                        fj_b[c] = uf[c * n + j];
+                        dj_b[c] = u[c * n + j];
+                    }
+                    double hm = hh[i] > hh[j] ? hh[i] : hh[j];
+                    if (ORC_WITHIN(a, b, sr[i]) && ORC_WITHIN(a, b, hm)) {
+                        if (pass == 1) idx[base + c0] = (int32_t)j;
+                        ++c0;
+                    }
+                }
+                if (pass == 0) cnt[i] = c0;
+                else qsort(idx + base, (size_t)c0, sizeof(int32_t), cmp_i32);
+            }
+            free(buf);
+        }
+    }
+#undef ORC_WITHIN
+    if (nbr && cap >= total && total > 0) memcpy(nbr, idx, sizeof(int32_t) * (size_t)total);
+    if (s_out)
+        for (int64_t i = 0; i < n; ++i) s_out[i] = sr[i];
+    free(idx);
+    free(cnt);
+    grid_free(&g);
+    free(u);
+    free(uf);
+    free(hh);
+    free(sr);
+    return total;
 }
 
 int orc_num_threads(void)
