@@ -13,8 +13,9 @@
  * Conventions shared by every call
  *  - Memory: the library never allocates device memory.  The caller owns the
  *    state, the outputs, the checkpoints and one workspace whose size
- *    sph_workspace_size() reports.  All pointers named "device" point to GPU
- *    memory; "host" pointers to CPU memory.
+ *    sph_workspace_size() reports, or binds the library's static per-device
+ *    workspace with sph_bind_scratch().  All pointers named "device" point to
+ *    GPU memory; "host" pointers to CPU memory.
  *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the default
  *    stream).  Calls enqueue work asynchronously on it unless documented as
  *    synchronous.  Calls on one plan must be ordered (one stream, or the
@@ -257,6 +258,27 @@ sph_status sph_set_graphs(sph_plan* plan, int32_t enable);
  * workspace on one stream; rebinding drops cached graphs and clears the
  * plan's status words and pair counter. */
 sph_status sph_bind(sph_plan* plan, void* workspace, size_t bytes, void* stream);
+
+/* Size in bytes of the static workspace of sph_bind_scratch (64 MiB per device). */
+#define SPH_SCRATCH_BYTES (64ull << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): sph_bind with the library's own static
+ * workspace instead of one the caller allocated.  The workspace is a device array of
+ * SPH_SCRATCH_BYTES bytes that every device the library runs on holds from the library's
+ * load until the process ends; its address on the current device is looked up on the first
+ * call on that device.  The call allocates nothing (no hipMalloc/hipFree, no allocating
+ * library routine); it copies the plan's tables into the array and clears the status words,
+ * the pair counter and the sort's counters with fill kernels, as sph_bind does, so nothing
+ * of an earlier plan's contents is read.  Every later call on the plan then works on that
+ * array and must be made with the same device current (STATE otherwise).  One array per
+ * device is shared by every plan bound to it: binding another plan there makes the calls of
+ * the earlier one fail with STATE until it is bound again, and calls of plans that overlap
+ * on one device race (call it from one thread per device, or order the calls yourself).
+ * sph_bind() of the caller's own workspace ends the plan's use of the array.  Errors:
+ * CAPACITY when sph_workspace_size() exceeds SPH_SCRATCH_BYTES (checked before any device
+ * call), INVALID_ARG for a null plan, DEVICE when the array's address cannot be obtained. */
+sph_status sph_bind_scratch(sph_plan* plan, void* stream);
 
 /* Cell list of the state s (App. B, steps 1-2): every particle is mapped into
  * the box, assigned to its cell, and the particles are counting-sorted by

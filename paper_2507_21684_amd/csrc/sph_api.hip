@@ -4,9 +4,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -115,6 +117,10 @@ struct sph_plan {
     size_t bytes = 0;
     char* ws = nullptr;
     bool bound = false;
+    // bound to the static workspace of device scratch_dev by sph_bind_scratch (-1: the caller's
+    // workspace), as that device's binding number scratch_gen
+    int scratch_dev = -1;
+    uint64_t scratch_gen = 0;
     // per-launch timing (sph_profile_enable)
     int32_t prof = 0;   // bit k: time launches of kernel class k
     struct Ev {
@@ -594,10 +600,38 @@ sph_status check_state(const sph_plan* P, const sph_state* s, const char* what)
     return SPH_OK;
 }
 
+// ---------------------------------------------------------------- static workspace
+// The workspace of sph_bind_scratch: one array per device, held from the library's load to
+// the end of the process.  Host code never uses its name as an address (on the host it is
+// only a stand-in for the symbol): the device address comes from hipGetSymbolAddress, once
+// per device, with that device current.
+static __device__ __align__(256) unsigned char scratch[SPH_SCRATCH_BYTES];
+
+constexpr int kMaxScratchDevices = 64;
+
+struct ScratchSlot {
+    void* ptr = nullptr;             // device address of `scratch` on this device
+    std::atomic<uint64_t> gen{0};    // number of the latest sph_bind_scratch on this device
+};
+
+std::mutex g_scratch_mu;
+ScratchSlot g_scratch[kMaxScratchDevices];
+
 sph_status check_bound(const sph_plan* P)
 {
     if (!P) return fail(SPH_ERR_INVALID_ARG, "plan is null");
     if (!P->bound) return fail(SPH_ERR_STATE, "plan has no workspace bound (call sph_bind)");
+    if (P->scratch_dev >= 0) {
+        int dev = -1;
+        HIP_TRY(hipGetDevice(&dev));
+        if (dev != P->scratch_dev)
+            return fail(SPH_ERR_STATE, "plan is bound to the static workspace of device " +
+                                           std::to_string(P->scratch_dev) + " but device " + std::to_string(dev) +
+                                           " is current");
+        if (g_scratch[dev].gen.load() != P->scratch_gen)
+            return fail(SPH_ERR_STATE,
+                        "the static workspace of this device was bound to another plan since (call sph_bind_scratch again)");
+    }
     return SPH_OK;
 }
 
@@ -1554,6 +1588,7 @@ sph_status sph_bind(sph_plan* P, void* workspace, size_t bytes, void* stream)
     if (((uintptr_t)workspace) % 256 != 0) return fail(SPH_ERR_INVALID_ARG, "workspace not 256-byte aligned");
     hipStream_t st = (hipStream_t)stream;
     P->clear_graphs();          // captured graphs hold addresses inside the old workspace
+    P->scratch_dev = -1;
     P->ws = (char*)workspace;
     HIP_TRY(hipMemcpyAsync(P->ws + P->o_simc, P->h_simc.data(), P->h_simc.size(), hipMemcpyHostToDevice, st));
     if (P->nblk > 0) {
@@ -1586,6 +1621,35 @@ sph_status sph_bind(sph_plan* P, void* workspace, size_t bytes, void* stream)
     // the tables are copied from pageable host memory, which the runtime stages before the
     // copy call returns, so nothing here waits for the device
     P->bound = true;
+    return SPH_OK;
+}
+
+sph_status sph_bind_scratch(sph_plan* P, void* stream)
+{
+    if (!P) return fail(SPH_ERR_INVALID_ARG, "plan is null");
+    if (P->bytes > (size_t)SPH_SCRATCH_BYTES)
+        return fail(SPH_ERR_CAPACITY, "plan needs a workspace of " + std::to_string(P->bytes) +
+                                          " bytes; the static workspace holds " +
+                                          std::to_string((size_t)SPH_SCRATCH_BYTES));
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxScratchDevices) return fail(SPH_ERR_UNSUPPORTED, "device index out of range");
+    void* ptr = nullptr;
+    uint64_t gen = 0;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch[dev].ptr) {
+            HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+            if (!ptr || ((uintptr_t)ptr) % 256 != 0)
+                return fail(SPH_ERR_DEVICE, "static workspace has no 256-byte aligned device address");
+            g_scratch[dev].ptr = ptr;
+        }
+        ptr = g_scratch[dev].ptr;
+        gen = g_scratch[dev].gen.fetch_add(1) + 1;
+    }
+    RC_TRY(sph_bind(P, ptr, (size_t)SPH_SCRATCH_BYTES, stream));
+    P->scratch_dev = dev;
+    P->scratch_gen = gen;
     return SPH_OK;
 }
 

@@ -93,6 +93,8 @@ def lib():
                                     ctypes.POINTER(ctypes.c_int32)]
         L.sph_bind.restype = st
         L.sph_bind.argtypes = [_VP, _VP, ctypes.c_size_t, _VP]
+        L.sph_bind_scratch.restype = st
+        L.sph_bind_scratch.argtypes = [_VP, _VP]
         L.sph_build_cells.restype = st
         L.sph_build_cells.argtypes = [_VP, ctypes.POINTER(SphState), _VP]
         L.sph_neighbors.restype = st
@@ -131,7 +133,11 @@ def exported_symbols() -> List[str]:
             "sph_pair_count", "sph_profile_enable", "sph_profile_read", "sph_last_error", "sph_set_tuning",
             "sph_get_tuning", "sph_rollout_backward", "sph_set_graphs", "sph_density_adjoint", "sph_set_reuse",
             "sph_set_integrator", "sph_set_symplectic", "sph_set_diffusion", "sph_shift",
-            "sph_shift_adjoint"]
+            "sph_shift_adjoint", "sph_bind_scratch"]
+
+
+# Bytes of the library's static per-device workspace (SPH_SCRATCH_BYTES in sph.h).
+SCRATCH_BYTES = 64 << 20
 
 
 KERNEL_CLASSES = ["sort", "build", "sweep", "adjoint", "other"]
@@ -212,7 +218,10 @@ class Plan:
 
     def __init__(self, sims: Sequence[dict], counts: Sequence[int], dtype: str = "f32",
                  max_neighbors: int = 0, tape_depth: int = 8, device: Optional[torch.device] = None,
-                 stream=None, skin=0.0, rebuild_every: int = 1, integrator=None, renormalised_diffusion: bool = False):
+                 stream=None, skin=0.0, rebuild_every: int = 1, integrator=None, renormalised_diffusion: bool = False,
+                 scratch: bool = False):
+        """scratch=True binds the library's static workspace of the current device
+        (sph_bind_scratch) instead of allocating one."""
         L = lib()
         self.dtype = dtype
         self.torch_dtype = torch.float64 if dtype == "f64" else torch.float32
@@ -248,10 +257,22 @@ class Plan:
         self.max_neighbors = int(mn.value)
         self.workspace_bytes = int(size.value)
         self.device = device if device is not None else torch.device("cuda", torch.cuda.current_device())
-        self.workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
-        base = self.workspace.data_ptr()
-        self._ws_ptr = (base + 255) // 256 * 256
-        _check(L.sph_bind(h, self._ws_ptr, self.workspace_bytes, _stream_ptr(stream)))
+        self.scratch = bool(scratch)
+        if self.scratch:
+            self.workspace = None
+            self._ws_ptr = None
+            try:
+                with torch.cuda.device(self.device):
+                    _check(L.sph_bind_scratch(h, _stream_ptr(stream)))
+            except Exception:
+                L.sph_plan_destroy(h)
+                self._h = None
+                raise
+        else:
+            self.workspace = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.workspace.data_ptr()
+            self._ws_ptr = (base + 255) // 256 * 256
+            _check(L.sph_bind(h, self._ws_ptr, self.workspace_bytes, _stream_ptr(stream)))
         self.rebuild_every = 1
         if rebuild_every != 1:
             self.set_reuse(rebuild_every)
@@ -359,6 +380,11 @@ class Plan:
         _check(lib().sph_density_adjoint(self._h, ctypes.byref(s), g.data_ptr(), xbar.data_ptr(),
                                          _stream_ptr(stream)))
         return xbar
+
+    def bind_scratch(self, stream=None):
+        """(Re)bind the plan to the library's static workspace of the current device."""
+        _check(lib().sph_bind_scratch(self._h, _stream_ptr(stream)))
+        self.scratch = True
 
     def set_tuning(self, lanes_fwd: int, lanes_adj: int):
         _check(lib().sph_set_tuning(self._h, int(lanes_fwd), int(lanes_adj)))

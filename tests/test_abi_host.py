@@ -221,3 +221,21 @@ def test_diffusion_setting_reserves_records_in_any_order():
     b = size_after(["symplectic_euler_reuse", "renorm"])
     assert a == b == size_after(["symplectic_euler"]) + (rn - base)
     assert L.lib().sph_set_diffusion(None, 1) != 0
+
+
+def test_scratch_binding_checks_before_any_device_call():
+    """sph_bind_scratch rejects a null plan and a plan larger than the static workspace
+    without touching a device; the binding's constant matches the header's."""
+    src = open(os.path.join(ROOT, "include", "sph.h")).read()
+    m = re.search(r"#define SPH_SCRATCH_BYTES \((\d+)ull << (\d+)\)", src)
+    assert m and int(m.group(1)) << int(m.group(2)) == L.SCRATCH_BYTES
+    assert L.lib().sph_bind_scratch(None, None) == -1
+    spec = SimSpec(3, 32)
+    rc, h = _plan([_p(spec)], [spec.n], 0, 8)
+    assert rc == 0
+    size = ctypes.c_size_t()
+    L.lib().sph_workspace_size(h, ctypes.byref(size))
+    assert size.value > L.SCRATCH_BYTES
+    assert L.lib().sph_bind_scratch(h, None) == -3
+    assert b"static workspace" in L.lib().sph_last_error()
+    L.lib().sph_plan_destroy(h)
