@@ -7,18 +7,24 @@ pass or in one adjoint step; recomputation during the backward pass is done but 
 counted as work.  One benchmark "step" is one pass of the whole job: the forward rollout
 with checkpoints, the loss seed and the checkpointed backward rollout.
 
-Default workload (tgv2d_64k_f32): 2D periodic Taylor-Green, 256^2 = 65536 particles,
-FP32, 64 steps of dt = 0.125 H / c0, checkpoint every 8, loss sum |v_T|^2, gradient with
-respect to the initial state.  Inputs are synthetic (seeded jittered lattice).
+Default workload (batched_512_tgv2d_f32, the largest single-GPU configuration): 512
+independent 2D periodic Taylor-Green simulations in one plan, particle counts log-uniform in
+[256, 16384] (1.96 M particles in all), amplitudes uniform in [0.5, 2], FP32, 32 steps of
+dt = 0.125 H / c0 with a checkpoint every 8, loss sum |v_T|^2, gradient with respect to the
+initial state.  Inputs are synthetic (seeded jittered lattices) and resident on the GPU
+before the timed region.
 
-The JSON line also carries the roofline of the dominant pair kernel (device time from HIP
-events that the library hands to that kernel's launches in the timed region, which hold
-each launch's own start and end), the CPU oracle
-on the host's cores, the batched workload (512 uneven 2D simulations in one plan)
-against the plain path (one plan per simulation, run one after the other), with the
-per-simulation completion latency p50/p99 of both, and the served workload (Poisson
-arrivals of uneven 2D/3D solve-plus-gradient requests under continuous batching) against
-the plain first-come first-served path on the same arrival trace.
+The JSON line carries, for the headline workload: the roofline of its dominant pair kernel
+(device time from HIP events that the library hands to that kernel's launches in the timed
+region, which hold each launch's own start and end); the per-simulation completion latency
+p50/p99 of the batched job against the plain path (one plan per simulation, run one after
+the other); and the CPU oracle timed on a bounded sample on all host threads and on one.
+Legs: the 3D 64^3 and 2D 256^2 fwd+adjoint jobs and the 2D 32^2 FP64 forward job, each
+with its own roofline and oracle baseline; the backward benchmark, the renormalised
+diffusion, particle shifting, the neighbour export, RK4 and symplectic jobs on the 2D 256^2
+state; and the served workload (Poisson arrivals of uneven 2D/3D solve-plus-gradient
+requests under continuous batching) against the plain first-come first-served path on the
+same arrival trace.
 """
 from __future__ import annotations
 
@@ -38,11 +44,12 @@ METRIC = "pair interactions/s fwd+adjoint; batched p50/p99 latency vs plain path
 # Algorithmic FP work per directed pair (FMA = 2 flops; add, mul, division, sqrt, rint = 1),
 # counted from the operations each sweep performs per pair.
 FLOPS_PER_PAIR = {("sweep", 2): 54, ("sweep", 3): 64, ("adjoint", 2): 149, ("adjoint", 3): 178}
-# Vector ALU ceilings of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz = 78.6
-# TFLOP/s for FP32 without packed instructions (the library is built with packed FP32 disabled)
-# and for FP64; the published FP32 figure, 157.3, counts packed FP32.
-PEAK_TFLOPS = {"f32": 78.6, "f64": 78.6}
-PEAK_TFLOPS_PACKED_F32 = 157.3
+# Vector ALU ceilings of MI355X (published): FP32 157.3 TFLOP/s, which counts packed FP32 (two
+# FP32 operations per lane per instruction), and FP64 78.6 TFLOP/s.  The library is built with
+# packed FP32 instructions disabled, which caps its FP32 code at 256 CUs x 4 SIMDs x 16 lanes x
+# 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s; the JSON gives the fraction of that ceiling as well.
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+PEAK_TFLOPS_UNPACKED_F32 = 78.6
 PEAK_HBM_GBS = 8000.0
 STAGE_SKIN = 0.05      # list skin of the multistage legs (stage list reuse)
 
@@ -125,16 +132,88 @@ def count_pairs_schedule(plan, x0, v0, r0, wl):
     return plan.pair_count()
 
 
-def cpu_baseline(wl, host):
-    """The oracle as it stands, on this host's cores, over the same job."""
+def host_info():
+    """Logical CPUs, the CPUs this process may run on, and the CPU model of the host."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": model}
+
+
+def sample_pairs(dev, specs, parts, steps, dtype):
+    """Directed pairs (j != i) of the states n = 0..steps-1 of the listed simulations, counted by
+    the library's exact list builds (one plan of the sample, lists rebuilt every step)."""
+    import numpy as np
+    import torch
+    from paper_2507_21684_amd.lib import Plan
+    plan = Plan([s.params() for s in specs], [s.n for s in specs], dtype, tape_depth=0, device=dev)
+    x, v, r = (torch.tensor(np.concatenate([p[k] for p in parts], axis=-1), device=dev) for k in range(3))
+    plan.pair_count()
+    total = 0
+    for _ in range(steps):
+        plan.step(x, v, r, 1)
+        total += plan.pair_count()
+    assert all(plan.poll() == 0)
+    return total
+
+
+def oracle_seconds(wl, parts, steps, threads=None):
+    """Wall time of the oracle over the listed simulations: `steps` forward steps keeping every
+    state and, for jobs with an adjoint, the adjoint steps back to the initial state (FP64)."""
     from oracle import oracle as O
-    spec = wl.sims[0]
-    p = O.Params(**spec.params())
-    threads = O.num_threads()
-    xd, vd, rd = [a.astype("float64") for a in host]
-    t0 = time.perf_counter()
-    O.rollout(p, xd, vd, rd, wl.steps, 1 if wl.loss == "ke" else 0)
-    return time.perf_counter() - t0, threads
+    spec_parts = parts
+    old = O.num_threads()
+    if threads is not None:
+        O.set_num_threads(threads)
+    try:
+        used = O.num_threads()
+        t0 = time.perf_counter()
+        for spec, (x, v, r) in spec_parts:
+            p = O.Params(**spec.params())
+            xd, vd, rd = (a.astype("float64") for a in (x, v, r))
+            if wl.adjoint:
+                O.rollout(p, xd, vd, rd, steps, 1 if wl.loss == "ke" else 0)
+            else:
+                O.step(p, xd, vd, rd, steps)
+        return time.perf_counter() - t0, used
+    finally:
+        O.set_num_threads(old)
+
+
+def cpu_baseline(dev, wl, parts_all, pick, steps, pick_1t=None, steps_1t=None):
+    """The oracle as it stands on this host's cores over a bounded sample of the workload: the
+    simulations `pick` for `steps` steps (forward and adjoint) with every OpenMP thread, and
+    `pick_1t` for `steps_1t` steps with one thread (None: not run).  Rates are the sample's
+    pair interactions (counted as in the GPU figure) over the oracle's wall time."""
+    factor = 2 if wl.adjoint else 1
+    sel = [(wl.sims[k], parts_all[k]) for k in pick]
+    pairs = factor * sample_pairs(dev, [s for s, _ in sel], [p for _, p in sel], steps, wl.dtype)
+    secs, threads = oracle_seconds(wl, sel, steps)
+    what = "%d simulation%s, %d step%s%s" % (len(sel), "s" if len(sel) > 1 else "", steps, "s" if steps > 1 else "",
+                                           " forward + adjoint" if wl.adjoint else " forward")
+    out = {"value": round(pairs / secs, 1), "unit": "pair interactions/s", "cores": threads, "kind": "oracle",
+           "sample": "%s, FP64, %d OpenMP threads, %.1f s, %d pair interactions" % (what, threads, secs, pairs),
+           **host_info()}
+    if pick_1t is not None:
+        sel1 = [(wl.sims[k], parts_all[k]) for k in pick_1t]
+        pairs1 = factor * sample_pairs(dev, [s for s, _ in sel1], [p for _, p in sel1], steps_1t, wl.dtype)
+        secs1, _ = oracle_seconds(wl, sel1, steps_1t, threads=1)
+        out["value_1thread"] = round(pairs1 / secs1, 1)
+        out["sample_1thread"] = "%d simulation%s, %d step%s, 1 OpenMP thread, %.1f s, %d pair interactions" % (
+            len(sel1), "s" if len(sel1) > 1 else "", steps_1t, "s" if steps_1t > 1 else "", secs1, pairs1)
+    else:
+        out["value_1thread"] = None
+    return out
 
 
 def timed_jobs(plan, x0, v0, r0, wl, reps, classes=None):
@@ -224,7 +303,7 @@ def roofline(prof, dom, wl, per_state, reps, dim, n_particles, lanes=(4, 4)):
            "frac": round(achieved / peak, 4), "traffic": traffic, "mean_launch_us": round(mean_launch_s * 1e6, 2),
            "launches": n_dom, "pairs_per_launch": int(pairs / n_dom)}
     if wl.dtype == "f32":
-        out["frac_of_packed_fp32_peak"] = round(achieved / PEAK_TFLOPS_PACKED_F32, 4)
+        out["frac_of_unpacked_fp32_peak"] = round(achieved / PEAK_TFLOPS_UNPACKED_F32, 4)
     if traffic is not None:
         # the HBM view of the same launches: counted bytes over the live launch time
         gbs = traffic / mean_launch_s / 1e9
@@ -233,32 +312,22 @@ def roofline(prof, dom, wl, per_state, reps, dim, n_particles, lanes=(4, 4)):
     return out
 
 
-def bench_batched(dev, reps):
-    """512 uneven 2D simulations: one batched plan vs one plan per simulation run in turn."""
+def plain_path(dev, wl, x0, v0, r0, skins, R):
+    """The plain path of a batched workload: one plan per simulation (the batch's own list
+    skins and rebuild interval, lanes tuned per plan), run one after the other.  Returns the
+    wall time of all of them and each simulation's completion time (ms) from events after its
+    job."""
     import numpy as np
     import torch
     from paper_2507_21684_amd import autotune
-    from paper_2507_21684_amd.inputs import batched_512_f32, Workload
+    from paper_2507_21684_amd.inputs import Workload
     from paper_2507_21684_amd.lib import Plan
-    wl = batched_512_f32()
-    host, (x0, v0, r0) = packed_inputs(wl, dev)
-    plan = autotune.tune_plan([s.params() for s in wl.sims], [s.n for s in wl.sims], wl.dtype, wl.ckpt_every,
-                              x0, v0, r0, dev)
-    skins, R = list(plan.skins), plan.rebuild_every
-    run_job(plan, x0, v0, r0, wl)
-    work = 2 * count_pairs_schedule(plan, x0, v0, r0, wl)
-    t_batched, _ = timed_jobs(plan, x0, v0, r0, wl, reps, ())
-    t_batched /= reps
-    assert np.all(plan.poll() == 0)
-    del plan
-    # plain path: one plan per simulation, run one after the other (FIFO)
     offs = np.concatenate([[0], np.cumsum([s.n for s in wl.sims])])
     plains = []
     for k, s in enumerate(wl.sims):
-        sub = Workload("one", [s], [wl.seeds[k]], wl.dtype, wl.steps, wl.ckpt_every, True, wl.loss)
+        sub = Workload("one", [s], [wl.seeds[k]], wl.dtype, wl.steps, wl.ckpt_every, wl.adjoint, wl.loss)
         st = (x0[:, offs[k]:offs[k + 1]].contiguous(), v0[:, offs[k]:offs[k + 1]].contiguous(),
               r0[offs[k]:offs[k + 1]].contiguous())
-        # the same list settings as the batch, each simulation in its own plan
         p = Plan([s.params()], [s.n], wl.dtype, tape_depth=wl.ckpt_every, device=dev, skin=skins[k],
                  rebuild_every=R)
         autotune.tune(p, *st)
@@ -276,18 +345,9 @@ def bench_batched(dev, reps):
         evs.append(e)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
-    lat_plain = np.array([ev0.elapsed_time(e) for e in evs])
-    lat_batched = np.full(len(wl.sims), t_batched * 1e3)
-    return {"workload": wl.name, "simulations": len(wl.sims), "particles": int(offs[-1]), "sim_steps": wl.steps,
-            "pair_interactions": work, "unit": "pair interactions/s", "list_rebuild_every": R,
-            "list_skin_range": [round(min(skins), 4), round(max(skins), 4)],
-            "batched": {"value": round(work / t_batched, 1), "ms_per_job": round(t_batched * 1e3, 3),
-                        "p50_ms": round(float(np.percentile(lat_batched, 50)), 3),
-                        "p99_ms": round(float(np.percentile(lat_batched, 99)), 3)},
-            "plain": {"value": round(work / t_plain, 1), "ms_per_job": round(t_plain * 1e3, 3),
-                      "p50_ms": round(float(np.percentile(lat_plain, 50)), 3),
-                      "p99_ms": round(float(np.percentile(lat_plain, 99)), 3)},
-            "speedup": round(t_plain / t_batched, 2)}
+    for p, _, _ in plains:
+        assert all(p.poll() == 0)
+    return t_plain, np.array([ev0.elapsed_time(e) for e in evs])
 
 
 def bench_density_backward(dev, reps=20):
@@ -587,15 +647,96 @@ def bench_serving(dev, count, warmup, load=0.75, budget_gib=96):
             "unit": "pair interactions/s"}
 
 
+def measure_workload(name, dev, reps, warmup):
+    """One workload end to end: its tuned plan (lanes, list skin, rebuild interval), `warmup`
+    untimed jobs, exact pair counts of its trajectory, an untimed pass with every kernel class
+    timed (breakdown and dominant kernel), then `reps` timed jobs in which only the dominant
+    kernel's launches carry HIP events, and that kernel's roofline."""
+    import numpy as np
+    import torch
+    from paper_2507_21684_amd import autotune
+    from paper_2507_21684_amd.lib import Plan
+    wl = workloads()[name]()
+    host, (x0, v0, r0) = packed_inputs(wl, dev)
+    if wl.adjoint:
+        plan = autotune.tune_plan([s.params() for s in wl.sims], [s.n for s in wl.sims], wl.dtype,
+                                  wl.ckpt_every, x0, v0, r0, dev)
+    else:
+        plan = Plan([s.params() for s in wl.sims], [s.n for s in wl.sims], wl.dtype, tape_depth=0, device=dev)
+    lanes = plan.get_tuning()
+    R = plan.rebuild_every
+    for _ in range(warmup):
+        run_job(plan, x0, v0, r0, wl)
+    torch.cuda.synchronize()
+    per_state = count_pairs(plan, x0, v0, r0, wl)
+    K = wl.ckpt_every
+    # pairs of the timed trajectory itself: calls of one rebuild interval each follow the job's
+    # build schedule; single steps give the per-state split (equal to within a few pairs)
+    p_fwd = count_pairs_schedule(plan, x0, v0, r0, wl)
+    scale = p_fwd / max(sum(per_state), 1)
+    per_state = [c * scale for c in per_state]
+    p_adj = p_fwd if wl.adjoint else 0          # adjoint step n runs on forward state n
+    recompute_swept = [n for n in range(wl.steps) if wl.adjoint and (n + 1) % K != 0 and n != wl.steps - 1]
+    p_rec = int(round(sum(per_state[n] for n in recompute_swept)))
+    plan.poll()
+    n_part = int(sum(s.n for s in wl.sims))
+    log("workload %s: %d simulation(s), %d particles, pairs per job %d" % (wl.name, len(wl.sims), n_part,
+                                                                            p_fwd + p_adj))
+    _, prof_all = timed_jobs(plan, x0, v0, r0, wl, 1)
+    breakdown = {k: round(v[0], 3) for k, v in prof_all.items()}
+    dom = max(("build", "sweep", "adjoint") if wl.adjoint else ("build", "sweep"), key=lambda k: prof_all[k][0])
+    elapsed, prof = timed_jobs(plan, x0, v0, r0, wl, reps, [dom])
+    status = plan.poll()
+    assert np.all(status == 0), "device reported non-finite values or neighbour overflow: %s" % status
+    dim = wl.sims[0].dim
+    roof = roofline(prof, dom, wl, per_state, reps, dim, n_part, tuple(lanes) + (R,))
+    ms = 1e3 * elapsed / reps
+    log("%s: timed %d jobs, %.3f ms per job" % (wl.name, reps, ms))
+    config = {"workload": wl.name, "dim": dim, "simulations": len(wl.sims), "particles": n_part,
+              "sim_steps": wl.steps, "ckpt_every": wl.ckpt_every, "adjoint": wl.adjoint, "loss": wl.loss,
+              "pairs_fwd": p_fwd, "pairs_adj": p_adj, "pairs_recompute": p_rec,
+              "lanes_per_particle": list(lanes), "list_rebuild_every": R}
+    if len(wl.sims) > 1:
+        config["list_skin_range"] = [round(min(plan.skins), 4), round(max(plan.skins), 4)]
+    else:
+        config["list_skin"] = round(plan.skin, 4)
+    res = {"workload": wl.name, "value": round((p_fwd + p_adj) * reps / elapsed, 1), "unit": "pair interactions/s",
+           "ms_per_job": round(ms, 3), "timed_jobs": reps, "dtype": wl.dtype, "config": config, "roofline": roof,
+           "kernel_ms_per_job": breakdown}
+    return res, wl, plan, host, (x0, v0, r0)
+
+
+def unpack(wl, host):
+    """Per-simulation (x, v, rho) host arrays of a packed workload state."""
+    import numpy as np
+    offs = np.concatenate([[0], np.cumsum([s.n for s in wl.sims])])
+    return [tuple(np.ascontiguousarray(a[..., offs[k]:offs[k + 1]]) for a in host) for k in range(len(wl.sims))]
+
+
+# Bounded oracle samples per workload: (simulations, steps) with every thread, and with one
+# thread; about 10-30 s of host time in all.
+def cpu_samples(wl):
+    n = len(wl.sims)
+    if n > 1:
+        pick = [int((k + 0.5) * n / 20) for k in range(20)]       # 20 simulations spread over the batch
+        return pick, wl.steps, pick, wl.steps
+    if wl.name == "tgv3d_262k_f32":
+        return [0], 2, None, None                                  # two steps of the full box
+    if wl.name == "tgv2d_64k_f32":
+        return [0], wl.steps, [0], 8
+    return [0], wl.steps, [0], wl.steps
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5, help="timed passes of the whole job")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="tgv2d_64k_f32", choices=sorted(workloads()))
+    ap.add_argument("--workload", default="batched_512_tgv2d_f32", choices=sorted(workloads()))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
-    ap.add_argument("--serving", type=int, default=200, help="requests of the served workload (0 skips it)")
+    ap.add_argument("--no-legs", action="store_true", help="only the headline workload and its plain path")
+    ap.add_argument("--serving", type=int, default=1000, help="requests of the served workload (0 skips it)")
+    ap.add_argument("--serving-warmup", type=int, default=50, help="requests left out of the latency percentiles")
     ap.add_argument("--counter-pass", action="store_true",
                     help="for hardware-counter runs: warm-up and one job of the workload, then a plain "
                          "device copy of 256 MiB (the calibration kernel for byte counters); prints nothing")
@@ -613,107 +754,97 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    wl = workloads()[args.workload]()
-    host, (x0, v0, r0) = packed_inputs(wl, dev)
-    if wl.adjoint:
-        # lanes, list skin and rebuild interval tuned on this state (cached per size bucket)
-        plan = autotune.tune_plan([s.params() for s in wl.sims], [s.n for s in wl.sims], wl.dtype,
-                                  wl.ckpt_every, x0, v0, r0, dev)
-    else:
-        plan = Plan([s.params() for s in wl.sims], [s.n for s in wl.sims], wl.dtype, tape_depth=0, device=dev)
-    lanes = plan.get_tuning()
-    list_skin, list_rebuild = plan.skin, plan.rebuild_every
-
-    for _ in range(args.warmup):
-        run_job(plan, x0, v0, r0, wl)
-    torch.cuda.synchronize()
     if args.counter_pass:
-        run_job(plan, x0, v0, r0, wl)
+        wl = workloads()[args.workload]()
+        host, (x0, v0, r0) = packed_inputs(wl, dev)
+        if wl.adjoint:
+            plan = autotune.tune_plan([s.params() for s in wl.sims], [s.n for s in wl.sims], wl.dtype,
+                                      wl.ckpt_every, x0, v0, r0, dev)
+        else:
+            plan = Plan([s.params() for s in wl.sims], [s.n for s in wl.sims], wl.dtype, tape_depth=0, device=dev)
+        for _ in range(args.warmup + 1):
+            run_job(plan, x0, v0, r0, wl)
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         return
-    per_state = count_pairs(plan, x0, v0, r0, wl)
-    K = wl.ckpt_every
-    # pairs of the timed trajectory itself: calls of one rebuild interval each follow the job's
-    # build schedule; single steps give the per-state split (equal to within a few pairs)
-    p_fwd = count_pairs_schedule(plan, x0, v0, r0, wl)
-    scale = p_fwd / max(sum(per_state), 1)
-    per_state = [c * scale for c in per_state]
-    p_adj = p_fwd if wl.adjoint else 0          # adjoint step n runs on forward state n
-    recompute_swept = [n for n in range(wl.steps) if wl.adjoint and (n + 1) % K != 0 and n != wl.steps - 1]
-    p_rec = int(round(sum(per_state[n] for n in recompute_swept)))
-    plan.poll()
 
-    log("workload %s: %d particles, pairs per job %d" % (wl.name, int(sum(s.n for s in wl.sims)), p_fwd + p_adj))
-    # untimed pass with every kernel class timed: the per-class breakdown and the dominant kernel
-    _, prof_all = timed_jobs(plan, x0, v0, r0, wl, 1)
-    breakdown = {k: round(v[0], 3) for k, v in prof_all.items()}
-    dom = max(("build", "sweep", "adjoint") if wl.adjoint else ("build", "sweep"), key=lambda k: prof_all[k][0])
-    # timed region: only the dominant kernel's launches carry events
-    elapsed, prof = timed_jobs(plan, x0, v0, r0, wl, args.steps, [dom])
-    status = plan.poll()
-    assert np.all(status == 0), "device reported non-finite values or neighbour overflow: %s" % status
-    value = (p_fwd + p_adj) * args.steps / elapsed
-    dim = wl.sims[0].dim
-    roof = roofline(prof, dom, wl, per_state, args.steps, dim, int(sum(s.n for s in wl.sims)),
-                    tuple(lanes) + (list_rebuild,))
+    head, wl, plan, host, (x0, v0, r0) = measure_workload(args.workload, dev, args.steps, args.warmup)
+    parts = unpack(wl, host)
+    skins, R = list(plan.skins), plan.rebuild_every
+    del plan
+    torch.cuda.empty_cache()
 
-    log("timed %d jobs: %.3f ms per job" % (args.steps, 1e3 * elapsed / args.steps))
-    cpu = None
-    if not args.no_cpu_baseline and len(wl.sims) == 1:
-        cdt, threads = cpu_baseline(wl, host)
-        cpu = {"value": round((p_fwd + p_adj) / cdt, 1), "unit": "pair interactions/s", "cores": threads,
-               "kind": "oracle",
-               "sample": "the whole job once: %d forward steps keeping every state + %d adjoint steps, FP64, "
-                         "%d OpenMP threads (%.1f s)" % (wl.steps, wl.steps if wl.adjoint else 0, threads, cdt)}
-
-    batched = None
-    if not args.no_batched and args.workload != "batched_512_tgv2d_f32":
-        del plan
+    latency = None
+    if len(wl.sims) > 1:
+        log("plain path: one plan per simulation, run in turn")
+        t_plain, lat_plain = plain_path(dev, wl, x0, v0, r0, skins, R)
+        work = head["config"]["pairs_fwd"] + head["config"]["pairs_adj"]
+        t_b = head["ms_per_job"]
+        latency = {"batched": {"p50_ms": t_b, "p99_ms": t_b,
+                               "note": "every simulation of the batch completes with the batch's job"},
+                   "plain": {"value": round(work / t_plain, 1), "ms_per_job": round(t_plain * 1e3, 3),
+                             "p50_ms": round(float(np.percentile(lat_plain, 50)), 3),
+                             "p99_ms": round(float(np.percentile(lat_plain, 99)), 3)},
+                   "speedup": round(t_plain * 1e3 / t_b, 2)}
         torch.cuda.empty_cache()
-        log("batched workload")
-        batched = bench_batched(dev, max(1, min(args.steps, 3)))
 
-    dens = renorm = None
-    if args.workload == "tgv2d_64k_f32":
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("CPU oracle baseline of %s" % wl.name)
+        cpu = cpu_baseline(dev, wl, parts, *cpu_samples(wl))
+
+    legs = {}
+    if not args.no_legs:
+        for name in ("tgv3d_262k_f32", "tgv2d_64k_f32", "tgv2d_1k_f64"):
+            if name == args.workload:
+                continue
+            res, lwl, lplan, lhost, _ = measure_workload(name, dev, max(1, min(args.steps, 10)), args.warmup)
+            del lplan
+            torch.cuda.empty_cache()
+            if not args.no_cpu_baseline:
+                log("CPU oracle baseline of %s" % name)
+                res["cpu_baseline"] = cpu_baseline(dev, lwl, unpack(lwl, lhost), *cpu_samples(lwl))
+            legs[name] = res
+
+    extra = {}
+    if not args.no_legs:
+        from paper_2507_21684_amd.inputs import tgv2d_64k_f32
+        w2 = tgv2d_64k_f32()
+        h2, (a0, b0, c0) = packed_inputs(w2, dev)
+        c2 = legs.get("tgv2d_64k_f32", head if wl.name == w2.name else None)
+        lanes2 = tuple(c2["config"]["lanes_per_particle"]) if c2 else (4, 4)
+        skin2 = c2["config"].get("list_skin", 0.26) if c2 else 0.26
+        R2 = c2["config"]["list_rebuild_every"] if c2 else 8
+        pairs2 = c2["config"]["pairs_fwd"] if c2 else None
         log("density backward benchmark")
-        dens = bench_density_backward(dev)
-        log("renormalised diffusion job")
-        renorm = bench_renorm(dev, wl, x0, v0, r0, list_skin, list_rebuild, lanes, 1e3 * elapsed / args.steps,
-                              p_fwd + p_adj)
-
-    rk4 = symp = shift = export = None
-    if args.workload == "tgv2d_64k_f32":
+        extra["density_backward"] = bench_density_backward(dev)
+        if c2:
+            log("renormalised diffusion job")
+            extra["renormalised_diffusion"] = bench_renorm(dev, w2, a0, b0, c0, skin2, R2, lanes2, c2["ms_per_job"],
+                                                           2 * pairs2)
+            log("particle shifting")
+            extra["shift"] = bench_shift(dev, w2, a0, b0, c0, lanes2, pairs2 / w2.steps)
         log("neighbour export")
-        export = bench_export(dev, wl, x0, v0, r0)
-        log("particle shifting")
-        shift = bench_shift(dev, wl, x0, v0, r0, lanes, p_fwd / wl.steps)
+        extra["neighbor_export"] = bench_export(dev, w2, a0, b0, c0)
         log("RK4 job")
-        rk4 = bench_rk4(dev)
+        extra["rk4"] = bench_rk4(dev)
         log("symplectic Euler jobs")
-        symp = bench_symplectic(dev)
+        extra["symplectic"] = bench_symplectic(dev)
 
     served = None
-    if args.serving > 0 and args.workload != "batched_512_tgv2d_f32":
+    if args.serving > 0:
         torch.cuda.empty_cache()
         log("served workload")
-        served = bench_serving(dev, args.serving, max(1, args.serving // 10))
+        served = bench_serving(dev, args.serving, min(args.serving_warmup, args.serving // 2))
 
-    out = {"metric": METRIC, "value": round(value, 1), "unit": "pair interactions/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+    out = {"metric": METRIC, "value": head["value"], "unit": "pair interactions/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_job"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": wl.dtype,
-           "data": "synthetic",
-           "config": {"workload": wl.name, "dim": dim, "simulations": len(wl.sims),
-                      "particles": int(sum(s.n for s in wl.sims)), "sim_steps": wl.steps,
-                      "ckpt_every": wl.ckpt_every, "adjoint": wl.adjoint, "loss": wl.loss,
-                      "pairs_fwd": p_fwd, "pairs_adj": p_adj, "pairs_recompute": p_rec,
-                      "lanes_per_particle": list(lanes), "list_skin": list_skin,
-                      "list_rebuild_every": list_rebuild},
-           "roofline": roof, "kernel_ms_per_job": breakdown, "cpu_baseline": cpu, "batched": batched, "serving": served,
-           "density_backward": dens, "rk4": rk4, "symplectic": symp,
-           "renormalised_diffusion": renorm, "shift": shift, "neighbor_export": export}
+           "data": "synthetic", "config": head["config"], "latency": latency,
+           "roofline": head["roofline"], "kernel_ms_per_job": head["kernel_ms_per_job"], "cpu_baseline": cpu,
+           "legs": legs, "serving": served, **extra}
     print(json.dumps(out), flush=True)
 
 
