@@ -303,6 +303,32 @@ sph_status sph_build_cells(sph_plan* plan, const sph_state* s, void* stream);
 sph_status sph_neighbors(sph_plan* plan, const sph_state* s, int64_t* offsets, int32_t* nbr,
                          int64_t capacity, int64_t* total, void* stream);
 
+/* Neighbour lists with a support radius per particle (Sec. 3.2, "Ensuring
+ * symmetric interactions"; App. B, the search-radius step).  support (device,
+ * N values of the plan's dtype, original order) holds h_i with 0 < h_i <= H,
+ * the simulation's support being the largest any of its particles may have
+ * (cells are sized for it, or for H (1 + skin)).  A particle searching with its
+ * own h_i would miss partners whose larger support reaches it, so:
+ *   1. search radius: s_k = max(h_k, max{h_i : |x_i - x_k| < h_i}), formed on
+ *      the device by an integer atomic maximum on the bit pattern of s_k (no
+ *      floating-point atomics; positive values order like their bits);
+ *   2. each particle searches with s_i and keeps the super-symmetric set
+ *      N(i) = { j : |x_i - x_j| < max(h_i, h_j) }, self included, a symmetric
+ *      relation that every particle's search finds in full.
+ * Predicates as for sph_neighbors, with h^2 = h * h rounded once in the plan's
+ * dtype.  Output as for sph_neighbors: CSR over original indices, each row
+ * ascending, in offsets (device, int64[N+1]) and nbr (device, int32[capacity]),
+ * *total (host) the entry count; search_radius (device, N values, original
+ * order, nullable) receives s_i.  SYNCHRONOUS.  Errors: INVALID_ARG for a null
+ * support or a support outside (0, H] (found on the device, reported after the
+ * synchronisation, no entries written); CAPACITY as for sph_neighbors.  The
+ * status words that sph_poll() reads are not touched (a non-finite position
+ * found by the sort still is).  Steps and sweeps keep using the plan's fixed
+ * support. */
+sph_status sph_neighbors_adaptive(sph_plan* plan, const sph_state* s, const void* support, void* search_radius,
+                                  int64_t* offsets, int32_t* nbr, int64_t capacity, int64_t* total,
+                                  void* stream);
+
 /* One evaluation of the update function f (App. C) at the state s:
  *   drho_i = -rho_i sum_j V_j (v_j - v_i).gW_ij
  *            + delta H c0 sum_j V_j 2 (rho_j - rho_i) (x_ji.gW_ij) / (r^2 + eps H^2)

@@ -1180,17 +1180,11 @@ sph_status do_density_adjoint(sph_plan* P, const sph_state* s, const T* g, T* xb
     return SPH_OK;
 }
 
-template <typename T, int D>
-sph_status do_neighbors(sph_plan* P, const sph_state* s, int64_t* offsets, int32_t* nbr, int64_t capacity,
+// CSR export (original indices, rows ascending) of the lists in slot 0, whose build flagged its
+// faults in the private status words xstat.  SYNCHRONOUS.
+sph_status export_lists(sph_plan* P, const int32_t* xstat, int64_t* offsets, int32_t* nbr, int64_t capacity,
                         int64_t* total, hipStream_t st)
 {
-    RC_TRY((sort_into<T, D>(P, user_state<T, D>(s), nullptr, 0, st)));
-    // this build's overflow goes to private status words, cleared first: status bits left by
-    // earlier calls neither fail the export nor get the export's overflow added to them
-    int32_t* xstat = wsp<int32_t>(P, P->o_status_x);
-    k_fill<int32_t><<<grid_for(P->nsims, 256), 256, 0, st>>>(xstat, P->nsims, 0);
-    LAUNCH_CHECK("fill");
-    RC_TRY((build_lists<T, D>(P, 0, st, true, xstat)));
     const int64_t N = P->N;
     const SlotLayout& L = P->slot[0];
     const int32_t* orig = wsp<int32_t>(P, L.orig);
@@ -1208,6 +1202,10 @@ sph_status do_neighbors(sph_plan* P, const sph_state* s, int64_t* offsets, int32
     HIP_TRY(hipStreamSynchronize(st));
     *total = tot;
     for (int s2 = 0; s2 < P->nsims; ++s2)
+        if (stat[s2] & kFlagBadSupport)
+            return fail(SPH_ERR_INVALID_ARG, "simulation " + std::to_string(s2) +
+                                                 ": a particle's support is not in (0, H]");
+    for (int s2 = 0; s2 < P->nsims; ++s2)
         if (stat[s2] & kFlagOverflow) return fail(SPH_ERR_CAPACITY, "a particle has more neighbours than max_neighbors");
     if (tot > capacity) return fail(SPH_ERR_CAPACITY, "neighbour capacity too small");
     if (N > 0) {
@@ -1217,6 +1215,62 @@ sph_status do_neighbors(sph_plan* P, const sph_state* s, int64_t* offsets, int32
     }
     HIP_TRY(hipStreamSynchronize(st));
     return SPH_OK;
+}
+
+template <typename T, int D>
+sph_status do_neighbors(sph_plan* P, const sph_state* s, int64_t* offsets, int32_t* nbr, int64_t capacity,
+                        int64_t* total, hipStream_t st)
+{
+    RC_TRY((sort_into<T, D>(P, user_state<T, D>(s), nullptr, 0, st)));
+    // this build's overflow goes to private status words, cleared first: status bits left by
+    // earlier calls neither fail the export nor get the export's overflow added to them
+    int32_t* xstat = wsp<int32_t>(P, P->o_status_x);
+    k_fill<int32_t><<<grid_for(P->nsims, 256), 256, 0, st>>>(xstat, P->nsims, 0);
+    LAUNCH_CHECK("fill");
+    RC_TRY((build_lists<T, D>(P, 0, st, true, xstat)));
+    return export_lists(P, xstat, offsets, nbr, capacity, total, st);
+}
+
+// Lists with a support per particle: sort, supports into sorted order (in the sweep output
+// block, free between steps), search radii by atomic maximum, the search with them, the export
+// and the radii in original order.
+template <typename T, int D>
+sph_status do_neighbors_adaptive(sph_plan* P, const sph_state* s, const T* h, T* sr_out, int64_t* offsets,
+                                 int32_t* nbr, int64_t capacity, int64_t* total, hipStream_t st)
+{
+    RC_TRY((sort_into<T, D>(P, user_state<T, D>(s), nullptr, 0, st)));
+    int32_t* xstat = wsp<int32_t>(P, P->o_status_x);
+    k_fill<int32_t><<<grid_for(P->nsims, 256), 256, 0, st>>>(xstat, P->nsims, 0);
+    LAUNCH_CHECK("fill");
+    const int64_t N = P->N;
+    const SlotLayout& L = P->slot[0];
+    P->list_of[0] = 0;
+    if (N > 0) {
+        T* hs = wsp<T>(P, P->o_SB);
+        T* sr = hs + N;
+        const int32_t* orig = wsp<int32_t>(P, L.orig);
+        const int32_t* psim = wsp<int32_t>(P, P->o_psim);
+        const SimConst<T>* simc = wsp<SimConst<T>>(P, P->o_simc);
+        const int32_t* cstart = wsp<int32_t>(P, P->o_cell_start);
+        const int32_t* brank = wsp<int32_t>(P, P->o_blk_rank);
+        const vec4_t<T>* jd0 = wsp<vec4_t<T>>(P, L.jd0);
+        const unsigned g = grid_for(N, 256);
+        k_adapt_prepare<T><<<g, 256, 0, st>>>(N, h, orig, psim, simc, hs, sr, xstat);
+        LAUNCH_CHECK("adapt_prepare");
+        {
+            ProfScope prof(P, st, SPH_KERN_BUILD);
+            k_adapt_radius<T, D><<<g, 256, 0, st>>>(N, jd0, hs, sr, cstart, psim, simc, brank);
+            LAUNCH_CHECK("adapt_radius");
+            k_adapt_build<T, D><<<g, 256, 0, st>>>(N, jd0, hs, sr, cstart, psim, simc, brank, P->width,
+                                                   wsp<int32_t>(P, L.nbr), wsp<int32_t>(P, L.cnt), xstat);
+            LAUNCH_CHECK("adapt_build");
+        }
+        if (sr_out) {
+            k_scatter_orig<T><<<g, 256, 0, st>>>(N, sr, orig, sr_out);
+            LAUNCH_CHECK("scatter_orig");
+        }
+    }
+    return export_lists(P, xstat, offsets, nbr, capacity, total, st);
 }
 
 }  // namespace
@@ -1668,6 +1722,26 @@ sph_status sph_neighbors(sph_plan* P, const sph_state* s, int64_t* offsets, int3
     if (!offsets || !total) return fail(SPH_ERR_INVALID_ARG, "offsets and total must not be null");
     if (capacity < 0 || (capacity > 0 && !nbr)) return fail(SPH_ERR_INVALID_ARG, "bad neighbour buffer");
     return DISPATCH(P, do_neighbors, P, s, offsets, nbr, capacity, total, (hipStream_t)stream);
+}
+
+sph_status sph_neighbors_adaptive(sph_plan* P, const sph_state* s, const void* support, void* search_radius,
+                                  int64_t* offsets, int32_t* nbr, int64_t capacity, int64_t* total, void* stream)
+{
+    RC_TRY(check_bound(P));
+    RC_TRY(check_state(P, s, "state"));
+    if (!offsets || !total) return fail(SPH_ERR_INVALID_ARG, "offsets and total must not be null");
+    if (P->N > 0 && !support) return fail(SPH_ERR_INVALID_ARG, "support must not be null");
+    if (capacity < 0 || (capacity > 0 && !nbr)) return fail(SPH_ERR_INVALID_ARG, "bad neighbour buffer");
+    hipStream_t st = (hipStream_t)stream;
+    if (P->dtype == SPH_F32)
+        return P->dim == 2 ? do_neighbors_adaptive<float, 2>(P, s, (const float*)support, (float*)search_radius,
+                                                             offsets, nbr, capacity, total, st)
+                           : do_neighbors_adaptive<float, 3>(P, s, (const float*)support, (float*)search_radius,
+                                                             offsets, nbr, capacity, total, st);
+    return P->dim == 2 ? do_neighbors_adaptive<double, 2>(P, s, (const double*)support, (double*)search_radius,
+                                                          offsets, nbr, capacity, total, st)
+                       : do_neighbors_adaptive<double, 3>(P, s, (const double*)support, (double*)search_radius,
+                                                          offsets, nbr, capacity, total, st);
 }
 
 sph_status sph_rhs(sph_plan* P, const sph_state* s, void* drho, void* acc, void* rho_sum, void* stream)

@@ -2119,4 +2119,164 @@ __global__ __launch_bounds__(64) void k_export_rows(int64_t N, int32_t width, co
     }
 }
 
+
+// ---------------------------------------------------------------- per-particle support radii
+//
+// Neighbour search when every particle carries its own support h_i (Sec. 3.2, "Ensuring
+// symmetric interactions"; App. B, the search-radius step).  A particle searching with its own
+// support would miss partners whose larger support reaches it, so the search radius s_k
+// starts at h_k and is raised by an integer atomic maximum on its bit pattern (positive IEEE
+// values order like their bits) to h_i for every i that has k as a neighbour under h_i.  Each
+// particle then searches with s_i and keeps the pairs with r_ij < max(h_i, h_j), a symmetric
+// relation: if h_i >= h_j the pair lies within h_i <= s_i, else i is a neighbour of j under h_j
+// and s_i >= h_j.  One thread per particle in sorted order, candidates from the stencil cells
+// (the inner 3^dim when the radius fits half the list radius, on cells sized for that half),
+// predicates with the arithmetic of the fixed-support search.  Supports must lie in (0, H].
+
+constexpr int kFlagBadSupport = 8;  // a support outside (0, H] (status words of this search only)
+
+// Stencil half-width a particle of search radius rad visits.
+template <typename T>
+__device__ __forceinline__ int reach_of(const SimConst<T>& S, T rad)
+{
+    return (S.sub == 2 && rad * rad <= T(0.25) * S.HL2) ? 1 : S.sub;
+}
+
+// Cell coordinates of a wrapped position, as the cell assignment computes them.
+template <typename T, int DIM>
+__device__ __forceinline__ void cell_of_u(const SimConst<T>& S, const T* u, int* cc)
+{
+    cc[0] = cell_coord(u[0], S.cinv, S.nc);
+    cc[1] = cell_coord(u[1], S.cinv, S.nc);
+    cc[2] = (DIM == 3) ? cell_coord(u[2], S.cinv, S.nc) : 0;
+}
+
+// Calls f(j, r2) for every particle j of the cells within `reach` of cell cc, in the canonical
+// order (stencil offset lexicographic in z, y, x, then sorted order inside a cell).
+template <typename T, int DIM, typename F>
+__device__ __forceinline__ void for_each_candidate(const SimConst<T>& S, const int32_t* __restrict__ blk_rank,
+                                                   const int32_t* __restrict__ cell_start,
+                                                   const vec4_t<T>* __restrict__ jd0, const int* cc, const T* ui,
+                                                   int reach, F&& f)
+{
+    const int sw = 2 * S.sub + 1;
+    const int zr = (DIM == 3) ? reach : 0;
+    for (int oz = -zr; oz <= zr; ++oz)
+        for (int oy = -reach; oy <= reach; ++oy)
+            for (int ox = -reach; ox <= reach; ++ox) {
+                const int u = ((DIM == 3 ? (oz + S.sub) * sw : 0) + (oy + S.sub)) * sw + (ox + S.sub);
+                const int code = stencil_entry<DIM>(S, blk_rank, cc, u);
+                const int id = code & kStencilIdMask;
+                T sh[3];
+                sh[0] = T(((code >> kStencilIdBits) & 3) - 1) * S.L;
+                sh[1] = T(((code >> (kStencilIdBits + 2)) & 3) - 1) * S.L;
+                sh[2] = T(((code >> (kStencilIdBits + 4)) & 3) - 1) * S.L;
+                const int j1 = cell_start[id + 1];
+                for (int j = cell_start[id]; j < j1; ++j) {
+                    T uj[3] = {T(0), T(0), T(0)};
+                    unpack_u<T, DIM>(jd0[j], uj);
+                    f(j, dist2_exact<T, DIM>(ui, uj, sh));
+                }
+            }
+}
+
+// s <- max(s, v) on the bits (v > 0).
+__device__ __forceinline__ void raise_to(float* s, float v)
+{
+    atomicMax(reinterpret_cast<int*>(s), __float_as_int(v));
+}
+__device__ __forceinline__ void raise_to(double* s, double v)
+{
+    atomicMax(reinterpret_cast<unsigned long long*>(s), (unsigned long long)__double_as_longlong(v));
+}
+
+// Supports into sorted order, search radii initialised to them, supports checked.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adapt_prepare(int64_t N, const T* __restrict__ h,
+                                                       const int32_t* __restrict__ orig,
+                                                       const int32_t* __restrict__ psim,
+                                                       const SimConst<T>* __restrict__ sims, T* __restrict__ hs,
+                                                       T* __restrict__ sr, int32_t* __restrict__ status)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N) return;
+    const int s = psim[q];
+    T v = h[orig[q]];
+    if (!(v > T(0) && v <= sims[s].H)) {
+        atomicOr(&status[s], kFlagBadSupport);
+        v = sims[s].H;
+    }
+    hs[q] = v;
+    sr[q] = v;
+}
+
+// Search radii: every k within h_i of particle i gets s_k >= h_i.
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_adapt_radius(int64_t N, const vec4_t<T>* __restrict__ jd0,
+                                                      const T* __restrict__ hs, T* __restrict__ sr,
+                                                      const int32_t* __restrict__ cell_start,
+                                                      const int32_t* __restrict__ psim,
+                                                      const SimConst<T>* __restrict__ sims,
+                                                      const int32_t* __restrict__ blk_rank)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const SimConst<T>& S = sims[psim[i]];
+    T ui[3] = {T(0), T(0), T(0)};
+    unpack_u<T, DIM>(jd0[i], ui);
+    int cc[3];
+    cell_of_u<T, DIM>(S, ui, cc);
+    const T hi = hs[i];
+    const T hi2 = hi * hi;
+    for_each_candidate<T, DIM>(S, blk_rank, cell_start, jd0, cc, ui, reach_of(S, hi), [&](int j, T r2) {
+        // only a partner with a smaller support can need its radius raised
+        if (r2 < hi2 && hi > hs[j]) raise_to(sr + j, hi);
+    });
+}
+
+// Lists: the search of radius s_i keeping r_ij < max(h_i, h_j), row-major (width entries per
+// row), counts, overflow flagged.
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_adapt_build(int64_t N, const vec4_t<T>* __restrict__ jd0,
+                                                     const T* __restrict__ hs, const T* __restrict__ sr,
+                                                     const int32_t* __restrict__ cell_start,
+                                                     const int32_t* __restrict__ psim,
+                                                     const SimConst<T>* __restrict__ sims,
+                                                     const int32_t* __restrict__ blk_rank, int32_t width,
+                                                     int32_t* __restrict__ nbr, int32_t* __restrict__ nbr_count,
+                                                     int32_t* __restrict__ status)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int s = psim[i];
+    const SimConst<T>& S = sims[s];
+    T ui[3] = {T(0), T(0), T(0)};
+    unpack_u<T, DIM>(jd0[i], ui);
+    int cc[3];
+    cell_of_u<T, DIM>(S, ui, cc);
+    const T hi = hs[i];
+    int32_t* row = nbr + i * (int64_t)width;
+    int c = 0;
+    for_each_candidate<T, DIM>(S, blk_rank, cell_start, jd0, cc, ui, reach_of(S, sr[i]), [&](int j, T r2) {
+        const T hj = hs[j];
+        const T hm = hi > hj ? hi : hj;
+        const T hm2 = hm * hm;
+        if (r2 < hm2) {
+            if (c < width) row[c] = j;
+            ++c;
+        }
+    });
+    nbr_count[i] = c;
+    if (c > width) atomicOr(&status[s], kFlagOverflow);
+}
+
+// Sorted-order values back to original order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatter_orig(int64_t N, const T* __restrict__ in,
+                                                      const int32_t* __restrict__ orig, T* __restrict__ out)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < N) out[orig[q]] = in[q];
+}
+
 }  // namespace sph

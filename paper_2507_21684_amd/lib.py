@@ -100,6 +100,9 @@ def lib():
         L.sph_neighbors.restype = st
         L.sph_neighbors.argtypes = [_VP, ctypes.POINTER(SphState), _VP, _VP, ctypes.c_int64,
                                     ctypes.POINTER(ctypes.c_int64), _VP]
+        L.sph_neighbors_adaptive.restype = st
+        L.sph_neighbors_adaptive.argtypes = [_VP, ctypes.POINTER(SphState), _VP, _VP, _VP, _VP, ctypes.c_int64,
+                                             ctypes.POINTER(ctypes.c_int64), _VP]
         L.sph_rhs.restype = st
         L.sph_rhs.argtypes = [_VP, ctypes.POINTER(SphState), _VP, _VP, _VP, _VP]
         L.sph_step.restype = st
@@ -133,7 +136,7 @@ def exported_symbols() -> List[str]:
             "sph_pair_count", "sph_profile_enable", "sph_profile_read", "sph_last_error", "sph_set_tuning",
             "sph_get_tuning", "sph_rollout_backward", "sph_set_graphs", "sph_density_adjoint", "sph_set_reuse",
             "sph_set_integrator", "sph_set_symplectic", "sph_set_diffusion", "sph_shift",
-            "sph_shift_adjoint", "sph_bind_scratch"]
+            "sph_shift_adjoint", "sph_bind_scratch", "sph_neighbors_adaptive"]
 
 
 # Bytes of the library's static per-device workspace (SPH_SCRATCH_BYTES in sph.h).
@@ -320,6 +323,24 @@ class Plan:
         _check(lib().sph_neighbors(self._h, ctypes.byref(s), off.data_ptr(), nbr.data_ptr(), int(cap),
                                    ctypes.byref(total), _stream_ptr(stream)))
         return off, nbr[: total.value]
+
+    def neighbors_adaptive(self, x, v, rho, support: torch.Tensor, capacity: Optional[int] = None,
+                           stream=None) -> Tuple[torch.Tensor, torch.Tensor, torch.Tensor]:
+        """Lists with a support per particle (0 < h_i <= H): CSR (offsets int64[N+1], nbr int32[total])
+        over original indices of the pairs with r_ij < max(h_i, h_j), rows ascending, self included,
+        and the search radii s[N]."""
+        s = self.state(x, v, rho)
+        h = support.contiguous()
+        if tuple(h.shape) != (self.N,) or h.dtype != self.torch_dtype or not h.is_cuda:
+            raise ValueError("support must be a %s GPU tensor of shape (%d,)" % (self.torch_dtype, self.N))
+        off = torch.empty(self.N + 1, dtype=torch.int64, device=self.device)
+        cap = capacity if capacity is not None else self.N * self.max_neighbors
+        nbr = torch.empty(max(cap, 1), dtype=torch.int32, device=self.device)
+        sr = torch.empty(self.N, dtype=self.torch_dtype, device=self.device)
+        total = ctypes.c_int64()
+        _check(lib().sph_neighbors_adaptive(self._h, ctypes.byref(s), h.data_ptr(), sr.data_ptr(), off.data_ptr(),
+                                            nbr.data_ptr(), int(cap), ctypes.byref(total), _stream_ptr(stream)))
+        return off, nbr[: total.value], sr
 
     def rhs(self, x, v, rho, rho_sum: bool = True, stream=None):
         """(drho[N], a[dim, N], rho_sum[N] or None), original order."""
