@@ -604,6 +604,13 @@ def bench_serving(dev, count, warmup, load=0.75, budget_gib=96):
             log("serving, plain path: %d of %d requests, %.1f s of service" % (k + 1, count, sum(service)))
     service = np.array(service)
     log("serving, plain path done: mean service %.1f ms" % (service.mean() * 1e3))
+    # where the plain path's time goes: requests by dimension and by size; batching can only
+    # remove the per-launch cost of the requests too small to fill the GPU alone
+    dims = np.array([r.spec.dim for r in base])
+    sizes = np.array([r.spec.n for r in base])
+    split = {"2d_s": round(float(service[dims == 2].sum()), 3), "3d_s": round(float(service[dims == 3].sum()), 3),
+             "ge_256k_particles_s": round(float(service[sizes >= 1 << 18].sum()), 3),
+             "requests_ge_256k_particles": int((sizes >= 1 << 18).sum())}
     rate = load / service.mean()
     trace = [Request(r.rid, r.arrival / rate, r.spec, r.seed, r.steps) for r in base]
     arrivals = np.array([r.arrival for r in trace])
@@ -637,7 +644,8 @@ def bench_serving(dev, count, warmup, load=0.75, budget_gib=96):
                   "failed_requests": int(sum(1 for j in done_b if j.error))}
     return {"workload": "poisson_%d_mixed_2d3d_f32" % count, "requests": count, "warmup_requests": warmup,
             "rate_per_s": round(rate, 3), "load_vs_plain_saturation": load,
-            "mean_plain_service_ms": round(float(service.mean() * 1e3), 3), "pair_interactions": work,
+            "mean_plain_service_ms": round(float(service.mean() * 1e3), 3), "plain_service_split": split,
+            "pair_interactions": work,
             "hbm_budget_gib": budget_gib, **served_info,
             "served": {"value": round(work / makespan_served, 1), "p50_ms": round(ps["p50_ms"], 3),
                        "p99_ms": round(ps["p99_ms"], 3), "makespan_s": round(makespan_served, 3)},

@@ -83,12 +83,25 @@ def cache_key(plan: Plan) -> str:
     return "%s:d%d:%s:n%d" % (_arch(), plan.dim, plan.dtype, bucket)
 
 
+_TABLE: Dict[str, tuple] = {}   # path -> (modification time, table): the file is read once per change
+
+
 def _load() -> Dict[str, list]:
+    path = cache_path()
     try:
-        with open(cache_path()) as f:
-            return json.load(f)
+        mtime = os.stat(path).st_mtime_ns
+    except OSError:
+        return {}
+    hit = _TABLE.get(path)
+    if hit is not None and hit[0] == mtime:
+        return dict(hit[1])
+    try:
+        with open(path) as f:
+            table = json.load(f)
     except (OSError, ValueError):
         return {}
+    _TABLE[path] = (mtime, table)
+    return dict(table)
 
 
 def _store(table: Dict[str, list]) -> None:

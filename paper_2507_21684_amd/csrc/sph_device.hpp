@@ -715,6 +715,7 @@ template <> __device__ __forceinline__ float fast_sqrt<float>(float x) { return 
 template <typename T>
 struct PairConst {
     T L, invL, invH, kG, kH, epsH2, cA, cD, H2;
+    T kGF;  // kG (-56/3): grad W = kGF t^5 (1 + 5 q) x_ij
 };
 
 // Squared distance of a listed pair with the arithmetic of the neighbour predicate (per
@@ -730,7 +731,9 @@ __device__ __forceinline__ T r2_exact(const T* ui, const vec4_t<T>& a, T L, T in
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
         T dk = ui[k] - uj[k];
-        dk = dk - L * rint(dk * invL);
+        // L rint(.) is 0 or +-L exactly, so the fused form rounds once, as the separate
+        // product and difference do
+        dk = fma(-L, rint(dk * invL), dk);
         d[k] = dk;
         T dd = dk * dk;
         r2 = r2 + dd;
@@ -763,6 +766,7 @@ __device__ __forceinline__ PairConst<T> pair_const(const SimConst<T>& S)
     c.cA = S.cA;
     c.cD = S.cD;
     c.H2 = S.H2;
+    c.kGF = S.kG * T(-56.0 / 3.0);
     return c;
 }
 
@@ -980,7 +984,7 @@ __device__ __forceinline__ void fwd_pair(const PairConst<T>& c, const T* vi, T r
     const T t2 = t * t;
     const T t4 = t2 * t2;
     const T t5 = t4 * t;
-    const T gF = c.kG * (T(-56.0 / 3.0) * t5 * (T(1) + T(5) * q));  // grad W = gF x_ij
+    const T gF = c.kGF * (t5 * (T(1) + T(5) * q));  // grad W = gF x_ij
     const T inv = fast_rcp(r2 + c.epsH2);
     const T pij = ue * inv;
     const T cg = ((c.cA * pij - pi) * Vj - pVj) * gF;
