@@ -354,7 +354,9 @@ def bench_density_backward(dev, reps=20):
     """The paper's backward benchmark (Sec. 4.1): one step of the 2D 256^2 FP32 state, the
     summation density of all particles after it, and the gradient of its sum with respect to
     the initial positions.  Reports the forward and backward device times and the backward
-    share of the total (the paper measured 32 % at 64 Ki particles)."""
+    share of the total (the paper measured 32 % at 64 Ki particles), with the backward reusing
+    the sort and lists that the forward built (as the paper's backward reuses the forward's
+    adjacency, and as the autograd path does) and with the backward rebuilding them."""
     import numpy as np
     import torch
     from paper_2507_21684_amd import inputs as I
@@ -368,39 +370,45 @@ def bench_density_backward(dev, reps=20):
     def fwd():
         x, v, r = x0.clone(), v0.clone(), r0.clone()
         plan.step(x, v, r, 1)
+        k0 = plan.retained_lists()
         _, _, rs = plan.rhs(x, v, r, rho_sum=True)
-        return x, v, r, rs
+        return x, v, r, rs, (k0, plan.retained_lists())
 
-    def bwd(x1, v1, r1):
-        xb = plan.density_adjoint(x1, v1, r1, ones)
+    def bwd(x1, v1, r1, kept):
+        xb = plan.density_adjoint(x1, v1, r1, ones, retained=kept[1] if kept else None)
         vb, rb = torch.zeros_like(v0), torch.zeros_like(r0)
-        plan.step_adjoint(x0, v0, r0, xb, vb, rb)
+        plan.step_adjoint(x0, v0, r0, xb, vb, rb, retained=kept[0] if kept else None)
         return xb
 
-    for _ in range(3):
-        bwd(*fwd()[:3])
-    torch.cuda.synchronize()
-    t_f, t_b = [], []
-    for _ in range(reps):
-        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-        e0.record()
-        x1, v1, r1, _ = fwd()
-        e1.record()
-        bwd(x1, v1, r1)
-        e2.record()
+    out = {"workload": "density_backward_tgv2d_64k_f32", "particles": spec.n, "paper_backward_share": 0.32}
+    for name, reuse in (("retained", True), ("rebuilt", False)):
+        for _ in range(3):
+            x1, v1, r1, _, kept = fwd()
+            bwd(x1, v1, r1, kept if reuse else None)
         torch.cuda.synchronize()
-        t_f.append(e0.elapsed_time(e1))
-        t_b.append(e1.elapsed_time(e2))
+        t_f, t_b = [], []
+        for _ in range(reps):
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record()
+            x1, v1, r1, _, kept = fwd()
+            e1.record()
+            bwd(x1, v1, r1, kept if reuse else None)
+            e2.record()
+            torch.cuda.synchronize()
+            t_f.append(e0.elapsed_time(e1))
+            t_b.append(e1.elapsed_time(e2))
+        tf, tb = float(np.median(t_f)), float(np.median(t_b))
+        out[name] = {"forward_ms": round(tf, 4), "backward_ms": round(tb, 4), "backward_share": round(tb / (tf + tb), 3)}
     plan.pair_count()
     fwd()
     pairs = plan.pair_count()          # two list builds: the step's state and the state after it
-    tf, tb = float(np.median(t_f)), float(np.median(t_b))
-    return {"workload": "density_backward_tgv2d_64k_f32", "particles": spec.n,
-            "forward_ms": round(tf, 4), "backward_ms": round(tb, 4),
-            "backward_share": round(tb / (tf + tb), 3), "paper_backward_share": 0.32,
-            "pair_interactions_per_s": round(2 * pairs / ((tf + tb) * 1e-3), 1),
-            "note": "forward = one step + summation density (2 list builds); backward = density VJP + step VJP "
-                    "(2 list builds); median of %d on events around each phase" % reps}
+    r = out["retained"]
+    out.update({"forward_ms": r["forward_ms"], "backward_ms": r["backward_ms"], "backward_share": r["backward_share"],
+                "pair_interactions_per_s": round(2 * pairs / ((r["forward_ms"] + r["backward_ms"]) * 1e-3), 1),
+                "note": "forward = one step + summation density (2 sorts and list builds); backward = density VJP "
+                        "+ step VJP, on the forward's retained lists ('retained') or rebuilding both ('rebuilt'); "
+                        "median of %d on events around each phase" % reps})
+    return out
 
 
 def bench_rk4(dev, reps=3):
@@ -572,6 +580,54 @@ def bench_export(dev, wl, x0, v0, r0, reps=20):
     return {"workload": wl.name + "_neighbor_export", "entries": total, "pairs": total - n,
             "ms_per_call": round(t * 1e3, 4), "csr_bytes": nbytes, "csr_gbs": round(nbytes / t / 1e9, 1),
             "note": "one synchronous sph_neighbors call: sort, exact list build, CSR export; wall time"}
+
+
+def bench_graphs(dev, name, skins, R, lanes, reps=5):
+    """One workload's job with every library call issued directly and as cached executable HIP
+    graphs (sph_set_graphs): fixed state, checkpoint and cotangent buffers, so the graphs are
+    captured once; the same plan settings as the timed job.  Wall time per job, median of reps
+    after a warm-up job."""
+    import numpy as np
+    import torch
+    from paper_2507_21684_amd.lib import Plan
+    wl = workloads()[name]()
+    _, (x0, v0, r0) = packed_inputs(wl, dev)
+    plan = Plan([s.params() for s in wl.sims], [s.n for s in wl.sims], wl.dtype, tape_depth=wl.ckpt_every,
+                device=dev, skin=skins, rebuild_every=R)
+    plan.set_tuning(*lanes)
+    T, K = wl.steps, wl.ckpt_every
+    x, v, r = plan.empty_state()
+    ck = [plan.empty_state() for _ in range((T + K - 1) // K)]
+    gx, gv, gr = torch.empty_like(x), torch.empty_like(v), torch.empty_like(r)
+    masses = plan_masses(plan, wl, v0) if wl.loss == "ke" else None
+
+    def job():
+        x.copy_(x0)
+        v.copy_(v0)
+        r.copy_(r0)
+        plan.step(x, v, r, T, ck, K)
+        gx.zero_()
+        gv.copy_(masses * v if masses is not None else 2.0 * v)
+        gr.zero_()
+        plan.rollout_backward(ck, T, K, gx, gv, gr)
+
+    out = {"workload": name}
+    for mode in ("direct", "graphs"):
+        plan.set_graphs(mode == "graphs")
+        job()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            job()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        out[mode + "_ms"] = round(float(np.median(times)) * 1e3, 3)
+        assert all(plan.poll() == 0)
+    plan.set_graphs(False)
+    out["speedup"] = round(out["direct_ms"] / out["graphs_ms"], 3)
+    out["note"] = "wall time per job, median of %d; the direct and graph paths give bitwise the same results" % reps
+    return out
 
 
 def log(msg):
@@ -840,6 +896,11 @@ def main():
         extra["rk4"] = bench_rk4(dev)
         log("symplectic Euler jobs")
         extra["symplectic"] = bench_symplectic(dev)
+        log("graph mode")
+        graphs = [bench_graphs(dev, wl.name, skins, R, tuple(head["config"]["lanes_per_particle"]))]
+        if c2 and wl.name != w2.name:
+            graphs.append(bench_graphs(dev, w2.name, skin2, R2, lanes2))
+        extra["graph_mode"] = graphs
 
     served = None
     if args.serving > 0:

@@ -393,6 +393,26 @@ sph_status sph_rollout_backward(sph_plan* plan, const sph_state* ckpt, int32_t n
 sph_status sph_density_adjoint(sph_plan* plan, const sph_state* s, const void* rho_sum_bar, void* x_bar,
                                void* stream);
 
+/* Retained neighbour lists (the paper's backward reuses the adjacency that the forward pass
+ * built, Sec. 3.2 and Sec. 4.1).  sph_rhs and semi-implicit Euler sph_step calls keep, in one
+ * workspace slot, the sorted copy and the neighbour lists of their INPUT state (sph_rhs in the
+ * last slot, sph_step in slot 0).  Every later write of that slot (any call that sorts into it,
+ * a step's list-reusing sweep, a graph replay) gives the slot a new generation number.
+ * sph_retained_lists (host out-parameters) returns the slot and generation that the last such
+ * call left, or slot -1 when it is gone (or the call was a Runge-Kutta or symplectic step).
+ * The *_retained variants of the step and density adjoints take that pair: while the slot still
+ * has that generation they skip the sort and the list build and work on the retained copy, as
+ * the adjoint of the call that built it; otherwise they do exactly what sph_step_adjoint and
+ * sph_density_adjoint do with s.  Results are bitwise those of the plain calls on the state the
+ * retaining call received.  The caller guarantees that s is that state (autograd saves it).
+ * sph_step_adjoint_retained is for one-step calls of the default integrator (other schemes fall
+ * back to the plain call). */
+sph_status sph_retained_lists(const sph_plan* plan, int32_t* slot, uint64_t* generation);
+sph_status sph_step_adjoint_retained(sph_plan* plan, const sph_state* s_n, sph_state* cot, int32_t slot,
+                                     uint64_t generation, void* stream);
+sph_status sph_density_adjoint_retained(sph_plan* plan, const sph_state* s, const void* rho_sum_bar, void* x_bar,
+                                        int32_t slot, uint64_t generation, void* stream);
+
 /* Copy the per-simulation status words (host int32[nsims], SPH_FLAG_* bits)
  * and clear them.  SYNCHRONOUS. */
 sph_status sph_poll(sph_plan* plan, int32_t* per_sim_status, void* stream);

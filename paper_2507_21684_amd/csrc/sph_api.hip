@@ -113,6 +113,23 @@ struct sph_plan {
     size_t o_jdA2 = 0, o_jdB2 = 0;
     int adj_buf = 0, adj_ready = -1;
     std::vector<SlotLayout> slot;
+    // Every write of a slot's sorted state or lists gives the slot a new generation number; the
+    // last sph_rhs or sph_step call records the slot holding the sort and lists of its input
+    // state, which the retained adjoint calls reuse while that slot keeps its generation.
+    std::vector<uint64_t> slot_gen;
+    uint64_t gen_counter = 0;
+    int32_t kept_slot = -1;
+    uint64_t kept_gen = 0;
+    void touch(int sl) { slot_gen[(size_t)sl] = ++gen_counter; }
+    void touch_all()
+    {
+        for (size_t k = 0; k < slot_gen.size(); ++k) slot_gen[k] = ++gen_counter;
+    }
+    void keep(int sl)
+    {
+        kept_slot = sl;
+        kept_gen = sl >= 0 ? slot_gen[(size_t)sl] : 0;
+    }
     int64_t nparts = 0, nparts64 = 0;
     size_t bytes = 0;
     char* ws = nullptr;
@@ -138,6 +155,7 @@ struct sph_plan {
         hipGraph_t graph;
         hipGraphExec_t exec;
         uint64_t used;
+        int32_t kept_slot;  // slot whose retained sort the captured call leaves valid (-1: none)
     };
     bool graphs = false;
     std::vector<GraphEntry> gcache;
@@ -335,6 +353,7 @@ template <typename T, int D>
 sph_status sort_into(sph_plan* P, StatePtrs<T, D> src, const int32_t* orig_in, int slot, hipStream_t st,
                      bool assigned = false)
 {
+    P->touch(slot);
     const int64_t N = P->N;
     if (N == 0) return SPH_OK;
     const SlotLayout& L = P->slot[slot];
@@ -443,6 +462,7 @@ sph_status sweep(sph_plan* P, int slot, T* drho, T* acc, T* rhosum, hipStream_t 
     NextSlot<T> ns{nullptr, nullptr, nullptr, nullptr};
     StatePtrs<T, D> dst = ws_state<T, D>(P, P->o_SB);
     if (next_slot >= 0) {
+        P->touch(next_slot);
         const SlotLayout& N2 = P->slot[next_slot];
         dst = ws_state<T, D>(P, N2.SA);
         ns = NextSlot<T>{wsp<vec4_t<T>>(P, N2.jd0), wsp<vec4_t<T>>(P, N2.jd1), wsp<int32_t>(P, N2.orig),
@@ -707,9 +727,12 @@ sph_status do_build_cells(sph_plan* P, const sph_state* s, hipStream_t st)
 template <typename T, int D>
 sph_status do_rhs(sph_plan* P, const sph_state* s, void* drho, void* acc, void* rhosum, hipStream_t st)
 {
-    RC_TRY((sort_into<T, D>(P, user_state<T, D>(s), nullptr, 0, st)));
-    RC_TRY((build_lists<T, D>(P, 0, st)));
-    return sweep<T, D, kModeRhs>(P, 0, (T*)drho, (T*)acc, (T*)rhosum, st);
+    // the last slot, so that a one-step call's sort of its input (slot 0) stays retained too
+    const int sl = P->nslots - 1;
+    RC_TRY((sort_into<T, D>(P, user_state<T, D>(s), nullptr, sl, st)));
+    RC_TRY((build_lists<T, D>(P, sl, st)));
+    P->keep(sl);
+    return sweep<T, D, kModeRhs>(P, sl, (T*)drho, (T*)acc, (T*)rhosum, st);
 }
 
 // nsteps forward steps from `src` (original order).  Without a tape, steps alternate between
@@ -729,6 +752,7 @@ sph_status run_steps(sph_plan* P, StatePtrs<T, D> src, int32_t nsteps, bool tape
         const int cur = tape ? t : (t & 1);
         if (t % R == 0) {
             if (t == 0) RC_TRY((sort_into<T, D>(P, src, nullptr, cur, st)));
+            if (t == 0) P->keep(cur);  // the input state's sort; later writes of the slot retire it
             else
                 RC_TRY((sort_into<T, D>(P, ws_state<T, D>(P, P->o_SB), wsp<int32_t>(P, P->slot[slot].orig), cur, st,
                                         true)));
@@ -799,6 +823,7 @@ sph_status stage_into_slot0(sph_plan* P, StatePtrs<T, D> w, bool first, hipStrea
         RC_TRY((sort_into<T, D>(P, w, nullptr, 0, st)));
         return build_lists<T, D>(P, 0, st);
     }
+    P->touch(0);
     if (P->N == 0) return SPH_OK;
     const SlotLayout& L = P->slot[0];
     ProfScope prof(P, st, SPH_KERN_SORT);
@@ -983,6 +1008,7 @@ sph_status do_step(sph_plan* P, sph_state* s, int32_t nsteps, const sph_state* c
 {
     if (nsteps == 0) return SPH_OK;
     StatePtrs<T, D> user = user_state<T, D>(s);
+    P->keep(-1);
     if (P->symplectic) {
         // with re-use the predictor's rates are evaluated afresh at the first step and at every
         // checkpoint, so that each checkpoint segment can be recomputed on its own
@@ -1106,6 +1132,9 @@ sph_status run_graphed(sph_plan* P, std::vector<uintptr_t> key, hipStream_t st, 
         if (g.key == key) {
             g.used = ++P->gclock;
             HIP_TRY(hipGraphLaunch(g.exec, st));
+            // the replay rewrites slots without the host bookkeeping of a direct call
+            P->touch_all();
+            if (g.kept_slot >= 0) P->keep(g.kept_slot);
             return SPH_OK;
         }
     }
@@ -1134,7 +1163,11 @@ sph_status run_graphed(sph_plan* P, std::vector<uintptr_t> key, hipStream_t st, 
         (void)hipGraphDestroy(lru->graph);
         P->gcache.erase(lru);
     }
-    P->gcache.push_back({std::move(key), graph, exec, ++P->gclock});
+    // a step call leaves its input's sort retained (when valid at the end of the call)
+    const int32_t kept = (key[0] == 1 && P->kept_slot >= 0 && P->slot_gen[(size_t)P->kept_slot] == P->kept_gen)
+                             ? P->kept_slot
+                             : -1;
+    P->gcache.push_back({std::move(key), graph, exec, ++P->gclock, kept});
     HIP_TRY(hipGraphLaunch(exec, st));
     return SPH_OK;
 }
@@ -1161,12 +1194,17 @@ void launch_density_adj(sph_plan* P, const SlotLayout& L, const T* gs, T* xbar, 
 // Summation-density VJP of the state s: sort, lists, the cotangent gathered into sorted
 // order (adjoint scratch), then the pair sweep writing xbar in original order.
 template <typename T, int D>
-sph_status do_density_adjoint(sph_plan* P, const sph_state* s, const T* g, T* xbar, hipStream_t st)
+sph_status do_density_adjoint(sph_plan* P, const sph_state* s, const T* g, T* xbar, hipStream_t st,
+                              int kept = -1)
 {
     if (P->N == 0) return SPH_OK;
-    RC_TRY((sort_into<T, D>(P, user_state<T, D>(s), nullptr, 0, st)));
-    RC_TRY((build_lists<T, D>(P, 0, st)));
-    const SlotLayout& L = P->slot[0];
+    int sl = kept;
+    if (sl < 0) {
+        sl = 0;
+        RC_TRY((sort_into<T, D>(P, user_state<T, D>(s), nullptr, 0, st)));
+        RC_TRY((build_lists<T, D>(P, 0, st)));
+    }
+    const SlotLayout& L = P->slot[sl];
     T* gs = wsp<T>(P, P->o_jdA);
     ProfScope prof(P, st, SPH_KERN_ADJOINT);
     k_gather_sorted<T><<<grid_for(P->N, 256), 256, 0, st>>>(P->N, g, wsp<int32_t>(P, L.orig), gs);
@@ -1447,6 +1485,7 @@ sph_status sph_plan_create(const sph_params* sims, int32_t nsims, const int64_t*
     P->o_uref = take(V4 * N);
     P->slot.resize((size_t)P->nslots);
     P->list_of.assign((size_t)P->nslots, 0);
+    P->slot_gen.assign((size_t)P->nslots, 0);
     for (int k = 0; k < P->nslots; ++k) {
         SlotLayout& L = P->slot[k];
         L.SA = take(T * N * (2 * d + 1));
@@ -1781,6 +1820,56 @@ sph_status sph_step_adjoint(sph_plan* P, const sph_state* s_n, sph_state* cot, v
     RC_TRY(check_state(P, cot, "cotangent"));
     P->adj_ready = -1;
     return DISPATCH(P, do_step_adjoint, P, s_n, cot, (hipStream_t)stream);
+}
+
+sph_status sph_retained_lists(const sph_plan* P, int32_t* slot, uint64_t* generation)
+{
+    if (!P || !slot || !generation) return fail(SPH_ERR_INVALID_ARG, "null argument");
+    const bool valid = P->kept_slot >= 0 && P->slot_gen[(size_t)P->kept_slot] == P->kept_gen;
+    *slot = valid ? P->kept_slot : -1;
+    *generation = valid ? P->kept_gen : 0;
+    return SPH_OK;
+}
+
+namespace {
+// The retained slot when (slot, generation) still names it, else -1.
+int retained(const sph_plan* P, int32_t slot, uint64_t generation)
+{
+    if (slot < 0 || slot >= P->nslots) return -1;
+    return P->slot_gen[(size_t)slot] == generation && generation != 0 ? slot : -1;
+}
+}  // namespace
+
+sph_status sph_step_adjoint_retained(sph_plan* P, const sph_state* s_n, sph_state* cot, int32_t slot,
+                                     uint64_t generation, void* stream)
+{
+    RC_TRY(check_bound(P));
+    RC_TRY(check_state(P, s_n, "state"));
+    RC_TRY(check_state(P, cot, "cotangent"));
+    P->adj_ready = -1;
+    const int sl = retained(P, slot, generation);
+    if (sl < 0 || P->symplectic || P->rk_stages > 0)
+        return DISPATCH(P, do_step_adjoint, P, s_n, cot, (hipStream_t)stream);
+    if (P->dtype == SPH_F32)
+        return P->dim == 2 ? adjoint<float, 2>(P, sl, user_state<float, 2>(cot), (hipStream_t)stream)
+                           : adjoint<float, 3>(P, sl, user_state<float, 3>(cot), (hipStream_t)stream);
+    return P->dim == 2 ? adjoint<double, 2>(P, sl, user_state<double, 2>(cot), (hipStream_t)stream)
+                       : adjoint<double, 3>(P, sl, user_state<double, 3>(cot), (hipStream_t)stream);
+}
+
+sph_status sph_density_adjoint_retained(sph_plan* P, const sph_state* s, const void* rho_sum_bar, void* x_bar,
+                                        int32_t slot, uint64_t generation, void* stream)
+{
+    RC_TRY(check_bound(P));
+    RC_TRY(check_state(P, s, "state"));
+    if (P->N > 0 && (!rho_sum_bar || !x_bar)) return fail(SPH_ERR_INVALID_ARG, "rho_sum_bar and x_bar must not be null");
+    const int sl = retained(P, slot, generation);
+    hipStream_t st = (hipStream_t)stream;
+    if (P->dtype == SPH_F32)
+        return P->dim == 2 ? do_density_adjoint<float, 2>(P, s, (const float*)rho_sum_bar, (float*)x_bar, st, sl)
+                           : do_density_adjoint<float, 3>(P, s, (const float*)rho_sum_bar, (float*)x_bar, st, sl);
+    return P->dim == 2 ? do_density_adjoint<double, 2>(P, s, (const double*)rho_sum_bar, (double*)x_bar, st, sl)
+                       : do_density_adjoint<double, 3>(P, s, (const double*)rho_sum_bar, (double*)x_bar, st, sl);
 }
 
 sph_status sph_density_adjoint(sph_plan* P, const sph_state* s, const void* rho_sum_bar, void* x_bar, void* stream)

@@ -193,6 +193,13 @@ __device__ __forceinline__ T dist2_exact(const T* ui, const T* uj, const T* sh)
     return r2;
 }
 
+// FP32 sweeps use the hardware reciprocal and square root (about 1 ulp); FP64 keeps IEEE
+// division and square root.
+template <typename T> __device__ __forceinline__ T fast_rcp(T x) { return T(1) / x; }
+template <> __device__ __forceinline__ float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <typename T> __device__ __forceinline__ T fast_sqrt(T x) { return sqrt(x); }
+template <> __device__ __forceinline__ float fast_sqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 template <typename T>
 __device__ __forceinline__ T tait(const SimConst<T>& S, T rho)
 {
@@ -414,7 +421,7 @@ __global__ __launch_bounds__(256) void k_order_gather(int64_t N, const int32_t* 
     const T rho = src.rho[p];
     dst.rho[d] = rho;
     orig_out[d] = op;
-    const T V = S.m / rho;
+    const T V = S.m * fast_rcp(rho);
     const T pV = tait(S, rho) * V;
     vec4_t<T> a, b;
     if (DIM == 3) {
@@ -456,7 +463,7 @@ __global__ __launch_bounds__(256) void k_repack(int64_t N, const int32_t* __rest
     }
     const T rho = src.rho[p];
     dst.rho[d] = rho;
-    const T V = S.m / rho;
+    const T V = S.m * fast_rcp(rho);
     const T pV = tait(S, rho) * V;
     vec4_t<T> a, b;
     if (DIM == 3) {
@@ -704,12 +711,7 @@ __device__ __forceinline__ void load_entries_clamped(const int32_t* __restrict__
     }
 }
 
-// FP32 sweeps use the hardware reciprocal and square root (about 1 ulp); FP64 keeps IEEE
-// division and square root.
-template <typename T> __device__ __forceinline__ T fast_rcp(T x) { return T(1) / x; }
-template <> __device__ __forceinline__ float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-template <typename T> __device__ __forceinline__ T fast_sqrt(T x) { return sqrt(x); }
-template <> __device__ __forceinline__ float fast_sqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 
 // Per-simulation constants the pair loops use, held in registers.
 template <typename T>
@@ -1132,7 +1134,7 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
         rdg = combine_leaves<LPP>(tmp);
     }
     if (r == 0) {
-    const T invrho = T(1) / rhoi;
+    const T invrho = fast_rcp(rhoi);
     T a[3];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) a[k] = ax[k] * invrho;
@@ -1165,7 +1167,7 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
             T u[3] = {0, 0, 0};
 #pragma unroll
             for (int k = 0; k < DIM; ++k) u[k] = wrap_pos(isfinite(xn[k]) ? xn[k] : T(0), S.L, S.invL);
-            const T V = S.m / rhon;
+            const T V = S.m * fast_rcp(rhon);
             const T pV = tait(S, rhon) * V;
             vec4_t<T> pa, pb;
             if (DIM == 3) {
@@ -1267,23 +1269,14 @@ __global__ __launch_bounds__(256) void k_density_adj(int64_t N, int32_t width, c
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (m0 + u >= mcount) continue;
-            T e_[3];
-            if (filter && !(r2_exact<T, DIM>(ui, a[u], c.L, c.invL, e_) < c.H2)) continue;
-            T uj[3] = {0, 0, 0}, d[3] = {0, 0, 0};
-            unpack_u<T, DIM>(a[u], uj);
-            T r2 = 0;
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) {
-                T dd = ui[k] - uj[k];
-                dd -= c.L * rint(dd * c.invL);
-                d[k] = dd;
-                r2 += dd * dd;
-            }
+            T d[3] = {0, 0, 0};
+            const T r2 = r2_exact<T, DIM>(ui, a[u], c.L, c.invL, d);
+            if (filter && !(r2 < c.H2)) continue;
             const T q = fast_sqrt(r2) * c.invH;
             const T tt = T(1) - q;
             const T t2 = tt * tt;
             const T t5 = t2 * t2 * tt;
-            const T gF = c.kG * (T(-56.0 / 3.0) * t5 * (T(1) + T(5) * q));
+            const T gF = c.kGF * (t5 * (T(1) + T(5) * q));
             const T w = (gi + gj[u]) * gF;
 #pragma unroll
             for (int k = 0; k < DIM; ++k) acc[u % NQ][k] += w * d[k];
@@ -1495,7 +1488,7 @@ __global__ __launch_bounds__(256) void k_adj_prologue(int64_t N, const int32_t* 
     vec4_t<T> b;
     b.x = rho;
     b.y = tait(S, rho);
-    b.z = T(1) / rho;
+    b.z = fast_rcp(rho);
     b.w = tait_slope(S, rho);
     jdB[q] = b;
 }
@@ -1535,41 +1528,37 @@ struct AdjNbr {
 // (c = -delta H c0) adds, for q = rbar_k V_j - rbar_j V_k and s = G_k + G_j with the
 // gradients held fixed: gx += c q Jg s, Gbar += c q gF e, gr += (V_k / rho_k) c rbar_j gF s.e.
 template <typename T, int DIM, bool RENORM>
-__device__ __forceinline__ void adj_pair(const PairConst<T>& c, const T* uk, const T* vk, const T* ak, T rbk, T Vk,
-                                         T rhok, T pk, T irk, T dpk, const T* Gk, const AdjNbr<T>& nb,
+__device__ __forceinline__ void adj_pair(const PairConst<T>& c, const T* vk, const T* ak, T rbk, T Vk, T rhok, T pk,
+                                         T irk, T dpk, const T* Gk, const AdjNbr<T>& nb, const T* e, T r2,
                                          AdjAcc<T, DIM>& acc)
 {
-    T uj[3], vj[3], aj[3];
+    T vj[3], aj[3];
     T Vj, rbj;
     if (DIM == 3) {
-        uj[0] = nb.a.x; uj[1] = nb.a.y; uj[2] = nb.a.z; Vj = nb.a.w;
+        Vj = nb.a.w;
         vj[0] = nb.b.x; vj[1] = nb.b.y; vj[2] = nb.b.z;
         aj[0] = nb.A.x; aj[1] = nb.A.y; aj[2] = nb.A.z; rbj = nb.A.w;
     } else {
-        uj[0] = nb.a.x; uj[1] = nb.a.y; Vj = nb.a.z;
+        Vj = nb.a.z;
         vj[0] = nb.b.x; vj[1] = nb.b.y;
         aj[0] = nb.A.x; aj[1] = nb.A.y; rbj = nb.A.z;
     }
     const T rhoj = nb.B.x, pj = nb.B.y, irj = nb.B.z;
     const T cA = c.cA, cD = c.cD;
-    T e[3], u[3];
-    T r2 = 0, ue = 0, ake = 0, aje = 0;
+    T u[3];
+    T ue = 0, ake = 0, aje = 0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-        T dd = uk[k] - uj[k];
-        dd -= c.L * rint(dd * c.invL);
-        e[k] = dd;
         u[k] = vk[k] - vj[k];
-        r2 += dd * dd;
-        ue += u[k] * dd;
-        ake += ak[k] * dd;
-        aje += aj[k] * dd;
+        ue += u[k] * e[k];
+        ake += ak[k] * e[k];
+        aje += aj[k] * e[k];
     }
     const T q = fast_sqrt(r2) * c.invH;
     const T t = T(1) - q;
     const T t2 = t * t;
     const T t4 = t2 * t2;
-    const T gF = c.kG * (T(-56.0 / 3.0) * t4 * t * (T(1) + T(5) * q));  // grad W = gF e
+    const T gF = c.kGF * (t4 * t * (T(1) + T(5) * q));  // grad W = gF e
     const T hF = c.kH * t4;                                              // Hessian: gF I + hF e e^T
     const T inv = fast_rcp(r2 + c.epsH2);
     const T pij = ue * inv;
@@ -1691,9 +1680,10 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (m0 + u >= mcount) continue;
-            T e_[3];
-            if (filter && !(r2_exact<T, DIM>(uk, nb[u].a, c.L, c.invL, e_) < c.H2)) continue;
-            adj_pair<T, DIM, RENORM>(c, uk, vk, ak, rbk, Vk, rhok, pk, irk, dpk, Gk, nb[u], acc[u % NQ]);
+            T e[3];
+            const T r2 = r2_exact<T, DIM>(uk, nb[u].a, c.L, c.invL, e);
+            if (filter && !(r2 < c.H2)) continue;
+            adj_pair<T, DIM, RENORM>(c, vk, ak, rbk, Vk, rhok, pk, irk, dpk, Gk, nb[u], e, r2, acc[u % NQ]);
         }
     }
     T gx[3] = {0, 0, 0}, gv[3] = {0, 0, 0};
@@ -1779,7 +1769,7 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
         vec4_t<T> b;
         b.x = rho;
         b.y = tait(S, rho);
-        b.z = T(1) / rho;
+        b.z = fast_rcp(rho);
         b.w = tait_slope(S, rho);
         na.jdB[k] = b;
     }

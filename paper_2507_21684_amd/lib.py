@@ -103,6 +103,14 @@ def lib():
         L.sph_neighbors_adaptive.restype = st
         L.sph_neighbors_adaptive.argtypes = [_VP, ctypes.POINTER(SphState), _VP, _VP, _VP, _VP, ctypes.c_int64,
                                              ctypes.POINTER(ctypes.c_int64), _VP]
+        L.sph_retained_lists.restype = st
+        L.sph_retained_lists.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_uint64)]
+        L.sph_step_adjoint_retained.restype = st
+        L.sph_step_adjoint_retained.argtypes = [_VP, ctypes.POINTER(SphState), ctypes.POINTER(SphState),
+                                                ctypes.c_int32, ctypes.c_uint64, _VP]
+        L.sph_density_adjoint_retained.restype = st
+        L.sph_density_adjoint_retained.argtypes = [_VP, ctypes.POINTER(SphState), _VP, _VP, ctypes.c_int32,
+                                                   ctypes.c_uint64, _VP]
         L.sph_rhs.restype = st
         L.sph_rhs.argtypes = [_VP, ctypes.POINTER(SphState), _VP, _VP, _VP, _VP]
         L.sph_step.restype = st
@@ -136,7 +144,8 @@ def exported_symbols() -> List[str]:
             "sph_pair_count", "sph_profile_enable", "sph_profile_read", "sph_last_error", "sph_set_tuning",
             "sph_get_tuning", "sph_rollout_backward", "sph_set_graphs", "sph_density_adjoint", "sph_set_reuse",
             "sph_set_integrator", "sph_set_symplectic", "sph_set_diffusion", "sph_shift",
-            "sph_shift_adjoint", "sph_bind_scratch", "sph_neighbors_adaptive"]
+            "sph_shift_adjoint", "sph_bind_scratch", "sph_neighbors_adaptive", "sph_retained_lists",
+            "sph_step_adjoint_retained", "sph_density_adjoint_retained"]
 
 
 # Bytes of the library's static per-device workspace (SPH_SCRATCH_BYTES in sph.h).
@@ -374,11 +383,24 @@ class Plan:
         c = self.state(gx, gv, grho)
         _check(lib().sph_shift_adjoint(self._h, ctypes.byref(s), ctypes.byref(c), float(beta), _stream_ptr(stream)))
 
-    def step_adjoint(self, x, v, rho, gx, gv, grho, stream=None):
-        """Map the output cotangents (gx, gv, grho) of one step started at (x, v, rho) to its inputs, in place."""
+    def step_adjoint(self, x, v, rho, gx, gv, grho, stream=None, retained=None):
+        """Map the output cotangents (gx, gv, grho) of one step started at (x, v, rho) to its inputs, in place.
+        retained: a (slot, generation) pair from retained_lists() taken after the one-step call that
+        started at this state; its sort and lists are reused while still in the workspace."""
         s = self.state(x, v, rho)
         c = self.state(gx, gv, grho)
-        _check(lib().sph_step_adjoint(self._h, ctypes.byref(s), ctypes.byref(c), _stream_ptr(stream)))
+        if retained is None:
+            _check(lib().sph_step_adjoint(self._h, ctypes.byref(s), ctypes.byref(c), _stream_ptr(stream)))
+        else:
+            _check(lib().sph_step_adjoint_retained(self._h, ctypes.byref(s), ctypes.byref(c), int(retained[0]),
+                                                   int(retained[1]), _stream_ptr(stream)))
+
+    def retained_lists(self) -> Tuple[int, int]:
+        """(slot, generation) of the sort and lists that the last rhs or step call kept for its input state
+        (slot -1 when gone)."""
+        sl, gen = ctypes.c_int32(), ctypes.c_uint64()
+        _check(lib().sph_retained_lists(self._h, ctypes.byref(sl), ctypes.byref(gen)))
+        return int(sl.value), int(gen.value)
 
     def rollout_backward(self, ckpt: List[tuple], nsteps: int, ckpt_every: int, gx, gv, grho, stream=None):
         """Cotangents (gx, gv, grho) of the state after nsteps steps -> those of the initial state, in place,
@@ -391,15 +413,20 @@ class Plan:
         _check(lib().sph_rollout_backward(self._h, cp, int(nsteps), int(ckpt_every), ctypes.byref(c),
                                           _stream_ptr(stream)))
 
-    def density_adjoint(self, x, v, rho, rho_sum_bar, stream=None) -> torch.Tensor:
-        """Cotangent of the positions for cotangents rho_sum_bar[N] of the summation density."""
+    def density_adjoint(self, x, v, rho, rho_sum_bar, stream=None, retained=None) -> torch.Tensor:
+        """Cotangent of the positions for cotangents rho_sum_bar[N] of the summation density.
+        retained: a (slot, generation) pair from retained_lists() taken after the rhs call at this state."""
         s = self.state(x, v, rho)
         g = rho_sum_bar.contiguous()
         if tuple(g.shape) != (self.N,) or g.dtype != self.torch_dtype or not g.is_cuda:
             raise ValueError("rho_sum_bar must be a %s GPU tensor of shape (%d,)" % (self.torch_dtype, self.N))
         xbar = torch.empty((self.dim, self.N), dtype=self.torch_dtype, device=self.device)
-        _check(lib().sph_density_adjoint(self._h, ctypes.byref(s), g.data_ptr(), xbar.data_ptr(),
-                                         _stream_ptr(stream)))
+        if retained is None:
+            _check(lib().sph_density_adjoint(self._h, ctypes.byref(s), g.data_ptr(), xbar.data_ptr(),
+                                             _stream_ptr(stream)))
+        else:
+            _check(lib().sph_density_adjoint_retained(self._h, ctypes.byref(s), g.data_ptr(), xbar.data_ptr(),
+                                                      int(retained[0]), int(retained[1]), _stream_ptr(stream)))
         return xbar
 
     def bind_scratch(self, stream=None):

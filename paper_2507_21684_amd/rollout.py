@@ -2,7 +2,10 @@
 
 The forward pass advances the state with `sph_step`, keeping only a checkpoint of the state
 every K steps (the paper's gradient checkpointing, Sec. 3: only particle data are retained,
-intermediate pair quantities are recomputed).  The backward pass is `sph_rollout_backward`:
+intermediate pair quantities are recomputed).  A one-step rollout and the summation density
+hand their backward the sort and neighbour lists that their forward built (retained in the
+plan's workspace, reused while nothing has overwritten them), as the paper's backward reuses
+the forward's adjacency.  The backward pass is `sph_rollout_backward`:
 segment by segment in reverse, it recomputes the segment from its checkpoint (keeping each
 step's sorted state and neighbour lists in the plan's tape) and applies the one-step
 vector-Jacobian product (Sec. 2.2) to every step in reverse.  The plan's tape_depth must be
@@ -41,8 +44,12 @@ class SPHRollout(torch.autograd.Function):
         nseg = math.ceil(nsteps / K) if nsteps > 0 else 0
         x, v, rho = x0.detach().clone(), v0.detach().clone(), rho0.detach().clone()
         ckpts = [plan.empty_state() for _ in range(nseg)]
+        ctx.retained = (-1, 0)
         if nsteps > 0:
             plan.step(x, v, rho, nsteps, ckpts, K)
+            if nsteps == 1:
+                # the sort and lists of the initial state, reused by the backward while they last
+                ctx.retained = plan.retained_lists()
             if check:
                 check_status(plan, "rollout forward")
         ctx.plan, ctx.nsteps, ctx.K, ctx.nseg, ctx.check = plan, int(nsteps), K, nseg, bool(check)
@@ -59,7 +66,13 @@ class SPHRollout(torch.autograd.Function):
         cx = gx.detach().clone().contiguous() if gx is not None else torch.zeros_like(ref[0])
         cv = gv.detach().clone().contiguous() if gv is not None else torch.zeros_like(ref[1])
         cr = grho.detach().clone().contiguous() if grho is not None else torch.zeros_like(ref[2])
-        if ctx.nsteps > 0:
+        if ctx.nsteps == 1 and ctx.retained[0] >= 0:
+            # one step: its adjoint on the forward's retained lists (a plain step adjoint if they
+            # have been overwritten since)
+            plan.step_adjoint(*ckpts[0], cx, cv, cr, retained=ctx.retained)
+            if ctx.check:
+                check_status(plan, "rollout backward")
+        elif ctx.nsteps > 0:
             plan.rollout_backward(ckpts, ctx.nsteps, ctx.K, cx, cv, cr)
             if ctx.check:
                 check_status(plan, "rollout backward")
@@ -83,6 +96,7 @@ class SPHDensitySum(torch.autograd.Function):
         xs, vs, rs = x.detach().contiguous(), v.detach().contiguous(), rho.detach().contiguous()
         _, _, rho_sum = plan.rhs(xs, vs, rs, rho_sum=True)
         ctx.plan = plan
+        ctx.retained = plan.retained_lists()  # the lists of this state, reused by the backward
         ctx.save_for_backward(xs, vs, rs)
         return rho_sum
 
@@ -91,7 +105,7 @@ class SPHDensitySum(torch.autograd.Function):
         xs, vs, rs = ctx.saved_tensors
         if g is None:
             return None, None, None, None
-        return ctx.plan.density_adjoint(xs, vs, rs, g.detach().contiguous()), None, None, None
+        return ctx.plan.density_adjoint(xs, vs, rs, g.detach().contiguous(), retained=ctx.retained), None, None, None
 
 
 def density_sum(plan: Plan, x, v, rho) -> torch.Tensor:
