@@ -258,7 +258,7 @@ def measured_traffic(workload, kernel_symbol):
     return None
 
 
-def roofline(prof, dom, wl, per_state, reps, dim, n_particles, lanes=(4, 4)):
+def roofline(prof, dom, wl, per_state, reps, dim, n_particles, lanes=(4, 4), taped=False):
     """Roofline of the dominant kernel from its HIP-event launch times in the timed region.
 
     k_sweep / k_adj_sweep: ALU-bound; algorithmic flops per launch = flops per directed pair x
@@ -266,7 +266,9 @@ def roofline(prof, dom, wl, per_state, reps, dim, n_particles, lanes=(4, 4)):
     4 B per list entry (pairs plus the self entry) + 4 B per count + the 16 B record read per
     particle."""
     K = wl.ckpt_every
-    recompute = [n for n in range(wl.steps) if wl.adjoint and (n + 1) % K != 0 and n != wl.steps - 1]
+    # states whose forward sweep the backward recomputes (none when it runs on the forward's tape)
+    recompute = [] if taped else [n for n in range(wl.steps) if wl.adjoint and (n + 1) % K != 0
+                                  and n != wl.steps - 1]
     p_fwd = sum(per_state)
     ms_dom, n_dom = prof[dom]
     mean_launch_s = ms_dom / n_dom * 1e-3
@@ -275,7 +277,7 @@ def roofline(prof, dom, wl, per_state, reps, dim, n_particles, lanes=(4, 4)):
         # one build per rebuild interval, forward and again in the backward's recomputation
         # (with a list skin the lists hold more entries than the pairs counted here)
         R = lanes[2] if len(lanes) > 2 else 1
-        states = [n for n in range(wl.steps) if n % R == 0] * (2 if wl.adjoint else 1)
+        states = [n for n in range(wl.steps) if n % R == 0] * (2 if wl.adjoint and not taped else 1)
         entries = sum(per_state[n] + n_particles for n in states) * reps
         launches = len(states) * reps
         bytes_per_launch = (4 * entries + launches * n_particles * (4 + (16 if wl.dtype == "f32" else 32))) / launches
@@ -328,7 +330,7 @@ def plain_path(dev, wl, x0, v0, r0, skins, R):
         sub = Workload("one", [s], [wl.seeds[k]], wl.dtype, wl.steps, wl.ckpt_every, wl.adjoint, wl.loss)
         st = (x0[:, offs[k]:offs[k + 1]].contiguous(), v0[:, offs[k]:offs[k + 1]].contiguous(),
               r0[offs[k]:offs[k + 1]].contiguous())
-        p = Plan([s.params()], [s.n], wl.dtype, tape_depth=wl.ckpt_every, device=dev, skin=skins[k],
+        p = Plan([s.params()], [s.n], wl.dtype, tape_depth=max(wl.ckpt_every, wl.tape), device=dev, skin=skins[k],
                  rebuild_every=R)
         autotune.tune(p, *st)
         run_job(p, *st, sub)
@@ -592,8 +594,8 @@ def bench_graphs(dev, name, skins, R, lanes, reps=5):
     from paper_2507_21684_amd.lib import Plan
     wl = workloads()[name]()
     _, (x0, v0, r0) = packed_inputs(wl, dev)
-    plan = Plan([s.params() for s in wl.sims], [s.n for s in wl.sims], wl.dtype, tape_depth=wl.ckpt_every,
-                device=dev, skin=skins, rebuild_every=R)
+    plan = Plan([s.params() for s in wl.sims], [s.n for s in wl.sims], wl.dtype,
+                tape_depth=max(wl.ckpt_every, wl.tape), device=dev, skin=skins, rebuild_every=R)
     plan.set_tuning(*lanes)
     T, K = wl.steps, wl.ckpt_every
     x, v, r = plan.empty_state()
@@ -724,7 +726,7 @@ def measure_workload(name, dev, reps, warmup):
     host, (x0, v0, r0) = packed_inputs(wl, dev)
     if wl.adjoint:
         plan = autotune.tune_plan([s.params() for s in wl.sims], [s.n for s in wl.sims], wl.dtype,
-                                  wl.ckpt_every, x0, v0, r0, dev)
+                                  wl.ckpt_every, x0, v0, r0, dev, tape_depth=wl.tape or None)
     else:
         plan = Plan([s.params() for s in wl.sims], [s.n for s in wl.sims], wl.dtype, tape_depth=0, device=dev)
     lanes = plan.get_tuning()
@@ -740,7 +742,9 @@ def measure_workload(name, dev, reps, warmup):
     scale = p_fwd / max(sum(per_state), 1)
     per_state = [c * scale for c in per_state]
     p_adj = p_fwd if wl.adjoint else 0          # adjoint step n runs on forward state n
-    recompute_swept = [n for n in range(wl.steps) if wl.adjoint and (n + 1) % K != 0 and n != wl.steps - 1]
+    taped = wl.adjoint and plan.tape_depth >= wl.steps
+    recompute_swept = [] if taped else [n for n in range(wl.steps) if wl.adjoint and (n + 1) % K != 0
+                                        and n != wl.steps - 1]
     p_rec = int(round(sum(per_state[n] for n in recompute_swept)))
     plan.poll()
     n_part = int(sum(s.n for s in wl.sims))
@@ -753,13 +757,15 @@ def measure_workload(name, dev, reps, warmup):
     status = plan.poll()
     assert np.all(status == 0), "device reported non-finite values or neighbour overflow: %s" % status
     dim = wl.sims[0].dim
-    roof = roofline(prof, dom, wl, per_state, reps, dim, n_part, tuple(lanes) + (R,))
+    roof = roofline(prof, dom, wl, per_state, reps, dim, n_part, tuple(lanes) + (R,), taped)
     ms = 1e3 * elapsed / reps
     log("%s: timed %d jobs, %.3f ms per job" % (wl.name, reps, ms))
     config = {"workload": wl.name, "dim": dim, "simulations": len(wl.sims), "particles": n_part,
               "sim_steps": wl.steps, "ckpt_every": wl.ckpt_every, "adjoint": wl.adjoint, "loss": wl.loss,
               "pairs_fwd": p_fwd, "pairs_adj": p_adj, "pairs_recompute": p_rec,
-              "lanes_per_particle": list(lanes), "list_rebuild_every": R}
+              "lanes_per_particle": list(lanes), "list_rebuild_every": R, "tape_depth": plan.tape_depth,
+              "backward": "on the forward's tape" if plan.tape_depth >= wl.steps else
+                          "recomputes each checkpoint segment"}
     if len(wl.sims) > 1:
         config["list_skin_range"] = [round(min(plan.skins), 4), round(max(plan.skins), 4)]
     else:
@@ -823,7 +829,7 @@ def main():
         host, (x0, v0, r0) = packed_inputs(wl, dev)
         if wl.adjoint:
             plan = autotune.tune_plan([s.params() for s in wl.sims], [s.n for s in wl.sims], wl.dtype,
-                                      wl.ckpt_every, x0, v0, r0, dev)
+                                      wl.ckpt_every, x0, v0, r0, dev, tape_depth=wl.tape or None)
         else:
             plan = Plan([s.params() for s in wl.sims], [s.n for s in wl.sims], wl.dtype, tape_depth=0, device=dev)
         for _ in range(args.warmup + 1):

@@ -349,7 +349,10 @@ sph_status sph_rhs(sph_plan* plan, const sph_state* s, void* drho, void* acc, vo
  * must hold ceil(nsteps / ckpt_every) states; slot k receives the state at
  * step k * ckpt_every (slot 0 = the input state), in original order.  These
  * are the segment starts for checkpointed recomputation (Sec. 3: gradient
- * checkpointing with on-the-fly recompute). */
+ * checkpointing with on-the-fly recompute).  When the plan's tape_depth is at
+ * least nsteps (and the default integrator is in use), every step keeps its
+ * sorted state and neighbour lists in its own tape slot (the forward tape),
+ * which sph_rollout_backward then uses instead of recomputing. */
 sph_status sph_step(sph_plan* plan, sph_state* s, int32_t nsteps, const sph_state* ckpt, int32_t ckpt_every,
                     void* stream);
 
@@ -375,6 +378,11 @@ sph_status sph_step_adjoint(sph_plan* plan, const sph_state* s_n, sph_state* cot
  * from its checkpoint keeping every step's sorted state and neighbour lists in
  * the workspace tape, then its steps' adjoints run in reverse on the taped
  * data (each equal to sph_step_adjoint() on that step's start state).
+ * When the last sph_step call on the plan kept a forward tape of exactly these
+ * nsteps with exactly these checkpoints (same pointers), and no call has
+ * written any of its slots since (every write of a slot changes its
+ * generation number, which is checked), the adjoint steps run on that tape and
+ * nothing is recomputed; the result is bitwise the same.
  * Needs tape_depth >= min(ckpt_every, nsteps) (else CAPACITY). */
 sph_status sph_rollout_backward(sph_plan* plan, const sph_state* ckpt, int32_t nsteps, int32_t ckpt_every,
                                 sph_state* cot, void* stream);

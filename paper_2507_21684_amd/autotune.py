@@ -11,8 +11,9 @@
   simulation's skin is 2 x 1.3 x v_max dt R / H from the largest speed of its state (30 %
   margin; the device flags any particle that moves farther).  `tune_plan` builds a plan per
   candidate R dividing the checkpoint interval, tunes its lanes, times one checkpoint segment
-  forward and backward, discards candidates whose run raised a device flag, and returns the
-  fastest plan.
+  forward and backward (with a tape as deep as the segment, so the backward runs on the
+  forward's tape), discards candidates whose run raised a device flag, and returns the fastest
+  plan, with a tape as deep as the caller asks.
 
 Choices are cached in a JSON file keyed by GPU architecture, dimension, dtype and a
 power-of-two bucket of the plan's particle count (the cache path is $SPH_TUNING_CACHE, else
@@ -190,16 +191,19 @@ def _segment_seconds(plan: Plan, x, v, rho, K: int, reps: int = 3) -> Tuple[floa
 
 
 def tune_plan(sims: Sequence[dict], counts: Sequence[int], dtype: str, ckpt_every: int, x, v, rho,
-              device=None, use_cache: bool = True, choices=REBUILD_CHOICES) -> Plan:
-    """Plan with the fastest (rebuild interval, skins, lanes) for one checkpoint segment of this state."""
+              device=None, use_cache: bool = True, choices=REBUILD_CHOICES, tape_depth: Optional[int] = None) -> Plan:
+    """Plan with the fastest (rebuild interval, skins, lanes) for one checkpoint segment of this state.
+    The returned plan has tape_depth slots (default: the checkpoint interval); with as many slots as a
+    rollout has steps, the forward keeps every step and the backward runs without recomputing."""
     K = int(ckpt_every)
+    depth = K if tape_depth is None else max(int(tape_depth), K)
     probe = Plan(sims, counts, dtype, tape_depth=K, device=device)
     key = cache_key(probe) + ":K%d:reuse" % K
     del probe
     table = _load() if use_cache else {}
     if key in table:
         R, lf, la = (int(t) for t in table[key][:3])
-        plan = Plan(sims, counts, dtype, tape_depth=K, device=device, skin=skins_for(sims, counts, v, R),
+        plan = Plan(sims, counts, dtype, tape_depth=depth, device=device, skin=skins_for(sims, counts, v, R),
                     rebuild_every=R)
         plan.set_tuning(lf, la)
         return plan
@@ -221,7 +225,7 @@ def tune_plan(sims: Sequence[dict], counts: Sequence[int], dtype: str, ckpt_ever
     if use_cache:
         table[key] = [R, lf, la, trials]
         _store(table)
-    plan = Plan(sims, counts, dtype, tape_depth=K, device=device, skin=skins_for(sims, counts, v, R),
+    plan = Plan(sims, counts, dtype, tape_depth=depth, device=device, skin=skins_for(sims, counts, v, R),
                 rebuild_every=R)
     plan.set_tuning(lf, la)
     return plan

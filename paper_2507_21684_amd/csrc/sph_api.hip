@@ -130,6 +130,14 @@ struct sph_plan {
         kept_slot = sl;
         kept_gen = sl >= 0 ? slot_gen[(size_t)sl] : 0;
     }
+    // A semi-implicit Euler sph_step call of nsteps <= the tape slots keeps step t's sorted state
+    // and lists in slot t (the forward tape).  A later sph_rollout_backward over the same steps and
+    // the checkpoints that call wrote runs its adjoint steps on that tape, without recomputing the
+    // segments, while every slot still has the generation the forward left.
+    bool ftape = false;
+    int32_t ftape_n = 0, ftape_every = 0;
+    std::vector<uint64_t> ftape_gen;
+    std::vector<uintptr_t> ftape_ckpt;
     int64_t nparts = 0, nparts64 = 0;
     size_t bytes = 0;
     char* ws = nullptr;
@@ -190,6 +198,16 @@ template <typename T>
 T* wsp(const sph_plan* p, size_t off) { return reinterpret_cast<T*>(p->ws + off); }
 
 size_t tsize(const sph_plan* p) { return p->dtype == SPH_F64 ? 8 : 4; }
+
+// The pointers of a state, appended to a key.
+void key_state(std::vector<uintptr_t>& key, const sph_state* s)
+{
+    for (int k = 0; k < 3; ++k) {
+        key.push_back((uintptr_t)s->x[k]);
+        key.push_back((uintptr_t)s->v[k]);
+    }
+    key.push_back((uintptr_t)s->rho);
+}
 
 // Brackets a group of launches of one kernel class with HIP events on the launch stream
 // when profiling is enabled.  A scope that holds exactly one kernel launch (one_kernel) gives
@@ -1028,7 +1046,18 @@ sph_status do_step(sph_plan* P, sph_state* s, int32_t nsteps, const sph_state* c
     }
     if (ckpt) RC_TRY((copy_state<T, D>(P, user_state<T, D>(&ckpt[0]), user, st)));
     int last = 0;
-    RC_TRY((run_steps<T, D>(P, user, nsteps, false, true, ckpt, every, &last, st)));
+    // with room for every step, step t keeps its sorted state and lists in slot t (forward tape)
+    const bool tape = nsteps <= P->nslots && P->tape_depth >= nsteps;
+    P->ftape = false;
+    RC_TRY((run_steps<T, D>(P, user, nsteps, tape, true, ckpt, every, &last, st)));
+    if (tape && ckpt) {
+        P->ftape = true;
+        P->ftape_n = nsteps;
+        P->ftape_every = every;
+        P->ftape_gen.assign(P->slot_gen.begin(), P->slot_gen.begin() + nsteps);
+        P->ftape_ckpt.clear();
+        for (int32_t k = 0; k < (nsteps + every - 1) / every; ++k) key_state(P->ftape_ckpt, &ckpt[k]);
+    }
     return unsort_from<T, D>(P, ws_state<T, D>(P, P->o_SB), last, user, st);
 }
 
@@ -1049,7 +1078,7 @@ sph_status do_step_adjoint(sph_plan* P, const sph_state* sn, sph_state* cot, hip
 // reverse on the taped data.
 template <typename T, int D>
 sph_status do_rollout_backward(sph_plan* P, const sph_state* ckpt, int32_t nsteps, int32_t every, sph_state* cot,
-                               hipStream_t st)
+                               hipStream_t st, bool use_tape)
 {
     if (nsteps == 0) return SPH_OK;
     const int32_t nseg = (nsteps + every - 1) / every;
@@ -1098,6 +1127,16 @@ sph_status do_rollout_backward(sph_plan* P, const sph_state* ckpt, int32_t nstep
         }
         return SPH_OK;
     }
+    if (use_tape) {
+        // the forward's tape holds every step: the adjoint steps in reverse, no recomputation
+        P->adj_buf = 0;
+        P->adj_ready = -1;
+        for (int32_t t = nsteps - 1; t >= 0; --t) {
+            const int next = (t > 0 && P->list_of[t] == P->list_of[t - 1]) ? t - 1 : -1;
+            RC_TRY((adjoint<T, D>(P, t, c, st, false, next)));
+        }
+        return SPH_OK;
+    }
     for (int32_t seg = nseg - 1; seg >= 0; --seg) {
         const int32_t len = std::min(every, nsteps - seg * every);
         int last = 0;
@@ -1111,6 +1150,20 @@ sph_status do_rollout_backward(sph_plan* P, const sph_state* ckpt, int32_t nstep
         }
     }
     return SPH_OK;
+}
+
+// Whether sph_rollout_backward over (ckpt, nsteps, every) may run on the forward tape: the last
+// sph_step call taped exactly these steps with these checkpoints, and no slot was written since.
+bool forward_tape_intact(const sph_plan* P, const sph_state* ckpt, int32_t nsteps, int32_t every)
+{
+    if (!P->ftape || P->ftape_n != nsteps || P->ftape_every != every || P->symplectic || P->rk_stages > 0)
+        return false;
+    std::vector<uintptr_t> k;
+    for (int32_t s2 = 0; s2 < (nsteps + every - 1) / every; ++s2) key_state(k, &ckpt[s2]);
+    if (k != P->ftape_ckpt) return false;
+    for (int32_t t = 0; t < nsteps; ++t)
+        if (P->slot_gen[(size_t)t] != P->ftape_gen[(size_t)t]) return false;
+    return true;
 }
 
 constexpr size_t kGraphCache = 8;
@@ -1132,8 +1185,10 @@ sph_status run_graphed(sph_plan* P, std::vector<uintptr_t> key, hipStream_t st, 
         if (g.key == key) {
             g.used = ++P->gclock;
             HIP_TRY(hipGraphLaunch(g.exec, st));
-            // the replay rewrites slots without the host bookkeeping of a direct call
+            // the replay rewrites slots without the host bookkeeping of a direct call: the
+            // forward tape is not reused after a replay
             P->touch_all();
+            P->ftape = false;
             if (g.kept_slot >= 0) P->keep(g.kept_slot);
             return SPH_OK;
         }
@@ -1172,14 +1227,6 @@ sph_status run_graphed(sph_plan* P, std::vector<uintptr_t> key, hipStream_t st, 
     return SPH_OK;
 }
 
-void key_state(std::vector<uintptr_t>& key, const sph_state* s)
-{
-    for (int k = 0; k < 3; ++k) {
-        key.push_back((uintptr_t)s->x[k]);
-        key.push_back((uintptr_t)s->v[k]);
-    }
-    key.push_back((uintptr_t)s->rho);
-}
 
 template <typename T, int D, int LPP>
 void launch_density_adj(sph_plan* P, const SlotLayout& L, const T* gs, T* xbar, hipStream_t st)
@@ -1916,11 +1963,12 @@ sph_status sph_rollout_backward(sph_plan* P, const sph_state* ckpt, int32_t nste
     const int32_t nseg = nsteps > 0 ? (nsteps + ckpt_every - 1) / ckpt_every : 0;
     for (int32_t k = 0; k < nseg; ++k) RC_TRY(check_state(P, &ckpt[k], "checkpoint slot"));
     P->adj_ready = -1;
-    std::vector<uintptr_t> key = {2u, (uintptr_t)nsteps, (uintptr_t)ckpt_every};
+    const bool use_tape = nsteps > 0 && forward_tape_intact(P, ckpt, nsteps, ckpt_every);
+    std::vector<uintptr_t> key = {2u, (uintptr_t)nsteps, (uintptr_t)ckpt_every, (uintptr_t)use_tape};
     key_state(key, cot);
     for (int32_t k = 0; k < nseg; ++k) key_state(key, &ckpt[k]);
     return run_graphed(P, std::move(key), (hipStream_t)stream, [&](hipStream_t st) {
-        return DISPATCH(P, do_rollout_backward, P, ckpt, nsteps, ckpt_every, cot, st);
+        return DISPATCH(P, do_rollout_backward, P, ckpt, nsteps, ckpt_every, cot, st, use_tape);
     });
 }
 

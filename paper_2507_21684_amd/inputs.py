@@ -101,6 +101,7 @@ class Workload:
     ckpt_every: int = 8
     adjoint: bool = True
     loss: str = "sum_v2"  # "sum_v2": sum |v_T|^2 ; "ke": 1/2 sum m |v_T|^2
+    tape: int = 0         # plan tape depth (0: the checkpoint interval, so the backward recomputes)
 
 
 def tgv2d_1k_f64() -> Workload:
@@ -114,8 +115,9 @@ def tgv2d_64k_f32() -> Workload:
 
 
 def tgv3d_262k_f32() -> Workload:
-    """3D, 64^3 = 262144 particles, FP32, 32 steps + adjoint of the kinetic energy."""
-    return Workload("tgv3d_262k_f32", [SimSpec(3, 64)], [0], "f32", 32, 8, True, "ke")
+    """3D, 64^3 = 262144 particles, FP32, 32 steps + adjoint of the kinetic energy; the plan keeps
+    every step of the forward (32 tape slots), so the backward does not recompute."""
+    return Workload("tgv3d_262k_f32", [SimSpec(3, 64)], [0], "f32", 32, 8, True, "ke", tape=32)
 
 
 def batched_512_specs(seed: int = 1234, count: int = 512):
@@ -134,8 +136,10 @@ def batched_512_specs(seed: int = 1234, count: int = 512):
 
 
 def batched_512_f32() -> Workload:
+    """The 512 simulations, 32 steps + adjoint of sum |v_T|^2; the plan keeps every step of the
+    forward (32 tape slots), so the backward does not recompute."""
     sims, seeds = batched_512_specs()
-    return Workload("batched_512_tgv2d_f32", sims, seeds, "f32", 32, 8, True, "sum_v2")
+    return Workload("batched_512_tgv2d_f32", sims, seeds, "f32", 32, 8, True, "sum_v2", tape=32)
 
 
 @dataclass

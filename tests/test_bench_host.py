@@ -88,3 +88,11 @@ def test_host_info_names_the_cpu():
     info = bench.host_info()
     assert info["nproc"] >= 1 and 1 <= info["usable_cpus"] <= info["nproc"]
     assert isinstance(info["cpu_model"], str)
+
+
+def test_taped_backward_counts_no_recomputed_sweeps():
+    wl = wl2d()
+    per_state = [1e6] * wl.steps
+    prof = {"sweep": (16 * 0.030, 16)}
+    r = bench.roofline(prof, "sweep", wl, per_state, 1, 2, 4096, (4, 4, 1), taped=True)
+    assert r["pairs_per_launch"] == int(1e6)

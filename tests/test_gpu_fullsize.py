@@ -107,7 +107,8 @@ def test_c3_full_size_rollout_gradient_tuned():
         h.update(np.ascontiguousarray(a).tobytes())
     assert h.hexdigest() == ref["input_sha256"], "inputs differ from those of the stored oracle result"
     x0, v0, r0 = (torch.tensor(a, device=DEV) for a in st)
-    plan = autotune.tune_plan([spec.params()], [spec.n], "f32", K, x0, v0, r0, DEV, use_cache=False)
+    # as the bench runs it: a tape of every step, so the backward runs on the forward's tape
+    plan = autotune.tune_plan([spec.params()], [spec.n], "f32", K, x0, v0, r0, DEV, use_cache=False, tape_depth=T)
     print("tuned plan: rebuild every %d, skin %.3f, lanes %s" % (plan.rebuild_every, plan.skin, plan.get_tuning()))
     masses = torch.full((spec.n,), spec.mass, dtype=torch.float64, device=DEV)
     loss, (x, v, r), (gx, gv, gr) = _job(plan, x0, v0, r0, T, K, "ke", masses)
@@ -130,7 +131,8 @@ def test_c4_batch_sampled_simulations_tuned(orc):
     host = [np.concatenate([p[k] for p in parts], axis=-1) for k in range(3)]
     x0, v0, r0 = (torch.tensor(a, device=DEV) for a in host)
     sims, counts = [s.params() for s in wl.sims], [s.n for s in wl.sims]
-    plan = autotune.tune_plan(sims, counts, wl.dtype, wl.ckpt_every, x0, v0, r0, DEV, use_cache=False)
+    plan = autotune.tune_plan(sims, counts, wl.dtype, wl.ckpt_every, x0, v0, r0, DEV, use_cache=False,
+                              tape_depth=wl.tape or None)
     print("tuned plan: rebuild every %d, skins %.3f..%.3f, lanes %s"
           % (plan.rebuild_every, min(plan.skins), max(plan.skins), plan.get_tuning()))
     loss, (x, v, r), (gx, gv, gr) = _job(plan, x0, v0, r0, wl.steps, wl.ckpt_every, wl.loss)
