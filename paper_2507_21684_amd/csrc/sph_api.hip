@@ -164,6 +164,9 @@ struct sph_plan {
         hipGraphExec_t exec;
         uint64_t used;
         int32_t kept_slot;  // slot whose retained sort the captured call leaves valid (-1: none)
+        // the forward tape the captured step call leaves (ftape_n == 0: none)
+        int32_t ftape_n, ftape_every;
+        std::vector<uintptr_t> ftape_ckpt;
     };
     bool graphs = false;
     std::vector<GraphEntry> gcache;
@@ -1185,11 +1188,19 @@ sph_status run_graphed(sph_plan* P, std::vector<uintptr_t> key, hipStream_t st, 
         if (g.key == key) {
             g.used = ++P->gclock;
             HIP_TRY(hipGraphLaunch(g.exec, st));
-            // the replay rewrites slots without the host bookkeeping of a direct call: the
-            // forward tape is not reused after a replay
+            // the replay rewrites slots without the host bookkeeping of a direct call: every slot
+            // gets a new generation, and what the captured call left (a retained sort, a forward
+            // tape) is recorded again with them
             P->touch_all();
             P->ftape = false;
             if (g.kept_slot >= 0) P->keep(g.kept_slot);
+            if (g.ftape_n > 0) {
+                P->ftape = true;
+                P->ftape_n = g.ftape_n;
+                P->ftape_every = g.ftape_every;
+                P->ftape_ckpt = g.ftape_ckpt;
+                P->ftape_gen.assign(P->slot_gen.begin(), P->slot_gen.begin() + g.ftape_n);
+            }
             return SPH_OK;
         }
     }
@@ -1222,7 +1233,11 @@ sph_status run_graphed(sph_plan* P, std::vector<uintptr_t> key, hipStream_t st, 
     const int32_t kept = (key[0] == 1 && P->kept_slot >= 0 && P->slot_gen[(size_t)P->kept_slot] == P->kept_gen)
                              ? P->kept_slot
                              : -1;
-    P->gcache.push_back({std::move(key), graph, exec, ++P->gclock, kept});
+    bool tape_left = key[0] == 1 && P->ftape;
+    for (int32_t t = 0; tape_left && t < P->ftape_n; ++t) tape_left = P->slot_gen[(size_t)t] == P->ftape_gen[(size_t)t];
+    P->gcache.push_back({std::move(key), graph, exec, ++P->gclock, kept, tape_left ? P->ftape_n : 0,
+                         tape_left ? P->ftape_every : 0,
+                         tape_left ? P->ftape_ckpt : std::vector<uintptr_t>()});
     HIP_TRY(hipGraphLaunch(exec, st));
     return SPH_OK;
 }

@@ -56,3 +56,31 @@ def test_overwritten_tape_is_recomputed():
     got, _ = _job(taped, st, T, K, between=lambda p: p.rhs(*[t.clone() for t in st]))
     for a, b in zip(got, ref):
         assert torch.equal(a, b)
+
+
+def test_graph_replays_keep_the_forward_tape_and_the_results():
+    """Graph mode on a taped plan: the forward and backward calls replayed, with eager work in
+    between, give bitwise the direct path's results on every replay."""
+    spec = SimSpec(2, 36, amplitude=1.2)
+    T, K = 8, 4
+    st = [torch.tensor(a.astype(np.float32), device=DEV) for a in make_state(spec, 6)]
+    ref, _ = _job(Plan([spec.params()], [spec.n], "f32", tape_depth=T, device=DEV, skin=0.2, rebuild_every=2),
+                  st, T, K)
+    plan = Plan([spec.params()], [spec.n], "f32", tape_depth=T, device=DEV, skin=0.2, rebuild_every=2)
+    plan.set_graphs(True)
+    x, v, r = plan.empty_state()
+    ck = [plan.empty_state() for _ in range(T // K)]
+    gx, gv, gr = torch.empty_like(x), torch.empty_like(v), torch.empty_like(r)
+    for rep in range(4):
+        for b, a in zip((x, v, r), st):
+            b.copy_(a)
+        plan.step(x, v, r, T, ck, K)
+        gx.zero_()
+        gv.copy_(2.0 * v)
+        gr.zero_()
+        assert torch.isfinite(torch.randn(4096, device=DEV).sum())   # eager work between replays
+        plan.rollout_backward(ck, T, K, gx, gv, gr)
+        torch.cuda.synchronize()
+        for k, (a, b) in enumerate(zip((x, v, r, gx, gv, gr), ref)):
+            assert torch.equal(a, b), "replay %d, output %d" % (rep, k)
+    assert np.all(plan.poll() == 0)
