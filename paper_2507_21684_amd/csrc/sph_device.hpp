@@ -501,6 +501,32 @@ __device__ __forceinline__ void unpack_u(const vec4_t<T>& a, T* u)
 // wavefronts' integer atomics do not serialise on a single address.
 constexpr int kPairSlots = 512;
 constexpr int kPairStride = 16;
+// Status read without a host wait: the pair total and the status words moved to a staging
+// area and cleared, for one copy to the host in stream order.  One workgroup of 256 lanes.
+__global__ __launch_bounds__(256) void k_poll_stage(int32_t nsims, int32_t* __restrict__ status,
+                                                    unsigned long long* __restrict__ pair_slots,
+                                                    unsigned long long* __restrict__ stage_pairs,
+                                                    int32_t* __restrict__ stage_status)
+{
+    __shared__ unsigned long long part[256];
+    unsigned long long sum = 0;
+    for (int k = threadIdx.x; k < kPairSlots; k += blockDim.x) {
+        sum += pair_slots[k * kPairStride];
+        pair_slots[k * kPairStride] = 0ull;
+    }
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *stage_pairs = part[0];
+    for (int k = threadIdx.x; k < nsims; k += blockDim.x) {
+        stage_status[k] = status[k];
+        status[k] = 0;
+    }
+}
+
 // Candidates (of the stencil of one cell) whose stencil cell is looked up in a byte table;
 // later ones, in dense clusters only, search the prefix sums.
 constexpr int kCandTable = 2048;
@@ -1451,8 +1477,10 @@ __global__ __launch_bounds__(256) void k_unsort(int64_t N, StatePtrs<T, DIM> src
 
 // ---------------------------------------------------------------- adjoint
 
-// Gathers the output cotangents into sorted order: jdA = (abar, rbar) with
-// vt = v'_bar + dt x'_bar, abar = dt vt, rbar = dt rho'_bar; jdB = (rho, p, 1/rho, dp/drho).
+// Gathers the output cotangents into sorted order: jdA = (abar / rho, rbar) with
+// vt = v'_bar + dt x'_bar, abar = dt vt, rbar = dt rho'_bar; jdB = (rho, p, rbar rho, dp/drho).
+// The acceleration cotangent enters every pair term divided by its particle's density, so the
+// record holds it divided once.
 template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_adj_prologue(int64_t N, const int32_t* __restrict__ orig,
                                                       StatePtrs<T, DIM> cot, StatePtrs<T, DIM> cur,
@@ -1477,18 +1505,19 @@ __global__ __launch_bounds__(256) void k_adj_prologue(int64_t N, const int32_t* 
         for (int k = 0; k < DIM; ++k) ab[k] = S.dt * (cot.v[k][o] + S.dt * cot.x[k][o]);
         rb = S.dt * cot.rho[o];
     }
+    const T rho = cur.rho[q];
+    const T ir = fast_rcp(rho);
     vec4_t<T> a;
     if (DIM == 3) {
-        a.x = ab[0]; a.y = ab[1]; a.z = ab[2]; a.w = rb;
+        a.x = ab[0] * ir; a.y = ab[1] * ir; a.z = ab[2] * ir; a.w = rb;
     } else {
-        a.x = ab[0]; a.y = ab[1]; a.z = rb; a.w = T(0);
+        a.x = ab[0] * ir; a.y = ab[1] * ir; a.z = rb; a.w = T(0);
     }
     jdA[q] = a;
-    const T rho = cur.rho[q];
     vec4_t<T> b;
     b.x = rho;
     b.y = tait(S, rho);
-    b.z = fast_rcp(rho);
+    b.z = rb * rho;
     b.w = tait_slope(S, rho);
     jdB[q] = b;
 }
@@ -1510,8 +1539,8 @@ struct AdjAcc {
     T Gb[3];   // cotangent of the renormalised density gradient
 };
 
-// Per-particle adjoint record of a neighbour: jd0 = (u, V), jd1 = (v, p V), jdA = (abar, rbar)
-// (2D: (u, V, p V), (v, rho, 0), (abar, rbar, 0)), jdB = (rho, p, 1/rho, dp/drho).
+// Per-particle adjoint record of a neighbour: jd0 = (u, V), jd1 = (v, p V), jdA = (abar / rho, rbar)
+// (2D: (u, V, p V), (v, rho, 0), (abar / rho, rbar, 0)), jdB = (rho, p, rbar rho, dp/drho).
 template <typename T>
 struct AdjNbr {
     vec4_t<T> a, b, A, B, G;
@@ -1522,15 +1551,25 @@ struct AdjNbr {
 // terms (k,j) and (j,k) contracted with their particles' cotangents (abar, rbar).  With
 // e = x_kj, G = gF e, the kernel Hessian Jg = gF I + hF e e^T, pi = (v_k - v_j).e / (r^2+eps H^2),
 // s = e.G / (r^2+eps H^2), these partials reduce to the closed forms below.  The self pair
-// contributes exactly zero.
+// contributes exactly zero.  The momentum term's factor 1/rho_k and 1/rho_j always multiplies
+// the acceleration cotangent of the same particle, so both sides take abar / rho from their
+// records (ak, aj here), and X = cA pi - p_k - p_j is the pressure-and-viscosity factor that
+// Q_k = X / rho_k and Q_j = X / rho_j share.
 //
 // With RENORM, the renormalised diffusion T_i = c sum_j V_j (G_i + G_j) . grad_i W_ij
 // (c = -delta H c0) adds, for q = rbar_k V_j - rbar_j V_k and s = G_k + G_j with the
 // gradients held fixed: gx += c q Jg s, Gbar += c q gF e, gr += (V_k / rho_k) c rbar_j gF s.e.
+template <typename T>
+struct AdjSelf {
+    T v[3], a[3];   // velocity, abar / rho
+    T rb, V, rho, p, ir, dp;
+    T rbr;          // rbar rho
+    T G[3];
+};
+
 template <typename T, int DIM, bool RENORM>
-__device__ __forceinline__ void adj_pair(const PairConst<T>& c, const T* vk, const T* ak, T rbk, T Vk, T rhok, T pk,
-                                         T irk, T dpk, const T* Gk, const AdjNbr<T>& nb, const T* e, T r2,
-                                         AdjAcc<T, DIM>& acc)
+__device__ __forceinline__ void adj_pair(const PairConst<T>& c, const AdjSelf<T>& K, const AdjNbr<T>& nb,
+                                         const T* e, T r2, AdjAcc<T, DIM>& acc)
 {
     T vj[3], aj[3];
     T Vj, rbj;
@@ -1543,15 +1582,16 @@ __device__ __forceinline__ void adj_pair(const PairConst<T>& c, const T* vk, con
         vj[0] = nb.b.x; vj[1] = nb.b.y;
         aj[0] = nb.A.x; aj[1] = nb.A.y; rbj = nb.A.z;
     }
-    const T rhoj = nb.B.x, pj = nb.B.y, irj = nb.B.z;
+    const T rhoj = nb.B.x, pj = nb.B.y, rbrj = nb.B.z;
     const T cA = c.cA, cD = c.cD;
+    const T Vk = K.V, rbk = K.rb, rhok = K.rho;
     T u[3];
     T ue = 0, ake = 0, aje = 0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-        u[k] = vk[k] - vj[k];
+        u[k] = K.v[k] - vj[k];
         ue += u[k] * e[k];
-        ake += ak[k] * e[k];
+        ake += K.a[k] * e[k];
         aje += aj[k] * e[k];
     }
     const T q = fast_sqrt(r2) * c.invH;
@@ -1565,16 +1605,15 @@ __device__ __forceinline__ void adj_pair(const PairConst<T>& c, const T* vk, con
     const T sij = gF * r2 * inv;
     const T sig = inv * (T(2) * gF + hF * r2 - T(2) * sij);              // d s / d e = sig e
     const T aGk = gF * ake, aGj = gF * aje, uG = gF * ue;
-    const T Qk = (cA * pij - pk - pj) * irk;
-    const T Qj = (cA * pij - pj - pk) * irj;
-    const T beta = cA * inv * (Vj * aGk * irk - Vk * aGj * irj);
-    const T gam = Vj * rbk * rhok + Vk * rbj * rhoj;
+    const T X = cA * pij - (K.p + pj);
+    const T beta = cA * inv * (Vj * aGk - Vk * aGj);
+    const T gam = Vj * K.rbr + Vk * rbrj;
     const T cdr = cD * sig * (rhok - rhoj) * (Vj * rbk - Vk * rbj);
     T w[3];
     T ew = 0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-        w[k] = Vj * Qk * ak[k] - Vk * Qj * aj[k] + gam * u[k];
+        w[k] = X * (Vj * K.a[k] - Vk * aj[k]) + gam * u[k];
         ew += e[k] * w[k];
     }
     const T ce = cdr - T(2) * beta * pij + hF * ew;  // coefficient of e in the position cotangent
@@ -1583,16 +1622,16 @@ __device__ __forceinline__ void adj_pair(const PairConst<T>& c, const T* vk, con
         acc.gx[k] += beta * u[k] + ce * e[k] + gF * w[k];
         acc.gv[k] += (beta + gam * gF) * e[k];
     }
-    const T phi2 = Vk * (-Qj * aGj + rbj * rhoj * uG + rbj * cD * (rhoj - rhok) * sij);
-    acc.gr += Vj * (aGk * (-dpk - Qk) * irk + rbk * uG + rbk * cD * sij) - phi2 * irk +
-              Vk * (aGj * dpk * irj - rbj * cD * sij);
+    const T phi2 = Vk * (-X * aGj + rbrj * uG + rbj * cD * (rhoj - rhok) * sij);
+    acc.gr += Vj * (aGk * (-K.dp - X * K.ir) + rbk * uG + rbk * cD * sij) - phi2 * K.ir +
+              Vk * (aGj * K.dp - rbj * cD * sij);
     if (RENORM) {
         const T cr = T(-0.5) * cD;
         const T Gj[3] = {nb.G.x, nb.G.y, nb.G.z};
         T sv[3], es = T(0);
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
-            sv[k] = Gk[k] + Gj[k];
+            sv[k] = K.G[k] + Gj[k];
             es += e[k] * sv[k];
         }
         const T qq = cr * (rbk * Vj - rbj * Vk);
@@ -1601,7 +1640,7 @@ __device__ __forceinline__ void adj_pair(const PairConst<T>& c, const T* vk, con
             acc.gx[k] += qq * (gF * sv[k] + hF * es * e[k]);
             acc.Gb[k] += qq * gF * e[k];
         }
-        acc.gr += Vk * irk * cr * rbj * gF * es;
+        acc.gr += Vk * K.ir * cr * rbj * gF * es;
     }
 }
 
@@ -1629,28 +1668,35 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
     const int s = psim[k];
     const SimConst<T>& S = sims[s];
     const PairConst<T> c = pair_const(S);
-    T uk[3] = {0, 0, 0}, vk[3] = {0, 0, 0}, ak[3] = {0, 0, 0};
-    T Vk, rbk;
+    T uk[3] = {0, 0, 0};
+    AdjSelf<T> K;
     {
         const vec4_t<T> a = jd0[k], b = jd1[k], A = jdA[k];
+        K.v[2] = K.a[2] = T(0);
         if (DIM == 3) {
-            uk[0] = a.x; uk[1] = a.y; uk[2] = a.z; Vk = a.w;
-            vk[0] = b.x; vk[1] = b.y; vk[2] = b.z;
-            ak[0] = A.x; ak[1] = A.y; ak[2] = A.z; rbk = A.w;
+            uk[0] = a.x; uk[1] = a.y; uk[2] = a.z; K.V = a.w;
+            K.v[0] = b.x; K.v[1] = b.y; K.v[2] = b.z;
+            K.a[0] = A.x; K.a[1] = A.y; K.a[2] = A.z; K.rb = A.w;
         } else {
-            uk[0] = a.x; uk[1] = a.y; Vk = a.z;
-            vk[0] = b.x; vk[1] = b.y;
-            ak[0] = A.x; ak[1] = A.y; rbk = A.z;
+            uk[0] = a.x; uk[1] = a.y; K.V = a.z;
+            K.v[0] = b.x; K.v[1] = b.y;
+            K.a[0] = A.x; K.a[1] = A.y; K.rb = A.z;
         }
     }
-    const vec4_t<T> Bk = jdB[k];
-    const T rhok = Bk.x, pk = Bk.y, irk = Bk.z, dpk = Bk.w;
-    T Gk[3] = {0, 0, 0};
+    {
+        const vec4_t<T> Bk = jdB[k];
+        K.rho = Bk.x;
+        K.p = Bk.y;
+        K.rbr = Bk.z;
+        K.dp = Bk.w;
+        K.ir = fast_rcp(K.rho);
+    }
+    K.G[0] = K.G[1] = K.G[2] = T(0);
     if (RENORM) {
         const vec4_t<T> g = jdG[k];
-        Gk[0] = g.x;
-        Gk[1] = g.y;
-        Gk[2] = g.z;
+        K.G[0] = g.x;
+        K.G[1] = g.y;
+        K.G[2] = g.z;
     }
     int n = nbr_count[k];
     n = n < width ? n : width;
@@ -1683,7 +1729,7 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
             T e[3];
             const T r2 = r2_exact<T, DIM>(uk, nb[u].a, c.L, c.invL, e);
             if (filter && !(r2 < c.H2)) continue;
-            adj_pair<T, DIM, RENORM>(c, vk, ak, rbk, Vk, rhok, pk, irk, dpk, Gk, nb[u], e, r2, acc[u % NQ]);
+            adj_pair<T, DIM, RENORM>(c, K, nb[u], e, r2, acc[u % NQ]);
         }
     }
     T gx[3] = {0, 0, 0}, gv[3] = {0, 0, 0};
@@ -1758,18 +1804,19 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
 #pragma unroll
         for (int d = 0; d < DIM; ++d) ab[d] = dt * (vn[d] + dt * xn[d]);
         const T rb = dt * rn;
+        const T rho = na.rho[k];
+        const T ir = fast_rcp(rho);
         vec4_t<T> a;
         if (DIM == 3) {
-            a.x = ab[0]; a.y = ab[1]; a.z = ab[2]; a.w = rb;
+            a.x = ab[0] * ir; a.y = ab[1] * ir; a.z = ab[2] * ir; a.w = rb;
         } else {
-            a.x = ab[0]; a.y = ab[1]; a.z = rb; a.w = T(0);
+            a.x = ab[0] * ir; a.y = ab[1] * ir; a.z = rb; a.w = T(0);
         }
         na.jdA[k] = a;
-        const T rho = na.rho[k];
         vec4_t<T> b;
         b.x = rho;
         b.y = tait(S, rho);
-        b.z = fast_rcp(rho);
+        b.z = rb * rho;
         b.w = tait_slope(S, rho);
         na.jdB[k] = b;
     }
