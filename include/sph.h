@@ -432,6 +432,17 @@ sph_status sph_poll(sph_plan* plan, int32_t* per_sim_status, void* stream);
  * SYNCHRONOUS. */
 sph_status sph_pair_count(sph_plan* plan, int64_t* pairs, void* stream);
 
+/* sph_poll and sph_pair_count together, without waiting: enqueues on `stream` the copy of the
+ * per-simulation status words into per_sim_status (host int32[nsims]) and of the directed pair
+ * count (as sph_pair_count counts it) into *pairs (host; null skips it), then clears both on the
+ * device.  The values are there once the stream has passed this point (hipStreamSynchronize, or
+ * an event recorded after the call); a later call on the same plan reuses the device staging
+ * area, so read the host copies before the stream reaches the next call.  The host buffers
+ * should be page-locked (hipHostMalloc): with pageable memory the runtime may wait for the copy
+ * before returning.  For callers that keep the device busy while they check many plans (one
+ * host synchronisation for all of them).  INVALID_ARG on a null per_sim_status. */
+sph_status sph_poll_async(sph_plan* plan, int32_t* per_sim_status, int64_t* pairs, void* stream);
+
 /* Kernel classes timed by the profiler. */
 #define SPH_KERN_SORT 0      /* cell assignment, scan, scatter, within-cell order, gather */
 #define SPH_KERN_BUILD 1     /* neighbour-list build */

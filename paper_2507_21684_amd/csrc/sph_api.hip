@@ -108,6 +108,8 @@ struct sph_plan {
     // status words of the neighbour export's own list build, kept apart from the plan's status
     // words (an overflow there is returned by sph_neighbors, not left for sph_poll)
     size_t o_status_x = 0;
+    // staging of sph_poll_async: the pair total (8 bytes), then the status words
+    size_t o_poll = 0;
     // two buffers of adjoint prologue records; adj_buf is the one in use, and adj_ready the tape
     // slot whose records an adjoint sweep has already written there (-1: none)
     size_t o_jdA2 = 0, o_jdB2 = 0;
@@ -1544,6 +1546,7 @@ sph_status sph_plan_create(const sph_params* sims, int32_t nsims, const int64_t*
     P->o_part64 = take(8 * ((size_t)P->nparts64 + 1) + 8 * (N + 1));
     P->o_pairs = take(8 * (size_t)kPairSlots * kPairStride);
     P->o_ticket = take(4);
+    P->o_poll = take(8 + 4 * (size_t)nsims);
     P->o_uref = take(V4 * N);
     P->slot.resize((size_t)P->nslots);
     P->list_of.assign((size_t)P->nslots, 0);
@@ -2014,6 +2017,21 @@ sph_status sph_pair_count(sph_plan* P, int64_t* pairs, void* stream)
     unsigned long long total = 0;
     for (int k = 0; k < kPairSlots; ++k) total += v[(size_t)k * kPairStride];
     *pairs = (int64_t)total;
+    return SPH_OK;
+}
+
+sph_status sph_poll_async(sph_plan* P, int32_t* per_sim_status, int64_t* pairs, void* stream)
+{
+    RC_TRY(check_bound(P));
+    if (!per_sim_status) return fail(SPH_ERR_INVALID_ARG, "per_sim_status is null");
+    hipStream_t st = (hipStream_t)stream;
+    unsigned long long* stage_pairs = wsp<unsigned long long>(P, P->o_poll);
+    int32_t* stage_status = wsp<int32_t>(P, P->o_poll + 8);
+    k_poll_stage<<<1, 256, 0, st>>>(P->nsims, wsp<int32_t>(P, P->o_status), wsp<unsigned long long>(P, P->o_pairs),
+                                    stage_pairs, stage_status);
+    LAUNCH_CHECK("poll_stage");
+    HIP_TRY(hipMemcpyAsync(per_sim_status, stage_status, sizeof(int32_t) * P->nsims, hipMemcpyDeviceToHost, st));
+    if (pairs) HIP_TRY(hipMemcpyAsync(pairs, stage_pairs, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     return SPH_OK;
 }
 

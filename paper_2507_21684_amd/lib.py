@@ -122,6 +122,8 @@ def lib():
         L.sph_poll.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32), _VP]
         L.sph_pair_count.restype = st
         L.sph_pair_count.argtypes = [_VP, ctypes.POINTER(ctypes.c_int64), _VP]
+        L.sph_poll_async.restype = st
+        L.sph_poll_async.argtypes = [_VP, _VP, _VP, _VP]
         L.sph_profile_enable.restype = st
         L.sph_profile_enable.argtypes = [_VP, ctypes.c_int32]
         L.sph_profile_read.restype = st
@@ -145,7 +147,7 @@ def exported_symbols() -> List[str]:
             "sph_get_tuning", "sph_rollout_backward", "sph_set_graphs", "sph_density_adjoint", "sph_set_reuse",
             "sph_set_integrator", "sph_set_symplectic", "sph_set_diffusion", "sph_shift",
             "sph_shift_adjoint", "sph_bind_scratch", "sph_neighbors_adaptive", "sph_retained_lists",
-            "sph_step_adjoint_retained", "sph_density_adjoint_retained"]
+            "sph_step_adjoint_retained", "sph_density_adjoint_retained", "sph_poll_async"]
 
 
 # Bytes of the library's static per-device workspace (SPH_SCRATCH_BYTES in sph.h).
@@ -477,3 +479,15 @@ class Plan:
         out = (ctypes.c_int32 * self.nsims)()
         _check(lib().sph_poll(self._h, out, _stream_ptr(stream)))
         return np.frombuffer(out, dtype=np.int32).copy()
+
+    def poll_async(self, status: torch.Tensor, pairs: Optional[torch.Tensor] = None, stream=None):
+        """Enqueue the status words (into `status`, host int32[nsims]) and the pair count (into
+        `pairs`, host int64[1], optional) without waiting; both are valid once the stream has
+        passed this point.  Pass page-locked tensors (pin_memory=True)."""
+        if status.device.type != "cpu" or status.dtype != torch.int32 or status.numel() < self.nsims \
+                or not status.is_contiguous():
+            raise ValueError("status must be a contiguous host int32 tensor of at least nsims entries")
+        if pairs is not None and (pairs.device.type != "cpu" or pairs.dtype != torch.int64 or pairs.numel() < 1):
+            raise ValueError("pairs must be a host int64 tensor")
+        _check(lib().sph_poll_async(self._h, status.data_ptr(), pairs.data_ptr() if pairs is not None else None,
+                                    _stream_ptr(stream)))

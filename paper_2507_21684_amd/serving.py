@@ -106,6 +106,12 @@ class Scheduler:
     for requests whose device status reports a failure (non-finite values, list overflow):
     those leave the server at once with job.error set.  The scheduler owns the clock and the
     queues and never touches device memory itself.
+
+    An engine with `lookahead` = 1 (and a drain() method) lets its device run one tick behind the
+    host: sync() of tick t waits only for tick t - 1 and reports its failures, so the host work
+    of a tick (deciding, packing, enqueueing) overlaps the device work of the previous one.  A
+    request whose last segment ran in tick t is then finished (finish(), completion time, budget
+    released) when tick t is known to be complete, at the end of tick t + 1 or at drain().
     """
 
     def __init__(self, engine, ckpt_every: int = 8, budget_bytes: int = 64 << 30,
@@ -168,12 +174,41 @@ class Scheduler:
             groups.setdefault((j.phase, j.dim, j.seg_len(self.K)), []).append(j)
         return groups
 
+    def _finalize(self, jobs: List[Job], done: List[Job]) -> None:
+        if jobs:
+            self.engine.finish(jobs)
+        for j in jobs:
+            j.finished = self.now
+            self.used -= j.footprint
+            done.append(j)
+
+    @staticmethod
+    def _mark_failed(failed: Dict[int, int], jobs) -> None:
+        for j in jobs:
+            if j.req.rid in failed:
+                j.error = int(failed[j.req.rid])
+                j.phase = "done"
+
     def run(self, trace: Sequence[Request]) -> List[Job]:
         pending = deque(sorted(trace, key=lambda r: (r.arrival, r.rid)))
         queue: deque = deque()
         active: List[Job] = []
         done: List[Job] = []
         K = self.K
+        lag = int(getattr(self.engine, "lookahead", 0))
+        inflight: deque = deque()   # per tick the device may still be running: its finished jobs
+
+        def drain():
+            # the device finishes the ticks still running; the wait is device time on the clock
+            t0 = self.clock_fn()
+            failed = self.engine.drain() or {}
+            self.wall_total += self.clock_fn() - t0
+            self.now += self.clock_fn() - t0
+            waiting = [j for batch in inflight for j in batch]
+            self._mark_failed(failed, waiting + active)
+            self._finalize(waiting, done)
+            inflight.clear()
+
         last_report = time.perf_counter()
         while pending or queue or active:
             if self.progress is not None and time.perf_counter() - last_report > self.progress_every:
@@ -184,6 +219,8 @@ class Scheduler:
                 r = pending.popleft()
                 queue.append(Job(r, int(self.engine.footprint(r))))
             if not queue and not active:
+                if inflight:
+                    drain()
                 self.now = max(self.now, pending[0].arrival)
                 continue
             # new requests start at the smallest virtual time among the requests that may run
@@ -231,22 +268,17 @@ class Scheduler:
                         if j.seg < 0:
                             j.phase = "done"
             failed = self.engine.sync() or {}
-            for j in active:
-                if j.req.rid in failed:
-                    j.error = int(failed[j.req.rid])
-                    j.phase = "done"
+            self._mark_failed(failed, active + [j for batch in inflight for j in batch])
             self.wall_total += self.clock_fn() - t0
             self.now += self.clock_fn() - t0
             self.ticks += 1
             self.batch_sizes.append(len(runnable))
-            finished = [j for j in active if j.phase == "done"]
-            if finished:
-                self.engine.finish(finished)
-            for j in finished:
-                j.finished = self.now
-                self.used -= j.footprint
-                done.append(j)
+            inflight.append([j for j in active if j.phase == "done"])
             active = [j for j in active if j.phase != "done"]
+            while len(inflight) > lag:
+                self._finalize(inflight.popleft(), done)
+        if inflight:
+            drain()
         return done
 
 
@@ -278,7 +310,15 @@ def rebuild_intervals(ckpt_every: int, reuse: int = 8) -> Dict[int, int]:
 
 
 class GpuEngine:
-    """Runs the scheduler's groups through batched plans of the HIP library."""
+    """Runs the scheduler's groups through batched plans of the HIP library.
+
+    The device runs one tick behind the host (lookahead = 1): nothing in a tick waits for the
+    device except sync(), which waits for the previous tick only.  Admission copies the
+    request's initial state from page-locked host memory without waiting, and the status words
+    and pair counts of every plan a tick used are read with sph_poll_async into page-locked
+    buffers that are examined once that tick is complete."""
+
+    lookahead = 1
 
     def __init__(self, dtype: str = "f32", ckpt_every: int = 8, device=None, tuned: bool = True,
                  reuse: int = 8):
@@ -303,6 +343,8 @@ class GpuEngine:
         self._host: Dict[int, list] = {}
         self._members: Dict[tuple, List[int]] = {}
         self.plan_seconds = 0.0         # host time spent creating and binding plans
+        self._keep: List[object] = []   # page-locked sources of this tick's host-to-device copies
+        self._ticks: deque = deque()    # ticks the device may still run: (event, readouts, sources)
 
     # -- accounting
     def workspace_bytes(self, spec) -> int:
@@ -381,7 +423,9 @@ class GpuEngine:
     # -- scheduler hooks
     def admit(self, job: Job):
         host = self._host.pop(job.req.rid)
-        job.state = tuple(self.torch.tensor(a, device=self.device) for a in host)
+        pinned = [self.torch.from_numpy(a).pin_memory() for a in host]
+        job.state = tuple(t.to(self.device, non_blocking=True) for t in pinned)
+        self._keep.extend(pinned)
 
     def forward(self, jobs: Sequence[Job], n: int):
         key = ("fwd", jobs[0].dim) + tuple(j.req.rid for j in jobs)
@@ -414,22 +458,52 @@ class GpuEngine:
             j.ckpts = []
 
     def sync(self):
-        # work is counted on the forward states only (each is also the start of one adjoint
-        # step); the recompute builds of the backward plans are not work and are discarded
+        """End the tick: enqueue the status reads of its plans, then wait for the previous tick
+        and return the failures it reported."""
+        torch = self.torch
+        used = list(self._used_plans.items())
+        total = sum(p.nsims for _, p in used)
+        status = torch.empty(max(total, 1), dtype=torch.int32, pin_memory=True)
+        pairs = torch.empty(max(len(used), 1), dtype=torch.int64, pin_memory=True)
+        reads, a = [], 0
+        for k, (key, p) in enumerate(used):
+            p.poll_async(status[a:a + p.nsims], pairs[k:k + 1])
+            reads.append((key[0], list(self._members[key]), a, p.nsims, k))
+            a += p.nsims
+        ev = torch.cuda.Event()
+        ev.record()
+        self._ticks.append((ev, reads, status, pairs, self._keep))
+        self._keep = []
         failed = {}
-        for key, p in self._used_plans.items():
-            n = p.pair_count()
-            if key[0] == "fwd":
-                self.pairs += n
-            st = p.poll()
-            for rid, word in zip(self._members[key], st):
-                if word:
-                    failed[rid] = int(word)
-        self.torch.cuda.synchronize()
-        # plans not used in this tick belong to compositions that no longer exist
+        while len(self._ticks) > self.lookahead:
+            failed.update(self._complete(self._ticks.popleft()))
+        # plans not used in this tick belong to compositions that no longer exist (the ticks
+        # that used them are complete)
         self._plans = dict(self._used_plans)
         self._members = {k: self._members[k] for k in self._plans}
         self._used_plans = {}
+        return failed
+
+    def drain(self):
+        """Wait for every tick still running; their failures."""
+        failed = {}
+        while self._ticks:
+            failed.update(self._complete(self._ticks.popleft()))
+        return failed
+
+    def _complete(self, tick) -> Dict[int, int]:
+        # work is counted on the forward states only (each is also the start of one adjoint
+        # step); the recompute builds of the backward plans are not work and are discarded
+        ev, reads, status, pairs, _sources = tick
+        ev.synchronize()
+        st, pr = status.numpy(), pairs.numpy()
+        failed = {}
+        for phase, members, a, n, k in reads:
+            if phase == "fwd":
+                self.pairs += int(pr[k])
+            for rid, word in zip(members, st[a:a + n]):
+                if word:
+                    failed[rid] = int(word)
         for rid in failed:
             self.results[rid] = None
         return failed

@@ -114,6 +114,8 @@ def test_calls_need_bound_plan():
     st = L.SphState()
     assert L.lib().sph_build_cells(h, ctypes.byref(st), None) == -7
     assert L.lib().sph_rollout_backward(h, None, 4, 2, ctypes.byref(st), None) == -7
+    words = (ctypes.c_int32 * 1)()
+    assert L.lib().sph_poll_async(h, words, None, None) == -7
     L.lib().sph_plan_destroy(h)
 
 

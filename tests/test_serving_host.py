@@ -308,3 +308,74 @@ def test_newcomers_do_not_freeze_the_running_set_while_a_large_request_waits():
         longest = max(longest, alone)
     assert any(done[k].finished > done[9].finished for k in range(11, 60))
     assert longest <= 2
+
+
+class LaggedEngine(RecordingEngine):
+    """The device runs one tick behind: sync() of tick t reports the failures of tick t - 1,
+    drain() those of the last tick."""
+
+    lookahead = 1
+
+    def __init__(self, clock):
+        super().__init__(clock)
+        self.ticks = []          # per tick: the rids of its group calls
+        self.reported = 0
+        self.finish_tick = {}
+        self._mark = 0
+
+    def sync(self):
+        self.ticks.append(sorted({rid for c in self.calls[self._mark:] for rid in c[1]}))
+        self._mark = len(self.calls)
+        out = self._report(len(self.ticks) - 1)
+        return out
+
+    def _report(self, upto):
+        failed = {}
+        while self.reported < upto:
+            failed.update({rid: 1 for rid in self.fail if rid in self.ticks[self.reported]})
+            self.reported += 1
+        return failed
+
+    def drain(self):
+        return self._report(len(self.ticks))
+
+    def finish(self, jobs):
+        super().finish(jobs)
+        for j in jobs:
+            self.finish_tick[j.req.rid] = len(self.ticks)
+
+
+def test_one_tick_lookahead_keeps_the_schedule_and_finishes_a_tick_later():
+    trace = small_trace(seed=11, count=30)
+    _, eng0, done0 = run(trace)
+    clock = FakeClock()
+    eng1 = LaggedEngine(clock)
+    done1 = Scheduler(eng1, 8, 1 << 40, clock=clock).run(trace)
+    # same group calls in the same order (the budget never binds here)
+    assert eng1.calls == eng0.calls
+    assert sorted(eng1.finished) == sorted(eng0.finished) == list(range(30))
+    fin0 = {j.req.rid: j.finished for j in done0}
+    for j in done1:
+        # finished once the tick of its last segment is known to be complete: at the end of
+        # the next tick (or when the device drains), never before the lag-free finish time
+        last = max(t for t, rids in enumerate(eng1.ticks) if j.req.rid in rids)
+        assert eng1.finish_tick[j.req.rid] >= last + 1
+        assert j.finished >= fin0[j.req.rid] - 1e-12
+        assert not j.error
+
+
+def test_one_tick_lookahead_failure_is_reported_late_and_the_request_leaves_once():
+    trace = small_trace(seed=5, count=12)
+    clock = FakeClock()
+    eng = LaggedEngine(clock)
+    eng.fail = {3}
+    done = Scheduler(eng, 4, 1 << 40, clock=clock).run(trace)
+    assert sorted(j.req.rid for j in done) == list(range(12))
+    bad = [j for j in done if j.req.rid == 3][0]
+    assert bad.error == 1
+    assert eng.finished.count(3) == 1
+    # it ran at most one tick after the tick whose status reported the failure
+    first = min(t for t, rids in enumerate(eng.ticks) if 3 in rids)
+    ran = [t for t, rids in enumerate(eng.ticks) if 3 in rids]
+    assert max(ran) <= first + 1
+    assert all(not j.error for j in done if j.req.rid != 3)
