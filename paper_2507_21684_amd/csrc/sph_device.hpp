@@ -422,14 +422,15 @@ __global__ __launch_bounds__(256) void k_order_gather(int64_t N, const int32_t* 
     dst.rho[d] = rho;
     orig_out[d] = op;
     const T V = S.m * fast_rcp(rho);
-    const T pV = tait(S, rho) * V;
+    const T pr = tait(S, rho);
+    const T pV = pr * V;
     vec4_t<T> a, b;
     if (DIM == 3) {
         a.x = u[0]; a.y = u[1]; a.z = u[2]; a.w = V;
         b.x = v[0]; b.y = v[1]; b.z = v[2]; b.w = pV;
     } else {
         a.x = u[0]; a.y = u[1]; a.z = V; a.w = pV;
-        b.x = v[0]; b.y = v[1]; b.z = rho; b.w = T(0);
+        b.x = v[0]; b.y = v[1]; b.z = rho; b.w = pr;
     }
     jd0[d] = a;
     jd1[d] = b;
@@ -464,14 +465,15 @@ __global__ __launch_bounds__(256) void k_repack(int64_t N, const int32_t* __rest
     const T rho = src.rho[p];
     dst.rho[d] = rho;
     const T V = S.m * fast_rcp(rho);
-    const T pV = tait(S, rho) * V;
+    const T pr = tait(S, rho);
+    const T pV = pr * V;
     vec4_t<T> a, b;
     if (DIM == 3) {
         a.x = u[0]; a.y = u[1]; a.z = u[2]; a.w = V;
         b.x = v[0]; b.y = v[1]; b.z = v[2]; b.w = pV;
     } else {
         a.x = u[0]; a.y = u[1]; a.z = V; a.w = pV;
-        b.x = v[0]; b.y = v[1]; b.z = rho; b.w = T(0);
+        b.x = v[0]; b.y = v[1]; b.z = rho; b.w = pr;
     }
     jd0[d] = a;
     jd1[d] = b;
@@ -988,7 +990,7 @@ struct FwdNbr {
 //   drho_i += V_j (v_i - v_j).gW     (times rho_i later)   and   V_j (rho_i - rho_j) x_ij.gW / (r^2 + eps H^2)
 //   rho_i  += W shape (times m C_d / H^d later)
 // In 3D jd0 = (u, V), jd1 = (v, p V) and rho comes separately; in 2D jd0 = (u, V, p V) and
-// jd1 = (v, rho, 0).  d and r2 are the pair vector x_ij and its square; with keep false the
+// jd1 = (v, rho, p).  d and r2 are the pair vector x_ij and its square; with keep false the
 // pair is computed but leaves acc unchanged (a select, not a branch).
 template <typename T, int DIM, bool RHOSUM, bool RENORM>
 __device__ __forceinline__ void fwd_pair(const PairConst<T>& c, const T* vi, T rhoi, T pi, const FwdNbr<T, DIM>& nb,
@@ -1194,14 +1196,15 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
 #pragma unroll
             for (int k = 0; k < DIM; ++k) u[k] = wrap_pos(isfinite(xn[k]) ? xn[k] : T(0), S.L, S.invL);
             const T V = S.m * fast_rcp(rhon);
-            const T pV = tait(S, rhon) * V;
+            const T pn = tait(S, rhon);
+            const T pV = pn * V;
             vec4_t<T> pa, pb;
             if (DIM == 3) {
                 pa.x = u[0]; pa.y = u[1]; pa.z = u[2]; pa.w = V;
                 pb.x = vn[0]; pb.y = vn[1]; pb.z = vn[2]; pb.w = pV;
             } else {
                 pa.x = u[0]; pa.y = u[1]; pa.z = V; pa.w = pV;
-                pb.x = vn[0]; pb.y = vn[1]; pb.z = rhon; pb.w = T(0);
+                pb.x = vn[0]; pb.y = vn[1]; pb.z = rhon; pb.w = pn;
             }
             ns.jd0[i] = pa;
             ns.jd1[i] = pb;
@@ -1511,7 +1514,7 @@ __global__ __launch_bounds__(256) void k_adj_prologue(int64_t N, const int32_t* 
     if (DIM == 3) {
         a.x = ab[0] * ir; a.y = ab[1] * ir; a.z = ab[2] * ir; a.w = rb;
     } else {
-        a.x = ab[0] * ir; a.y = ab[1] * ir; a.z = rb; a.w = T(0);
+        a.x = ab[0] * ir; a.y = ab[1] * ir; a.z = rb; a.w = rb * rho;
     }
     jdA[q] = a;
     vec4_t<T> b;
@@ -1539,8 +1542,10 @@ struct AdjAcc {
     T Gb[3];   // cotangent of the renormalised density gradient
 };
 
-// Per-particle adjoint record of a neighbour: jd0 = (u, V), jd1 = (v, p V), jdA = (abar / rho, rbar)
-// (2D: (u, V, p V), (v, rho, 0), (abar / rho, rbar, 0)), jdB = (rho, p, rbar rho, dp/drho).
+// Per-particle adjoint record of a neighbour: jd0 = (u, V), jd1 = (v, p V), jdA = (abar / rho, rbar),
+// jdB = (rho, p, rbar rho, dp/drho).  In 2D jd0 = (u, V, p V), jd1 = (v, rho, p) and
+// jdA = (abar / rho, rbar, rbar rho) hold everything a neighbour contributes, so the 2D sweep
+// gathers three records per neighbour and reads jdB for its own particle only.
 template <typename T>
 struct AdjNbr {
     vec4_t<T> a, b, A, B, G;
@@ -1582,7 +1587,9 @@ __device__ __forceinline__ void adj_pair(const PairConst<T>& c, const AdjSelf<T>
         vj[0] = nb.b.x; vj[1] = nb.b.y;
         aj[0] = nb.A.x; aj[1] = nb.A.y; rbj = nb.A.z;
     }
-    const T rhoj = nb.B.x, pj = nb.B.y, rbrj = nb.B.z;
+    const T rhoj = (DIM == 3) ? nb.B.x : nb.b.z;
+    const T pj = (DIM == 3) ? nb.B.y : nb.b.w;
+    const T rbrj = (DIM == 3) ? nb.B.z : nb.A.w;
     const T cA = c.cA, cD = c.cD;
     const T Vk = K.V, rbk = K.rb, rhok = K.rho;
     T u[3];
@@ -1719,7 +1726,7 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
             nb[u].a = ldo(jd0, j);
             nb[u].b = ldo(jd1, j);
             nb[u].A = ldo(jdA, j);
-            nb[u].B = ldo(jdB, j);
+            if (DIM == 3) nb[u].B = ldo(jdB, j);
             if (RENORM) nb[u].G = ldo(jdG, j);
         }
         load_entries<LPP, U>(row, r, m0 + U, mcount, (int)k, jn);
@@ -1810,7 +1817,7 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
         if (DIM == 3) {
             a.x = ab[0] * ir; a.y = ab[1] * ir; a.z = ab[2] * ir; a.w = rb;
         } else {
-            a.x = ab[0] * ir; a.y = ab[1] * ir; a.z = rb; a.w = T(0);
+            a.x = ab[0] * ir; a.y = ab[1] * ir; a.z = rb; a.w = rb * rho;
         }
         na.jdA[k] = a;
         vec4_t<T> b;
