@@ -200,6 +200,15 @@ template <> __device__ __forceinline__ float fast_rcp<float>(float x) { return _
 template <typename T> __device__ __forceinline__ T fast_sqrt(T x) { return sqrt(x); }
 template <> __device__ __forceinline__ float fast_sqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// Volume of a particle from its position record.  The 2D record (u, V, p V) holds it; the 3D
+// record (u, rho) holds the density, and V = m / rho is recomputed with the arithmetic of the
+// kernel that wrote the record, so it is the value that kernel had.
+template <typename T, int DIM>
+__device__ __forceinline__ T rec_volume(const vec4_t<T>& a, T m)
+{
+    return DIM == 3 ? m * fast_rcp(a.w) : a.z;
+}
+
 template <typename T>
 __device__ __forceinline__ T tait(const SimConst<T>& S, T rho)
 {
@@ -426,8 +435,8 @@ __global__ __launch_bounds__(256) void k_order_gather(int64_t N, const int32_t* 
     const T pV = pr * V;
     vec4_t<T> a, b;
     if (DIM == 3) {
-        a.x = u[0]; a.y = u[1]; a.z = u[2]; a.w = V;
-        b.x = v[0]; b.y = v[1]; b.z = v[2]; b.w = pV;
+        a.x = u[0]; a.y = u[1]; a.z = u[2]; a.w = rho;
+        b.x = v[0]; b.y = v[1]; b.z = v[2]; b.w = pr;
     } else {
         a.x = u[0]; a.y = u[1]; a.z = V; a.w = pV;
         b.x = v[0]; b.y = v[1]; b.z = rho; b.w = pr;
@@ -469,8 +478,8 @@ __global__ __launch_bounds__(256) void k_repack(int64_t N, const int32_t* __rest
     const T pV = pr * V;
     vec4_t<T> a, b;
     if (DIM == 3) {
-        a.x = u[0]; a.y = u[1]; a.z = u[2]; a.w = V;
-        b.x = v[0]; b.y = v[1]; b.z = v[2]; b.w = pV;
+        a.x = u[0]; a.y = u[1]; a.z = u[2]; a.w = rho;
+        b.x = v[0]; b.y = v[1]; b.z = v[2]; b.w = pr;
     } else {
         a.x = u[0]; a.y = u[1]; a.z = V; a.w = pV;
         b.x = v[0]; b.y = v[1]; b.z = rho; b.w = pr;
@@ -746,6 +755,7 @@ template <typename T>
 struct PairConst {
     T L, invL, invH, kG, kH, epsH2, cA, cD, H2;
     T kGF;  // kG (-56/3): grad W = kGF t^5 (1 + 5 q) x_ij
+    T m;    // particle mass
 };
 
 // Squared distance of a listed pair with the arithmetic of the neighbour predicate (per
@@ -797,6 +807,7 @@ __device__ __forceinline__ PairConst<T> pair_const(const SimConst<T>& S)
     c.cD = S.cD;
     c.H2 = S.H2;
     c.kGF = S.kG * T(-56.0 / 3.0);
+    c.m = S.m;
     return c;
 }
 
@@ -903,7 +914,7 @@ __global__ __launch_bounds__(256) void k_renorm(int64_t N, int32_t width, const 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             a[u] = ldo(jd0, (uint32_t)jn[u]);
-            rj[u] = (DIM == 3) ? ldo(rho3, (uint32_t)jn[u]) : ldo(jd1, (uint32_t)jn[u]).z;
+            rj[u] = (DIM == 3) ? a[u].w : ldo(jd1, (uint32_t)jn[u]).z;
         }
         load_entries<LPP, U>(row, r, m0 + U, mcount, (int)i, jn);
 #pragma unroll
@@ -916,7 +927,7 @@ __global__ __launch_bounds__(256) void k_renorm(int64_t N, int32_t width, const 
             const T tt = T(1) - q;
             const T t2 = tt * tt;
             const T gF = c.kG * (T(-56.0 / 3.0) * (t2 * t2 * tt) * (T(1) + T(5) * q));
-            const T Vj = (DIM == 3) ? a[u].w : a[u].z;
+            const T Vj = rec_volume<T, DIM>(a[u], S.m);
             const T f = Vj * gF;
             RenormAcc<T, DIM>& A = acc[u % NQ];
             if (DIM == 2) {
@@ -978,19 +989,20 @@ struct FwdAcc {
     T rdv, rdd, rs, rdg;
 };
 
-// Per-particle sweep record of a neighbour (jd0, jd1, and rho in 3D).
+// Per-particle sweep record of a neighbour (jd0, jd1; G with the renormalised diffusion).
 template <typename T, int DIM>
 struct FwdNbr {
     vec4_t<T> a, b, G;
-    T rho;
 };
 
 // Forward pair terms of (i, j), added to acc:
 //   a_i    += ((alpha H c0 rho0 pi_ij - p_i) V_j - p_j V_j) gW
 //   drho_i += V_j (v_i - v_j).gW     (times rho_i later)   and   V_j (rho_i - rho_j) x_ij.gW / (r^2 + eps H^2)
 //   rho_i  += W shape (times m C_d / H^d later)
-// In 3D jd0 = (u, V), jd1 = (v, p V) and rho comes separately; in 2D jd0 = (u, V, p V) and
-// jd1 = (v, rho, p).  d and r2 are the pair vector x_ij and its square; with keep false the
+// In 3D jd0 = (u, rho) and jd1 = (v, p), with V = m / rho recomputed as the writer computed it;
+// in 2D jd0 = (u, V, p V) and jd1 = (v, rho, p).  Two records per neighbour either way, since
+// the sweeps are bound by the vector L1's line rate, which counts gathers, not arithmetic.
+// d and r2 are the pair vector x_ij and its square; with keep false the
 // pair is computed but leaves acc unchanged (a select, not a branch).
 template <typename T, int DIM, bool RHOSUM, bool RENORM>
 __device__ __forceinline__ void fwd_pair(const PairConst<T>& c, const T* vi, T rhoi, T pi, const FwdNbr<T, DIM>& nb,
@@ -999,9 +1011,9 @@ __device__ __forceinline__ void fwd_pair(const PairConst<T>& c, const T* vi, T r
     T vj[3];
     T Vj, pVj, rhoj;
     if (DIM == 3) {
-        Vj = nb.a.w;
-        vj[0] = nb.b.x; vj[1] = nb.b.y; vj[2] = nb.b.z; pVj = nb.b.w;
-        rhoj = nb.rho;
+        rhoj = nb.a.w;
+        Vj = c.m * fast_rcp(rhoj);
+        vj[0] = nb.b.x; vj[1] = nb.b.y; vj[2] = nb.b.z; pVj = nb.b.w * Vj;
     } else {
         Vj = nb.a.z; pVj = nb.a.w;
         vj[0] = nb.b.x; vj[1] = nb.b.y; rhoj = nb.b.z;
@@ -1119,7 +1131,6 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
             const uint32_t j = (uint32_t)jj[u];
             nb[u].a = ldo(jd0, j);
             nb[u].b = ldo(jd1, j);
-            nb[u].rho = (DIM == 3) ? ldo(cur.rho, j) : T(0);
             if (RENORM) nb[u].G = ldo(jdG, j);
         }
         if (kSelect) load_entries_clamped<LPP, U>(row, width, r, m0 + U, mcount, (int)i, jn);
@@ -1200,8 +1211,8 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
             const T pV = pn * V;
             vec4_t<T> pa, pb;
             if (DIM == 3) {
-                pa.x = u[0]; pa.y = u[1]; pa.z = u[2]; pa.w = V;
-                pb.x = vn[0]; pb.y = vn[1]; pb.z = vn[2]; pb.w = pV;
+                pa.x = u[0]; pa.y = u[1]; pa.z = u[2]; pa.w = rhon;
+                pb.x = vn[0]; pb.y = vn[1]; pb.z = vn[2]; pb.w = pn;
             } else {
                 pa.x = u[0]; pa.y = u[1]; pa.z = V; pa.w = pV;
                 pb.x = vn[0]; pb.y = vn[1]; pb.z = rhon; pb.w = pn;
@@ -1542,13 +1553,14 @@ struct AdjAcc {
     T Gb[3];   // cotangent of the renormalised density gradient
 };
 
-// Per-particle adjoint record of a neighbour: jd0 = (u, V), jd1 = (v, p V), jdA = (abar / rho, rbar),
-// jdB = (rho, p, rbar rho, dp/drho).  In 2D jd0 = (u, V, p V), jd1 = (v, rho, p) and
-// jdA = (abar / rho, rbar, rbar rho) hold everything a neighbour contributes, so the 2D sweep
-// gathers three records per neighbour and reads jdB for its own particle only.
+// Per-particle adjoint record of a neighbour: jd0 = (u, rho), jd1 = (v, p), jdA = (abar / rho, rbar)
+// in 3D; jd0 = (u, V, p V), jd1 = (v, rho, p), jdA = (abar / rho, rbar, rbar rho) in 2D.  They
+// hold everything a neighbour contributes (3D: V = m / rho and rbar rho recomputed), so the
+// sweep gathers three records per neighbour; jdB = (rho, p, rbar rho, dp/drho) is read for the
+// particle itself only.
 template <typename T>
 struct AdjNbr {
-    vec4_t<T> a, b, A, B, G;
+    vec4_t<T> a, b, A, G;
 };
 
 // Adjoint pair terms, gather form.  For particle k and a neighbour j != k: the partial
@@ -1579,7 +1591,7 @@ __device__ __forceinline__ void adj_pair(const PairConst<T>& c, const AdjSelf<T>
     T vj[3], aj[3];
     T Vj, rbj;
     if (DIM == 3) {
-        Vj = nb.a.w;
+        Vj = c.m * fast_rcp(nb.a.w);
         vj[0] = nb.b.x; vj[1] = nb.b.y; vj[2] = nb.b.z;
         aj[0] = nb.A.x; aj[1] = nb.A.y; aj[2] = nb.A.z; rbj = nb.A.w;
     } else {
@@ -1587,9 +1599,9 @@ __device__ __forceinline__ void adj_pair(const PairConst<T>& c, const AdjSelf<T>
         vj[0] = nb.b.x; vj[1] = nb.b.y;
         aj[0] = nb.A.x; aj[1] = nb.A.y; rbj = nb.A.z;
     }
-    const T rhoj = (DIM == 3) ? nb.B.x : nb.b.z;
-    const T pj = (DIM == 3) ? nb.B.y : nb.b.w;
-    const T rbrj = (DIM == 3) ? nb.B.z : nb.A.w;
+    const T rhoj = (DIM == 3) ? nb.a.w : nb.b.z;
+    const T pj = nb.b.w;
+    const T rbrj = (DIM == 3) ? rbj * rhoj : nb.A.w;
     const T cA = c.cA, cD = c.cD;
     const T Vk = K.V, rbk = K.rb, rhok = K.rho;
     T u[3];
@@ -1681,7 +1693,7 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
         const vec4_t<T> a = jd0[k], b = jd1[k], A = jdA[k];
         K.v[2] = K.a[2] = T(0);
         if (DIM == 3) {
-            uk[0] = a.x; uk[1] = a.y; uk[2] = a.z; K.V = a.w;
+            uk[0] = a.x; uk[1] = a.y; uk[2] = a.z; K.V = S.m * fast_rcp(a.w);
             K.v[0] = b.x; K.v[1] = b.y; K.v[2] = b.z;
             K.a[0] = A.x; K.a[1] = A.y; K.a[2] = A.z; K.rb = A.w;
         } else {
@@ -1726,7 +1738,6 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
             nb[u].a = ldo(jd0, j);
             nb[u].b = ldo(jd1, j);
             nb[u].A = ldo(jdA, j);
-            if (DIM == 3) nb[u].B = ldo(jdB, j);
             if (RENORM) nb[u].G = ldo(jdG, j);
         }
         load_entries<LPP, U>(row, r, m0 + U, mcount, (int)k, jn);
@@ -1860,7 +1871,7 @@ __global__ __launch_bounds__(256) void k_renorm_adj(int64_t N, int32_t width, co
     const vec4_t<T> a0 = jd0[k];
     T uk[3] = {0, 0, 0};
     unpack_u<T, DIM>(a0, uk);
-    const T Vk = (DIM == 3) ? a0.w : a0.z;
+    const T Vk = rec_volume<T, DIM>(a0, S.m);
     const T rhok = jdB[k].x;
     const vec4_t<T> g4 = jdG[k], b4 = gbar[k];
     const T Gk[3] = {g4.x, g4.y, g4.z}, bk[3] = {b4.x, b4.y, b4.z};
@@ -1896,7 +1907,7 @@ __global__ __launch_bounds__(256) void k_renorm_adj(int64_t N, int32_t width, co
             const T t4 = t2 * t2;
             const T gF = c.kG * (T(-56.0 / 3.0) * t4 * tt * (T(1) + T(5) * q));
             const T hF = c.kH * t4;
-            const T Vj = (DIM == 3) ? na[u].w : na[u].z;
+            const T Vj = rec_volume<T, DIM>(na[u], S.m);
             const T rhoj = nB[u].x;
             const T Gj[3] = {nG[u].x, nG[u].y, nG[u].z}, bj[3] = {nb[u].x, nb[u].y, nb[u].z};
             T bke = 0, bje = 0, Gke = 0, Gje = 0;
@@ -1992,7 +2003,7 @@ __global__ __launch_bounds__(256) void k_shift(int64_t N, int32_t width, const i
             const T wr = S.kW * t4 * t2 * (T(1) + q * (T(6) + q * T(35.0 / 3.0))) * S.invW0;   // W / W(dx)
             const T w2 = wr * wr;
             const T phi = T(1) + T(kShiftR) * w2 * w2;
-            const T f = phi * ((DIM == 3) ? a[u].w : a[u].z) * gF;
+            const T f = phi * rec_volume<T, DIM>(a[u], S.m) * gF;
 #pragma unroll
             for (int k = 0; k < DIM; ++k) acc[u % NQ][k] += f * d[k];
         }
@@ -2053,7 +2064,7 @@ __global__ __launch_bounds__(256) void k_shift_adj(int64_t N, int32_t width, con
     const vec4_t<T> a0 = jd0[k];
     T uk[3] = {0, 0, 0};
     unpack_u<T, DIM>(a0, uk);
-    const T Vk = (DIM == 3) ? a0.w : a0.z;
+    const T Vk = rec_volume<T, DIM>(a0, S.m);
     const vec4_t<T> xk4 = xs[k];
     const T xbk[3] = {xk4.x, xk4.y, xk4.z};
     int n = nbr_count[k];
@@ -2089,7 +2100,7 @@ __global__ __launch_bounds__(256) void k_shift_adj(int64_t N, int32_t width, con
             const T w2 = wr * wr;
             const T phi = T(1) + T(kShiftR) * w2 * w2;
             const T dphi = T(4.0 * kShiftR) * w2 * wr * S.invW0;
-            const T Vj = (DIM == 3) ? a[u].w : a[u].z;
+            const T Vj = rec_volume<T, DIM>(a[u], S.m);
             const T xbj[3] = {b[u].x, b[u].y, b[u].z};
             // z = V_j xb_k - V_k xb_j;  D z = phi (gF z + hF (e.z) e) + dphi gF^2 (e.z) e
             T z[3], ez = T(0), exj = T(0);
