@@ -750,6 +750,42 @@ __device__ __forceinline__ void load_entries_clamped(const int32_t* __restrict__
 
 
 
+// Four lanes per particle (adjoint sweep): each group of 16 list positions (16 g .. 16 g + 15,
+// four per lane) is read as four 16-byte chunks, lane r reading positions 16 g + 4 r .. + 3, and
+// a 4 x 4 transpose inside the lane quad gives lane r its positions r + 4 c (c = 0..3), the ones
+// the canonical assignment gives it: one load instead of four.
+// The chunk start is clamped to the row (width is a multiple of 8), so a chunk past the row end
+// rereads its last chunk, whose positions the caller discards.  A lane leaves the loop after its
+// own last position; the values it would pass to the lanes still looping are positions at or
+// past the row's count (lane c stops once 4 c + 16 g >= count), which those lanes discard too.
+__device__ __forceinline__ int4 load_chunk4(const int32_t* __restrict__ row, int width, int pos)
+{
+    pos = pos < width - 4 ? pos : width - 4;
+    return *reinterpret_cast<const int4*>(row + pos);
+}
+
+template <int CTRL>
+__device__ __forceinline__ int quad_perm(int v)
+{
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
+}
+
+__device__ __forceinline__ void quad_transpose(int r, const int4& m, int* out)
+{
+    const bool hi = (r & 2) != 0, odd = (r & 1) != 0;
+    // exchange 2 x 2 blocks with lane r ^ 2 (quad permutation 2, 3, 0, 1)
+    const int y0 = quad_perm<0x4E>(hi ? m.x : m.z);
+    const int y1 = quad_perm<0x4E>(hi ? m.y : m.w);
+    const int n0 = hi ? y0 : m.x, n1 = hi ? y1 : m.y, n2 = hi ? m.z : y0, n3 = hi ? m.w : y1;
+    // exchange single elements with lane r ^ 1 (quad permutation 1, 0, 3, 2)
+    const int z0 = quad_perm<0xB1>(odd ? n0 : n1);
+    const int z1 = quad_perm<0xB1>(odd ? n2 : n3);
+    out[0] = odd ? z0 : n0;
+    out[1] = odd ? n1 : z0;
+    out[2] = odd ? z1 : n2;
+    out[3] = odd ? n3 : z1;
+}
+
 // Per-simulation constants the pair loops use, held in registers.
 template <typename T>
 struct PairConst {
@@ -1586,7 +1622,7 @@ struct AdjSelf {
 
 template <typename T, int DIM, bool RENORM>
 __device__ __forceinline__ void adj_pair(const PairConst<T>& c, const AdjSelf<T>& K, const AdjNbr<T>& nb,
-                                         const T* e, T r2, AdjAcc<T, DIM>& acc)
+                                         const T* e, T r2, bool keep, AdjAcc<T, DIM>& acc)
 {
     T vj[3], aj[3];
     T Vj, rbj;
@@ -1638,12 +1674,13 @@ __device__ __forceinline__ void adj_pair(const PairConst<T>& c, const AdjSelf<T>
     const T ce = cdr - T(2) * beta * pij + hF * ew;  // coefficient of e in the position cotangent
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-        acc.gx[k] += beta * u[k] + ce * e[k] + gF * w[k];
-        acc.gv[k] += (beta + gam * gF) * e[k];
+        acc.gx[k] = keep ? acc.gx[k] + (beta * u[k] + ce * e[k] + gF * w[k]) : acc.gx[k];
+        acc.gv[k] = keep ? acc.gv[k] + (beta + gam * gF) * e[k] : acc.gv[k];
     }
     const T phi2 = Vk * (-X * aGj + rbrj * uG + rbj * cD * (rhoj - rhok) * sij);
-    acc.gr += Vj * (aGk * (-K.dp - X * K.ir) + rbk * uG + rbk * cD * sij) - phi2 * K.ir +
-              Vk * (aGj * K.dp - rbj * cD * sij);
+    const T dgr = Vj * (aGk * (-K.dp - X * K.ir) + rbk * uG + rbk * cD * sij) - phi2 * K.ir +
+                  Vk * (aGj * K.dp - rbj * cD * sij);
+    acc.gr = keep ? acc.gr + dgr : acc.gr;
     if (RENORM) {
         const T cr = T(-0.5) * cD;
         const T Gj[3] = {nb.G.x, nb.G.y, nb.G.z};
@@ -1656,10 +1693,10 @@ __device__ __forceinline__ void adj_pair(const PairConst<T>& c, const AdjSelf<T>
         const T qq = cr * (rbk * Vj - rbj * Vk);
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
-            acc.gx[k] += qq * (gF * sv[k] + hF * es * e[k]);
-            acc.Gb[k] += qq * gF * e[k];
+            acc.gx[k] = keep ? acc.gx[k] + qq * (gF * sv[k] + hF * es * e[k]) : acc.gx[k];
+            acc.Gb[k] = keep ? acc.Gb[k] + qq * gF * e[k] : acc.Gb[k];
         }
-        acc.gr += Vk * K.ir * cr * rbj * gF * es;
+        acc.gr = keep ? acc.gr + Vk * K.ir * cr * rbj * gF * es : acc.gr;
     }
 }
 
@@ -1729,8 +1766,17 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
         acc[q].gr = T(0);
     }
     int jn[U];
-    load_entries<LPP, U>(row, r, 0, mcount, (int)k, jn);
+    int4 chunk = make_int4(0, 0, 0, 0);
+    constexpr bool kQuad = LPP == 4 && U == 4;
+    if (kQuad) chunk = load_chunk4(row, width, 4 * r);
+    else load_entries<LPP, U>(row, r, 0, mcount, (int)k, jn);
     for (int m0 = 0; m0 < mcount; m0 += U) {
+        if (kQuad) {
+            int t4[4];
+            quad_transpose(r, chunk, t4);
+#pragma unroll
+            for (int u = 0; u < U; ++u) jn[u] = (m0 + u < mcount) ? t4[u] : (int)k;
+        }
         AdjNbr<T> nb[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1740,14 +1786,18 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
             nb[u].A = ldo(jdA, j);
             if (RENORM) nb[u].G = ldo(jdG, j);
         }
-        load_entries<LPP, U>(row, r, m0 + U, mcount, (int)k, jn);
+        if (kQuad) chunk = load_chunk4(row, width, 4 * (m0 + U) + 4 * r);
+        else load_entries<LPP, U>(row, r, m0 + U, mcount, (int)k, jn);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (m0 + u >= mcount) continue;
+            // position m0 is below the count inside the loop; its pair is dropped by a select
+            // rather than a branch, which keeps its gathers ahead of the pair terms
+            if (u > 0 && m0 + u >= mcount) continue;
             T e[3];
             const T r2 = r2_exact<T, DIM>(uk, nb[u].a, c.L, c.invL, e);
-            if (filter && !(r2 < c.H2)) continue;
-            adj_pair<T, DIM, RENORM>(c, K, nb[u], e, r2, acc[u % NQ]);
+            const bool keep = !filter || r2 < c.H2;
+            if (u > 0 && !keep) continue;
+            adj_pair<T, DIM, RENORM>(c, K, nb[u], e, r2, keep, acc[u % NQ]);
         }
     }
     T gx[3] = {0, 0, 0}, gv[3] = {0, 0, 0};
