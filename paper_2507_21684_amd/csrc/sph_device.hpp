@@ -65,12 +65,28 @@ constexpr int32_t kStencilIdMask = (1 << kStencilIdBits) - 1;
 // cell at coordinates cc of simulation S, as a stencil entry.  Cells are numbered block-major:
 // blocks of B^dim cells in Morton order (blk_rank maps a row-major block index to its rank),
 // cells row-major inside a block.
+// Cells per block side: 4 in 2D, 2 in 3D (the host sets SimConst::B to the same values).
+template <int DIM>
+constexpr int kBlockSide = DIM == 3 ? 2 : 4;
+
+// Offsets (x, y, z) of stencil cell u for a stencil of SW cells per side (SW = 2 sub + 1 = 3 or
+// 5, a constant here so that the divisions are multiplications).
+template <int DIM, int SW>
+__device__ __forceinline__ void stencil_offsets(int u, int sub, int* o)
+{
+    const unsigned v = (unsigned)u;
+    o[0] = (int)(v % SW) - sub;
+    o[1] = (int)((v / SW) % SW) - sub;
+    o[2] = (DIM == 3) ? (int)(v / (SW * SW)) - sub : 0;
+}
+
 template <int DIM, typename T>
 __device__ __forceinline__ int32_t stencil_entry(const SimConst<T>& S, const int32_t* __restrict__ blk_rank,
                                                  const int* cc, int u)
 {
-    const int sw = 2 * S.sub + 1;
-    const int o[3] = {u % sw - S.sub, (u / sw) % sw - S.sub, (DIM == 3) ? u / (sw * sw) - S.sub : 0};
+    int o[3];
+    if (S.sub == 2) stencil_offsets<DIM, 5>(u, 2, o);
+    else stencil_offsets<DIM, 3>(u, 1, o);
     int c[3] = {0, 0, 0}, sh[3] = {0, 0, 0};
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
@@ -84,13 +100,13 @@ __device__ __forceinline__ int32_t stencil_entry(const SimConst<T>& S, const int
         }
         c[k] = r;
     }
-    const int B = S.B;
-    const int bx = c[0] / B, by = c[1] / B, bz = (DIM == 3) ? c[2] / B : 0;
+    constexpr unsigned B = kBlockSide<DIM>;
+    const int bx = (int)((unsigned)c[0] / B), by = (int)((unsigned)c[1] / B), bz = (DIM == 3) ? (int)((unsigned)c[2] / B) : 0;
     const int lin = (DIM == 3) ? (bz * S.nb + by) * S.nb + bx : by * S.nb + bx;
     const int rk = blk_rank[S.blk0 + lin];
     const int wl = (DIM == 3) ? ((c[2] - bz * B) * B + (c[1] - by * B)) * B + (c[0] - bx * B)
                               : (c[1] - by * B) * B + (c[0] - bx * B);
-    const int id = S.cell0 + rk * S.Bd + wl;
+    const int id = S.cell0 + rk * (DIM == 3 ? B * B * B : B * B) + wl;
     return id | ((sh[0] + 1) << kStencilIdBits) | ((sh[1] + 1) << (kStencilIdBits + 2)) |
            ((sh[2] + 1) << (kStencilIdBits + 4));
 }
@@ -166,12 +182,13 @@ template <typename T, int DIM>
 __device__ __forceinline__ int global_cell(const SimConst<T>& S, const int32_t* __restrict__ blk_rank, int cx, int cy,
                                            int cz)
 {
-    int bx = cx / S.B, by = cy / S.B, bz = (DIM == 3) ? cz / S.B : 0;
-    int wx = cx - bx * S.B, wy = cy - by * S.B, wz = (DIM == 3) ? cz - bz * S.B : 0;
+    constexpr int B = kBlockSide<DIM>;
+    int bx = (int)((unsigned)cx / B), by = (int)((unsigned)cy / B), bz = (DIM == 3) ? (int)((unsigned)cz / B) : 0;
+    int wx = cx - bx * B, wy = cy - by * B, wz = (DIM == 3) ? cz - bz * B : 0;
     int lin = (DIM == 3) ? ((bz * S.nb + by) * S.nb + bx) : (by * S.nb + bx);
     int rank = blk_rank[S.blk0 + lin];
-    int w = (DIM == 3) ? ((wz * S.B + wy) * S.B + wx) : (wy * S.B + wx);
-    return S.cell0 + rank * S.Bd + w;
+    int w = (DIM == 3) ? ((wz * B + wy) * B + wx) : (wy * B + wx);
+    return S.cell0 + rank * (DIM == 3 ? B * B * B : B * B) + w;
 }
 
 // r^2 of the minimum-image pair vector, every operation rounded in T (no contraction):
@@ -583,17 +600,20 @@ __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ c
     // the cell's coordinates from its block and its place inside the block
     int cc[3];
     {
-        const int local = gc - S.cell0;
-        const int rank = local / S.Bd, w = local - rank * S.Bd;
+        constexpr unsigned B = kBlockSide<DIM>, Bd = DIM == 3 ? B * B * B : B * B;
+        const unsigned local = (unsigned)(gc - S.cell0);
+        const int rank = (int)(local / Bd);
+        const unsigned w = local % Bd;
         const int coord = blk_coord[S.blk0 + rank];
-        cc[0] = (coord & 1023) * S.B + w % S.B;
-        cc[1] = ((coord >> 10) & 1023) * S.B + (w / S.B) % S.B;
-        cc[2] = (DIM == 3) ? ((coord >> 20) & 1023) * S.B + w / (S.B * S.B) : 0;
+        cc[0] = (coord & 1023) * (int)B + (int)(w % B);
+        cc[1] = ((coord >> 10) & 1023) * (int)B + (int)((w / B) % B);
+        cc[2] = (DIM == 3) ? ((coord >> 20) & 1023) * (int)B + (int)(w / (B * B)) : 0;
     }
 
     // stencil cells: particle range and periodic image code, two per lane at most
     int carry = 0;
-    for (int half = 0; half < 2; ++half) {
+    const int halves = ncu > 64 ? 2 : 1;
+    for (int half = 0; half < halves; ++half) {
         const int u = lane + 64 * half;
         int first = 0, count = 0, code = 0;
         if (u < ncu) {
