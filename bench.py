@@ -805,6 +805,8 @@ def main():
     ap.add_argument("--workload", default="batched_512_tgv2d_f32", choices=sorted(workloads()))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-legs", action="store_true", help="only the headline workload and its plain path")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain path of a batched workload (kernel traces of the batch alone)")
     ap.add_argument("--serving", type=int, default=1000, help="requests of the served workload (0 skips it)")
     ap.add_argument("--serving-warmup", type=int, default=50, help="requests left out of the latency percentiles")
     ap.add_argument("--counter-pass", action="store_true",
@@ -847,7 +849,7 @@ def main():
     torch.cuda.empty_cache()
 
     latency = None
-    if len(wl.sims) > 1:
+    if len(wl.sims) > 1 and not args.no_plain:
         log("plain path: one plan per simulation, run in turn")
         t_plain, lat_plain = plain_path(dev, wl, x0, v0, r0, skins, R)
         work = head["config"]["pairs_fwd"] + head["config"]["pairs_adj"]

@@ -282,16 +282,19 @@ def test_full_size_bench_config_sampled(orc, dim, side, skin, R, lanes):
     assert np.all(plan.poll() == 0)
 
 
-@pytest.mark.parametrize("dim,side", [(2, 40), (3, 14)])
-def test_lanes_per_particle_bitwise(dim, side):
-    """The sweeps give bitwise identical results for 2, 4 and 8 lanes per particle."""
+@pytest.mark.parametrize("dim,side,skin,R", [(2, 40, 0.0, 1), (3, 14, 0.0, 1), (2, 40, 0.25, 3), (3, 14, 0.15, 3)])
+def test_lanes_per_particle_bitwise(dim, side, skin, R):
+    """The sweeps give bitwise identical results for 2, 4 and 8 lanes per particle, with exact
+    lists and with skinned lists that the sweeps filter (four lanes take the adjoint's list entries
+    as quad chunks and drop a group's first rejected pair by a select, the others by loads and
+    branches per entry)."""
     spec = SimSpec(dim, side, jitter=0.2)
     st = _inputs(spec, 21, "f32", rho_noise=0.01, v_noise=0.2)
     rng = np.random.default_rng(22)
     cot = [rng.normal(size=a.shape).astype(np.float32) for a in st]
     outs = []
     for lanes in (2, 4, 8):
-        plan = _plan([spec], "f32")
+        plan = _plan([spec], "f32", skin=skin, rebuild_every=R)
         plan.set_tuning(lanes, lanes)
         g = _to_gpu(st, "f32")
         rhs = [t.cpu().numpy() for t in plan.rhs(*g)]
