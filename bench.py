@@ -331,7 +331,7 @@ def plain_path(dev, wl, x0, v0, r0, skins, R):
         st = (x0[:, offs[k]:offs[k + 1]].contiguous(), v0[:, offs[k]:offs[k + 1]].contiguous(),
               r0[offs[k]:offs[k + 1]].contiguous())
         p = Plan([s.params()], [s.n], wl.dtype, tape_depth=max(wl.ckpt_every, wl.tape), device=dev, skin=skins[k],
-                 rebuild_every=R)
+                 rebuild_every=R, speed_skins=R > 1)
         autotune.tune(p, *st)
         run_job(p, *st, sub)
         plains.append((p, sub, st))
@@ -499,7 +499,7 @@ def bench_renorm(dev, wl, x0, v0, r0, skin, R, lanes, ms_plain, pairs, reps=3):
     import torch
     from paper_2507_21684_amd.lib import Plan
     plan = Plan([s.params() for s in wl.sims], [s.n for s in wl.sims], wl.dtype, tape_depth=wl.ckpt_every,
-                device=dev, skin=skin, rebuild_every=R, renormalised_diffusion=True)
+                device=dev, skin=skin, rebuild_every=R, renormalised_diffusion=True, speed_skins=R > 1)
     plan.set_tuning(*lanes)
     run_job(plan, x0, v0, r0, wl)
     torch.cuda.synchronize()
@@ -595,7 +595,7 @@ def bench_graphs(dev, name, skins, R, lanes, reps=5):
     wl = workloads()[name]()
     _, (x0, v0, r0) = packed_inputs(wl, dev)
     plan = Plan([s.params() for s in wl.sims], [s.n for s in wl.sims], wl.dtype,
-                tape_depth=max(wl.ckpt_every, wl.tape), device=dev, skin=skins, rebuild_every=R)
+                tape_depth=max(wl.ckpt_every, wl.tape), device=dev, skin=skins, rebuild_every=R, speed_skins=R > 1)
     plan.set_tuning(*lanes)
     T, K = wl.steps, wl.ckpt_every
     x, v, r = plan.empty_state()
@@ -770,6 +770,7 @@ def measure_workload(name, dev, reps, warmup):
         config["list_skin_range"] = [round(min(plan.skins), 4), round(max(plan.skins), 4)]
     else:
         config["list_skin"] = round(plan.skin, 4)
+    config["half_skins"] = "speed-scaled" if plan.speed_skins else "uniform"
     res = {"workload": wl.name, "value": round((p_fwd + p_adj) * reps / elapsed, 1), "unit": "pair interactions/s",
            "ms_per_job": round(ms, 3), "timed_jobs": reps, "dtype": wl.dtype, "config": config, "roofline": roof,
            "kernel_ms_per_job": breakdown}

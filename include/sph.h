@@ -64,9 +64,9 @@ typedef int32_t sph_status;
 /* per-simulation device status bits, read by sph_poll() */
 #define SPH_FLAG_NONFINITE 1
 #define SPH_FLAG_NEIGHBOR_OVERFLOW 2
-#define SPH_FLAG_SKIN 4 /* with list reuse: a particle moved more than half the skin since its
-                           lists were built, so a pair may be missing; rerun with a larger skin
-                           or a shorter reuse interval */
+#define SPH_FLAG_SKIN 4 /* with list reuse: a particle moved more than its half skin h_i (see
+                           sph_params.skin) since its lists were built, so a pair may be
+                           missing; rerun with a larger skin or a shorter reuse interval */
 
 #define SPH_F32 0
 #define SPH_F64 1
@@ -92,10 +92,12 @@ typedef struct sph_params {
     double alpha;     /* artificial-viscosity coefficient */
     double eps;       /* regulariser in 1/(r^2 + eps H^2) */
     double dt;        /* fixed time step */
-    double skin;      /* neighbour-list skin as a fraction of the support: lists hold the
-                         pairs with r < H (1 + skin) and the sweeps keep those with r < H;
-                         0 = lists of exactly the pairs with r < H.  Needs 2 H (1 + skin) < L.
-                         Cells are sized for the list radius. */
+    double skin;      /* neighbour-list skin as a fraction of the support.  Each particle
+                         gets a half skin h_i (skin H / 2, or less with speed-scaled skins,
+                         see sph_set_skin_mode), the lists hold the pairs with
+                         r < H + h_i + h_j <= H (1 + skin), and the sweeps keep those with
+                         r < H; 0 = lists of exactly the pairs with r < H.  Needs
+                         2 H (1 + skin) < L.  Cells are sized for H (1 + skin). */
 } sph_params;
 
 /* Device pointers to one packed state in the plan's dtype.  Entries k >= dim
@@ -153,7 +155,7 @@ sph_status sph_get_tuning(const sph_plan* plan, int32_t* lanes_fwd, int32_t* lan
  * lists.  With a skin in the plan's parameters only the first stage of a step
  * sorts and builds; the later stages are gathered into its particle order, use
  * its lists filtered to r < H (so every stage still evaluates exactly its own
- * pair set), and set SPH_FLAG_SKIN when a particle moved more than half the
+ * pair set), and set SPH_FLAG_SKIN when a particle moved more than its half
  * skin since the build.  The reuse interval of sph_set_reuse applies to the
  * semi-implicit Euler step only.  sph_step, sph_step_adjoint and
  * sph_rollout_backward then use the scheme; the adjoint reverses the stages
@@ -172,7 +174,7 @@ sph_status sph_set_integrator(sph_plan* plan, int32_t stages, const double* A, c
  * each evaluation of f with its own sort and neighbour lists; with a list
  * skin, a corrector that follows an evaluation of f(u) in the same step keeps
  * that evaluation's particle order and lists (filtered to r < H, displacement
- * checked against half the skin as for Runge-Kutta stages).  With
+ * checked against each particle's half skin as for Runge-Kutta stages).  With
  * reuse_last_substep != 0, the predictor takes the previous step's corrector
  * rates (a2, D2) instead of evaluating f(u) (the modified scheme of Sec. 3.4 /
  * App. C that re-uses the last substep's update values): one evaluation of f
@@ -225,7 +227,8 @@ sph_status sph_shift_adjoint(sph_plan* plan, const sph_state* state, sph_state* 
  * lists of the last build, and their sweeps keep only the pairs with r < H, so
  * every step still evaluates exactly the pairs the method defines.  Each sweep
  * that hands its state to a reusing step checks every particle's displacement
- * since the build against skin H / 2 and sets SPH_FLAG_SKIN if it is exceeded.
+ * since the build against its half skin h_i (see sph_params.skin) and sets
+ * SPH_FLAG_SKIN if it is exceeded.
  * A call that spans more than one checkpoint interval needs the interval to be a
  * multiple of R (INVALID_ARG otherwise), so a backward recomputation, which starts
  * every segment with a build, follows the forward's build schedule exactly.  Results differ from R = 1 only
@@ -233,6 +236,23 @@ sph_status sph_shift_adjoint(sph_plan* plan, const sph_state* state, sph_state* 
  * independent of the batch.  Host-side setting; default 1.  INVALID_ARG for
  * R < 1, or R > 1 without a skin. */
 sph_status sph_set_reuse(sph_plan* plan, int32_t rebuild_every);
+
+/* Half skins of the lists a skin gives (not in the paper, which keeps one list
+ * radius; a choice of how many candidate pairs the lists carry).  Uniform
+ * (speed_scaled = 0, the default): every particle's half skin is h = skin H / 2.
+ * Speed-scaled (speed_scaled != 0): at each build particle i gets
+ *     h_i = min(skin H / 2, skin H / 16 + 1.3 R dt |v_i|)
+ * from its speed (R the reuse interval of sph_set_reuse, 1 by default, which also
+ * covers the stages of a Runge-Kutta or symplectic step), so slow particles carry
+ * shorter lists.  The
+ * skin H / 16 term is every particle's allowance for acceleration between
+ * builds; a skin sized as 2.6 v_max dt R / H for the simulation's largest speed
+ * v_max lets a particle at rest accelerate steadily to about a third of v_max.
+ * Either way the sweeps keep exactly the pairs with r < H, the displacement check
+ * uses each particle's own h_i (SPH_FLAG_SKIN), and results stay deterministic
+ * and independent of the batch; the two modes differ in summation order only.
+ * Host-side setting.  INVALID_ARG for speed_scaled != 0 without a skin. */
+sph_status sph_set_skin_mode(sph_plan* plan, int32_t speed_scaled);
 
 /* Graph mode (default off; host-side switch, no device work).  When on, every
  * sph_step and sph_rollout_backward call is issued as one executable HIP graph

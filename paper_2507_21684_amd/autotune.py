@@ -9,7 +9,9 @@
   reused for R steps save R - 1 of every R sorts and builds but hold more entries, which the
   sweeps filter back to r < H.  Half the skin must cover R steps of travel, so each
   simulation's skin is 2 x 1.3 x v_max dt R / H from the largest speed of its state (30 %
-  margin; the device flags any particle that moves farther).  `tune_plan` builds a plan per
+  margin), and the plans take speed-scaled half skins (sph_set_skin_mode): each particle's
+  list radius follows its own speed, with a floor for acceleration, and the device flags any
+  particle that moves farther than its own half skin.  `tune_plan` builds a plan per
   candidate R dividing the checkpoint interval, tunes its lanes, times one checkpoint segment
   forward and backward (with a tape as deep as the segment, so the backward runs on the
   forward's tape), discards candidates whose run raised a device flag, and returns the fastest
@@ -190,6 +192,12 @@ def _segment_seconds(plan: Plan, x, v, rho, K: int, reps: int = 3) -> Tuple[floa
     return best, status
 
 
+def _reuse_plan(sims, counts, dtype, depth: int, device, v, R: int) -> Plan:
+    """Plan rebuilding every R steps with skins from the state's speeds (speed-scaled half skins)."""
+    return Plan(sims, counts, dtype, tape_depth=depth, device=device, skin=skins_for(sims, counts, v, R),
+                rebuild_every=R, speed_skins=R > 1)
+
+
 def tune_plan(sims: Sequence[dict], counts: Sequence[int], dtype: str, ckpt_every: int, x, v, rho,
               device=None, use_cache: bool = True, choices=REBUILD_CHOICES, tape_depth: Optional[int] = None) -> Plan:
     """Plan with the fastest (rebuild interval, skins, lanes) for one checkpoint segment of this state.
@@ -198,21 +206,19 @@ def tune_plan(sims: Sequence[dict], counts: Sequence[int], dtype: str, ckpt_ever
     K = int(ckpt_every)
     depth = K if tape_depth is None else max(int(tape_depth), K)
     probe = Plan(sims, counts, dtype, tape_depth=K, device=device)
-    key = cache_key(probe) + ":K%d:reuse" % K
+    key = cache_key(probe) + ":K%d:reuse-speed" % K
     del probe
     table = _load() if use_cache else {}
     if key in table:
         R, lf, la = (int(t) for t in table[key][:3])
-        plan = Plan(sims, counts, dtype, tape_depth=depth, device=device, skin=skins_for(sims, counts, v, R),
-                    rebuild_every=R)
+        plan = _reuse_plan(sims, counts, dtype, depth, device, v, R)
         plan.set_tuning(lf, la)
         return plan
     best, trials = None, {}
     for R in choices:
         if K % R:
             continue
-        plan = Plan(sims, counts, dtype, tape_depth=K, device=device, skin=skins_for(sims, counts, v, R),
-                    rebuild_every=R)
+        plan = _reuse_plan(sims, counts, dtype, K, device, v, R)
         lf, la = tune(plan, x, v, rho, use_cache=False)
         secs, status = _segment_seconds(plan, x, v, rho, K)
         trials[str(R)] = [secs, status, lf, la, round(plan.skin, 4)]
@@ -225,7 +231,6 @@ def tune_plan(sims: Sequence[dict], counts: Sequence[int], dtype: str, ckpt_ever
     if use_cache:
         table[key] = [R, lf, la, trials]
         _store(table)
-    plan = Plan(sims, counts, dtype, tape_depth=depth, device=device, skin=skins_for(sims, counts, v, R),
-                rebuild_every=R)
+    plan = _reuse_plan(sims, counts, dtype, depth, device, v, R)
     plan.set_tuning(lf, la)
     return plan

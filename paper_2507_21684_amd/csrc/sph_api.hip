@@ -83,6 +83,7 @@ struct sph_plan {
     int32_t lpp_fwd = 4, lpp_adj = 4;
     bool filter = false;      // some simulation has a skin: sweeps keep only pairs with r < H
     int32_t reuse = 1;        // a step rebuilds the cell list and the lists every `reuse` steps
+    bool speed_skins = false; // per-particle half skins from the particles' speeds (else uniform)
     std::vector<int> list_of; // tape slot -> slot whose neighbour lists it uses
     // explicit Runge-Kutta tableau (0 stages: the semi-implicit Euler step)
     int32_t rk_stages = 0, rk_reserved = 0;
@@ -286,8 +287,7 @@ void fill_simconst(const sph_plan* P, std::vector<unsigned char>& out)
         {
             const T HL = (T)(q.support * (1.0 + q.skin));
             c.HL2 = HL * HL;
-            const double half = 0.5 * q.skin * q.support;
-            c.disp2 = (T)(half * half);
+            c.hmax = (T)(0.5 * q.skin * q.support);
         }
         {
             // 1 / W(dx) at the initial spacing dx = (m / rho0)^(1/d), for particle shifting
@@ -403,7 +403,9 @@ sph_status sort_into(sph_plan* P, StatePtrs<T, D> src, const int32_t* orig_in, i
     LAUNCH_CHECK("scatter");
     k_order_gather<T, D><<<g, 256, 0, st>>>(N, tmp, cell_of, cell_start, orig_in, src, ws_state<T, D>(P, L.SA),
                                             orig_out, wsp<vec4_t<T>>(P, L.jd0), wsp<vec4_t<T>>(P, L.jd1), psim,
-                                            simc, P->filter ? wsp<vec4_t<T>>(P, P->o_uref) : nullptr);
+                                            simc, P->filter ? wsp<vec4_t<T>>(P, P->o_uref) : nullptr,
+                                            (T)(P->speed_skins ? kSkinFloor : 1.0),
+                                            (T)(P->speed_skins ? kSkinMargin * P->reuse : 0.0));
     LAUNCH_CHECK("order_gather");
     return SPH_OK;
 }
@@ -421,12 +423,22 @@ sph_status build_lists(sph_plan* P, int slot, hipStream_t st, bool exact = false
     const SlotLayout& L = P->slot[slot];
     P->list_of[slot] = slot;
     ProfScope prof(P, st, SPH_KERN_BUILD, true);
-    launch_k(&prof, k_build_list<T, D>, dim3((unsigned)P->ncell), dim3(64), st,
-        wsp<int32_t>(P, P->o_cell_sim), wsp<int32_t>(P, P->o_blk_coord), wsp<int32_t>(P, P->o_blk_rank),
-        wsp<SimConst<T>>(P, P->o_simc),
-        wsp<int32_t>(P, P->o_cell_start), wsp<vec4_t<T>>(P, L.jd0), P->width,
-        wsp<int32_t>(P, L.nbr), wsp<int32_t>(P, L.cnt), status,
-        P->filter ? nullptr : wsp<unsigned long long>(P, P->o_pairs), exact ? 1 : 0);
+    // lists with speed-scaled skins use the half skins of the sort that preceded this build
+    if (P->filter && P->speed_skins && !exact)
+        launch_k(&prof, k_build_list<T, D, true>, dim3((unsigned)P->ncell), dim3(64), st,
+            wsp<int32_t>(P, P->o_cell_sim), wsp<int32_t>(P, P->o_blk_coord), wsp<int32_t>(P, P->o_blk_rank),
+            wsp<SimConst<T>>(P, P->o_simc),
+            wsp<int32_t>(P, P->o_cell_start), wsp<vec4_t<T>>(P, L.jd0), P->width,
+            wsp<int32_t>(P, L.nbr), wsp<int32_t>(P, L.cnt), status, (unsigned long long*)nullptr, 0,
+            (const vec4_t<T>*)wsp<vec4_t<T>>(P, P->o_uref));
+    else
+        launch_k(&prof, k_build_list<T, D, false>, dim3((unsigned)P->ncell), dim3(64), st,
+            wsp<int32_t>(P, P->o_cell_sim), wsp<int32_t>(P, P->o_blk_coord), wsp<int32_t>(P, P->o_blk_rank),
+            wsp<SimConst<T>>(P, P->o_simc),
+            wsp<int32_t>(P, P->o_cell_start), wsp<vec4_t<T>>(P, L.jd0), P->width,
+            wsp<int32_t>(P, L.nbr), wsp<int32_t>(P, L.cnt), status,
+            P->filter ? nullptr : wsp<unsigned long long>(P, P->o_pairs), exact ? 1 : 0,
+            (const vec4_t<T>*)nullptr);
     LAUNCH_CHECK("build_list");
     return SPH_OK;
 }
@@ -1186,6 +1198,7 @@ sph_status run_graphed(sph_plan* P, std::vector<uintptr_t> key, hipStream_t st, 
     key.push_back((uintptr_t)P->rk_stages);
     key.push_back((uintptr_t)(P->symplectic ? 1 + (P->symp_reuse ? 1 : 0) : 0));
     key.push_back((uintptr_t)(P->renorm ? 1 : 0));
+    key.push_back((uintptr_t)(P->speed_skins ? 1 : 0));
     for (auto& g : P->gcache) {
         if (g.key == key) {
             g.used = ++P->gclock;
@@ -1719,6 +1732,15 @@ sph_status sph_set_reuse(sph_plan* plan, int32_t rebuild_every)
     if (rebuild_every > 1 && !plan->filter)
         return fail(SPH_ERR_INVALID_ARG, "reusing lists needs a skin (sph_params.skin > 0)");
     plan->reuse = rebuild_every;
+    return SPH_OK;
+}
+
+sph_status sph_set_skin_mode(sph_plan* plan, int32_t speed_scaled)
+{
+    if (!plan) return fail(SPH_ERR_INVALID_ARG, "plan is null");
+    if (speed_scaled && !plan->filter)
+        return fail(SPH_ERR_INVALID_ARG, "speed-scaled skins need a skin (sph_params.skin > 0)");
+    plan->speed_skins = speed_scaled != 0;
     return SPH_OK;
 }
 

@@ -22,7 +22,19 @@ namespace sph {
 
 constexpr int kFlagNonfinite = 1;
 constexpr int kFlagOverflow = 2;
-constexpr int kFlagSkin = 4;  // a particle moved more than half the skin since its list was built
+constexpr int kFlagSkin = 4;  // a particle moved more than its half skin since its list was built
+
+// Half skins of reused lists: particle i may move h_i between two list builds, and a pair is
+// listed when r < H + h_i + h_j.  Uniform skins take h_i = hmax (half the simulation's skin);
+// speed-scaled skins take h_i = min(hmax, kSkinFloor hmax + kSkinMargin R dt |v_i|) from the
+// particle's speed when the lists are built (R the rebuild interval).  A pair that comes
+// within H before the next build is therefore listed as long as neither particle has moved more
+// than its own h_i, which every step checks (kFlagSkin).  The additive floor is every particle's
+// allowance for acceleration over the interval: with hmax sized for 1.3 times the largest speed,
+// a particle at rest may accelerate steadily to about a third of that speed; the margin covers
+// 30 % more than its own speed.
+constexpr double kSkinMargin = 1.3;
+constexpr double kSkinFloor = 0.125;
 
 template <typename T> struct Vec4;
 template <> struct Vec4<float> { using type = float4; };
@@ -43,7 +55,7 @@ struct SimConst {
     T cD;       // 2 delta H c0
     T Bt;       // rho0 c0^2 / 7
     T HL2;      // (H (1 + skin))^2: list radius squared (= H2 without a skin)
-    T disp2;    // (skin H / 2)^2: largest squared displacement a reused list allows
+    T hmax;     // skin H / 2: the largest half skin of a particle (the cells are sized for it)
     T invW0;    // 1 / W(dx), dx = (m / rho0)^(1/dim) the initial spacing (particle shifting)
     int64_t p0, n;      // packed particle range
     int32_t cell0;      // first global cell slot
@@ -419,7 +431,8 @@ __global__ __launch_bounds__(256) void k_order_gather(int64_t N, const int32_t* 
                                                       vec4_t<T>* __restrict__ jd0, vec4_t<T>* __restrict__ jd1,
                                                       const int32_t* __restrict__ psim,
                                                       const SimConst<T>* __restrict__ sims,
-                                                      vec4_t<T>* __restrict__ uref)
+                                                      vec4_t<T>* __restrict__ uref, T skin_floor,
+                                                      T skin_steps)
 {
     int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= N) return;
@@ -460,13 +473,25 @@ __global__ __launch_bounds__(256) void k_order_gather(int64_t N, const int32_t* 
     }
     jd0[d] = a;
     jd1[d] = b;
-    if (uref) uref[d] = a;  // the positions the lists were built from (list reuse)
+    if (uref) {
+        // the positions the lists are built from and the particle's half skin (list reuse):
+        // speed-scaled with skin_floor = kSkinFloor, skin_steps = kSkinMargin R, uniform (hmax)
+        // with skin_floor = 1, skin_steps = 0
+        T v2 = T(0);
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) v2 += v[k] * v[k];
+        const T hv = skin_floor * S.hmax + skin_steps * S.dt * sqrt(v2);
+        const T h = hv < S.hmax ? hv : S.hmax;   // a non-finite speed keeps hmax
+        vec4_t<T> r;
+        r.x = u[0]; r.y = u[1]; r.z = u[2]; r.w = h;
+        uref[d] = r;
+    }
 }
 
 // A state in original order gathered into the particle order of a slot that is already sorted
 // and has lists (a later stage of a multistage step, with the lists of the step's first stage):
 // the sorted state and the packed records as k_order_gather writes them, and the displacement
-// since the lists were built checked against half the skin.
+// since the lists were built checked against its half skin.
 template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_repack(int64_t N, const int32_t* __restrict__ orig, StatePtrs<T, DIM> src,
                                                 StatePtrs<T, DIM> dst, vec4_t<T>* __restrict__ jd0,
@@ -512,7 +537,7 @@ __global__ __launch_bounds__(256) void k_repack(int64_t N, const int32_t* __rest
         dk -= S.L * rint(dk * S.invL);
         d2 += dk * dk;
     }
-    if (!(d2 <= S.disp2)) atomicOr(&status[s], kFlagSkin);
+    if (!(d2 <= ref.w * ref.w)) atomicOr(&status[s], kFlagSkin);
 }
 
 template <typename T, int DIM>
@@ -571,7 +596,7 @@ constexpr int kCandTable = 2048;
 // gives each its rank, so the round appends a contiguous run to p's row, in candidate order.
 // Lane p keeps p's running count.  Lists are row-major: entry k of particle i is
 // nbr[i * width + k].
-template <typename T, int DIM>
+template <typename T, int DIM, bool PERPAIR>
 __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ cell_sim,
                                                    const int32_t* __restrict__ blk_coord,
                                                    const int32_t* __restrict__ blk_rank,
@@ -580,8 +605,12 @@ __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ c
                                                    const vec4_t<T>* __restrict__ jd0, int32_t width,
                                                    int32_t* __restrict__ nbr, int32_t* __restrict__ nbr_count,
                                                    int32_t* __restrict__ status,
-                                                   unsigned long long* __restrict__ pair_counter, int exact)
+                                                   unsigned long long* __restrict__ pair_counter, int exact,
+                                                   const vec4_t<T>* __restrict__ href)
 {
+    // PERPAIR: lists with per-particle half skins; positions and half skins come from href
+    // (written by the sort), and the list radius of a pair is H + h_i + h_j
+    const vec4_t<T>* __restrict__ rec = PERPAIR ? href : jd0;
     __shared__ vec4_t<T> pu[64];
     __shared__ int32_t uc_first[128];
     __shared__ int32_t uc_pref[129];
@@ -653,14 +682,14 @@ __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ c
         }
         j = uc_first[lo] + (m - uc_pref[lo]);
         code = uc_code[lo];
-        u = jd0[j];
+        u = rec[j];
     };
 
     int pairs_acc = 0;
     for (int pb = 0; pb < n; pb += 64) {
         const int nb = __builtin_amdgcn_readfirstlane((n - pb < 64) ? n - pb : 64);
         __syncthreads();
-        if (lane < nb) pu[lane] = jd0[i0 + pb + lane];
+        if (lane < nb) pu[lane] = rec[i0 + pb + lane];
         __syncthreads();
         int cnt = 0;  // lane p: entries of particle i0 + pb + p so far
         int jn = 0, coden = 0;
@@ -675,12 +704,19 @@ __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ c
             sh[0] = T(((coden >> kStencilIdBits) & 3) - 1) * S.L;
             sh[1] = T(((coden >> (kStencilIdBits + 2)) & 3) - 1) * S.L;
             sh[2] = T(((coden >> (kStencilIdBits + 4)) & 3) - 1) * S.L;
+            const T Aj = S.H + un.w;   // PERPAIR: H + h_j
             if (c0 + 64 + lane < M) fetch(c0 + 64 + lane, jn, un, coden);  // next chunk in flight
             const unsigned long long vmask = __ballot(valid);
             for (int p = 0; p < nb; ++p) {
                 T ui[3] = {T(0), T(0), T(0)};
-                unpack_u<T, DIM>(pu[p], ui);
-                const bool inr = dist2_exact<T, DIM>(ui, uj, sh) < R2;
+                const vec4_t<T> rp = pu[p];
+                unpack_u<T, DIM>(rp, ui);
+                T Rp2 = R2;
+                if (PERPAIR) {
+                    const T Rp = Aj + rp.w;
+                    Rp2 = Rp * Rp;
+                }
+                const bool inr = dist2_exact<T, DIM>(ui, uj, sh) < Rp2;
                 const unsigned long long mask = __ballot(inr) & vmask;
                 const bool ok = valid & inr;
                 const int base = __builtin_amdgcn_readlane(cnt, p);
@@ -840,7 +876,7 @@ __device__ __forceinline__ T r2_exact(const T* ui, const vec4_t<T>& a, T L, T in
 // What the sweep that finishes a step does for the next step when that step reuses the lists
 // (null jd0: the next step sorts and rebuilds): the next state goes straight into the next
 // tape slot in the same particle order, with its packed records and original indices, and each
-// particle's displacement since the list build is checked against half the skin.
+// particle's displacement since the list build is checked against its half skin.
 template <typename T>
 struct NextSlot {
     vec4_t<T>* jd0;
@@ -1286,7 +1322,7 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
                 d -= S.L * rint(d * S.invL);
                 d2 += d * d;
             }
-            if (!(d2 <= S.disp2)) atomicOr(&status[s], kFlagSkin);
+            if (!(d2 <= ref.w * ref.w)) atomicOr(&status[s], kFlagSkin);
         }
     } else {
         const int o = orig[i];

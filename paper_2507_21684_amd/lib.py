@@ -79,6 +79,8 @@ def lib():
         L.sph_set_symplectic.argtypes = [_VP, ctypes.c_int32]
         L.sph_set_reuse.restype = st
         L.sph_set_reuse.argtypes = [_VP, ctypes.c_int32]
+        L.sph_set_skin_mode.restype = st
+        L.sph_set_skin_mode.argtypes = [_VP, ctypes.c_int32]
         L.sph_set_graphs.restype = ctypes.c_int32
         L.sph_get_tuning.argtypes = [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         L.sph_rollout_backward.restype = st
@@ -145,6 +147,7 @@ def exported_symbols() -> List[str]:
             "sph_build_cells", "sph_neighbors", "sph_rhs", "sph_step", "sph_step_adjoint", "sph_poll",
             "sph_pair_count", "sph_profile_enable", "sph_profile_read", "sph_last_error", "sph_set_tuning",
             "sph_get_tuning", "sph_rollout_backward", "sph_set_graphs", "sph_density_adjoint", "sph_set_reuse",
+            "sph_set_skin_mode",
             "sph_set_integrator", "sph_set_symplectic", "sph_set_diffusion", "sph_shift",
             "sph_shift_adjoint", "sph_bind_scratch", "sph_neighbors_adaptive", "sph_retained_lists",
             "sph_step_adjoint_retained", "sph_density_adjoint_retained", "sph_poll_async"]
@@ -233,9 +236,10 @@ class Plan:
     def __init__(self, sims: Sequence[dict], counts: Sequence[int], dtype: str = "f32",
                  max_neighbors: int = 0, tape_depth: int = 8, device: Optional[torch.device] = None,
                  stream=None, skin=0.0, rebuild_every: int = 1, integrator=None, renormalised_diffusion: bool = False,
-                 scratch: bool = False):
+                 scratch: bool = False, speed_skins: bool = False):
         """scratch=True binds the library's static workspace of the current device
-        (sph_bind_scratch) instead of allocating one."""
+        (sph_bind_scratch) instead of allocating one; speed_skins=True gives the lists
+        speed-scaled half skins (sph_set_skin_mode)."""
         L = lib()
         self.dtype = dtype
         self.torch_dtype = torch.float64 if dtype == "f64" else torch.float32
@@ -290,6 +294,9 @@ class Plan:
         self.rebuild_every = 1
         if rebuild_every != 1:
             self.set_reuse(rebuild_every)
+        self.speed_skins = False
+        if speed_skins:
+            self.set_skin_mode(True)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -443,6 +450,11 @@ class Plan:
         """Rebuild the cell list and neighbour lists every `rebuild_every` steps (needs a skin)."""
         _check(lib().sph_set_reuse(self._h, int(rebuild_every)))
         self.rebuild_every = int(rebuild_every)
+
+    def set_skin_mode(self, speed_scaled: bool):
+        """Speed-scaled (True) or uniform (False) half skins for the lists (needs a skin)."""
+        _check(lib().sph_set_skin_mode(self._h, 1 if speed_scaled else 0))
+        self.speed_skins = bool(speed_scaled)
 
     def set_graphs(self, enable: bool = True):
         """Issue step / rollout_backward calls as cached executable HIP graphs."""

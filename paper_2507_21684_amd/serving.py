@@ -393,7 +393,7 @@ class GpuEngine:
             t0 = time.perf_counter()
             p = Plan([j.req.spec.params() for j in jobs], [j.req.spec.n for j in jobs], dtype=self.dtype,
                      tape_depth=tape, device=self.device, skin=[self._skin[j.req.rid] for j in jobs],
-                     rebuild_every=self.R[jobs[0].dim])
+                     rebuild_every=self.R[jobs[0].dim], speed_skins=self.R[jobs[0].dim] > 1)
             if self.tuned:
                 from .autotune import apply_cached
                 apply_cached(p)
@@ -539,7 +539,7 @@ def plain_request(req: Request, dtype: str = "f32", ckpt_every: int = 8, device=
     dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
     x, v, r = (torch.tensor(a, device=dev) for a in host)
     plan = Plan([spec.params()], [spec.n], dtype=dtype, tape_depth=ckpt_every, device=dev, skin=skin,
-                rebuild_every=R)
+                rebuild_every=R, speed_skins=R > 1)
     if tuned:
         from .autotune import apply_cached
         apply_cached(plan)

@@ -241,3 +241,19 @@ def test_scratch_binding_checks_before_any_device_call():
     assert L.lib().sph_bind_scratch(h, None) == -3
     assert b"static workspace" in L.lib().sph_last_error()
     L.lib().sph_plan_destroy(h)
+
+
+def test_skin_mode_setting_on_an_unbound_plan():
+    """Speed-scaled half skins need a skin; uniform ones are always accepted (host-only calls)."""
+    spec = SimSpec(2, 32)
+    rc, h = _plan([_p(spec)], [spec.n])
+    assert rc == 0
+    assert L.lib().sph_set_skin_mode(h, 1) == -1
+    assert L.lib().sph_set_skin_mode(h, 0) == 0
+    L.lib().sph_plan_destroy(h)
+    rc, h = _plan([L.make_params(spec.params(), "f32", 0.2)], [spec.n])
+    assert rc == 0
+    assert L.lib().sph_set_skin_mode(h, 1) == 0
+    assert L.lib().sph_set_skin_mode(h, 0) == 0
+    L.lib().sph_plan_destroy(h)
+    assert L.lib().sph_set_skin_mode(None, 1) == -1

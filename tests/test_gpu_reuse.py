@@ -37,11 +37,12 @@ def _plan(specs, dtype="f32", skin=SKIN, rebuild=R, **kw):
     return Plan([s.params() for s in specs], [s.n for s in specs], dtype, skin=skin, rebuild_every=rebuild, **kw)
 
 
+@pytest.mark.parametrize("speed", [False, True])
 @pytest.mark.parametrize("dim,side,steps", [(2, 48, 16), (3, 16, 8)])
-def test_reuse_forward_parity(orc, dim, side, steps):
+def test_reuse_forward_parity(orc, dim, side, steps, speed):
     spec = SimSpec(dim, side)
     x, v, rho = _state(spec, 1)
-    plan = _plan([spec])
+    plan = _plan([spec], speed_skins=speed)
     g = _gpu([x, v, rho])
     plan.step(*g, steps)
     assert np.all(plan.poll() == 0)
@@ -53,11 +54,12 @@ def test_reuse_forward_parity(orc, dim, side, steps):
     assert np.abs(gx - xr).max() <= 1e-4 * spec.dx
 
 
-def test_reuse_rollout_gradient(orc):
+@pytest.mark.parametrize("speed", [False, True])
+def test_reuse_rollout_gradient(orc, speed):
     from paper_2507_21684_amd.rollout import rollout
     spec = SimSpec(2, 48)
     x, v, rho = _state(spec, 0)
-    plan = _plan([spec], tape_depth=4)
+    plan = _plan([spec], tape_depth=4, speed_skins=speed)
     gx0, gv0, gr0 = _gpu([x, v, rho])
     for t in (gx0, gv0, gr0):
         t.requires_grad_(True)
@@ -89,6 +91,59 @@ def test_filtered_pair_count_and_export_are_exact():
     np.testing.assert_array_equal(o1, o2)
     for i in range(0, spec.n, 97):
         np.testing.assert_array_equal(np.sort(n1[o1[i]:o1[i + 1]]), np.sort(n2[o2[i]:o2[i + 1]]))
+
+
+@pytest.mark.parametrize("speed", [False, True])
+@pytest.mark.parametrize("dim,side,amp,skin,rebuild", [(2, 40, 1.5, 0.2, 4), (2, 32, 2.0, 0.4, 6), (3, 14, 1.2, 0.15, 4)])
+def test_reused_lists_hold_every_pair_of_the_interval(dim, side, amp, skin, rebuild, speed):
+    """Uniform and speed-scaled half skins: over a reuse interval the filtered sweeps count
+    exactly the pairs that exact lists of the same states hold.  FP64, where the two
+    trajectories differ only by summation order, far too little to move a pair across H.  The
+    cases put the fastest particle at about three quarters of its half skin."""
+    spec = SimSpec(dim, side, amplitude=amp)
+    st = _state(spec, 9, "f64")
+    reused = _plan([spec], "f64", skin=skin, rebuild=rebuild, speed_skins=speed)
+    exact = Plan([spec.params()], [spec.n], "f64")
+    g = _gpu(st, "f64")
+    reused.pair_count()
+    reused.step(*g, rebuild)
+    got = reused.pair_count()
+    assert reused.poll()[0] == 0
+    g = _gpu(st, "f64")
+    exact.pair_count()
+    want = 0
+    for _ in range(rebuild):
+        exact.step(*g, 1)
+        want += exact.pair_count()
+    assert got == want
+
+
+@pytest.mark.parametrize("dim,side", [(2, 40), (3, 14)])
+def test_speed_scaled_and_uniform_skins_agree(dim, side):
+    """Speed-scaled and uniform half skins sweep the same pairs over a reused rollout (equal
+    filtered pair counts), and each is bitwise deterministic (the oracle parity of both is
+    checked above)."""
+    spec = SimSpec(dim, side, amplitude=1.0)
+    st = _state(spec, 4)
+    outs, pairs = [], []
+    for speed in (False, True):
+        for rep in range(2):
+            p = _plan([spec], skin=0.3, rebuild=4, speed_skins=speed)
+            assert p.speed_skins == speed
+            g = _gpu(st)
+            p.pair_count()
+            p.step(*g, 8)
+            n = p.pair_count()
+            assert p.poll()[0] == 0
+            out = [t.cpu().numpy() for t in g]
+            if rep:
+                assert n == pairs[-1]
+                for a, b in zip(out, outs[-1]):
+                    np.testing.assert_array_equal(a, b)
+            else:
+                outs.append(out)
+                pairs.append(n)
+    assert pairs[0] == pairs[1]
 
 
 def test_reuse_deterministic_and_batch_invariant():

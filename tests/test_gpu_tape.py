@@ -84,3 +84,36 @@ def test_graph_replays_keep_the_forward_tape_and_the_results():
         for k, (a, b) in enumerate(zip((x, v, r, gx, gv, gr), ref)):
             assert torch.equal(a, b), "replay %d, output %d" % (rep, k)
     assert np.all(plan.poll() == 0)
+
+
+def test_graph_cache_follows_setting_changes():
+    """Graph mode: after the reuse interval, the skin mode or the lanes change, the next calls
+    give bitwise what a fresh plan with the new settings gives, not a replay of graphs captured
+    under the old ones; returning to the first settings replays their graphs."""
+    spec = SimSpec(2, 36, amplitude=1.2)
+    T, K = 8, 8
+    st = [torch.tensor(a.astype(np.float32), device=DEV) for a in make_state(spec, 6)]
+
+    def fresh(R, speed, lanes):
+        p = Plan([spec.params()], [spec.n], "f32", tape_depth=T, device=DEV, skin=0.3, rebuild_every=R,
+                 speed_skins=speed)
+        p.set_tuning(*lanes)
+        return _job(p, st, T, K)[0]
+
+    plan = Plan([spec.params()], [spec.n], "f32", tape_depth=T, device=DEV, skin=0.3, rebuild_every=2)
+    plan.set_graphs(True)
+    settings = [(2, False, (4, 4)), (4, False, (4, 4)), (4, True, (4, 4)), (4, True, (2, 8)), (2, False, (4, 4))]
+    prev = None
+    for R, speed, lanes in settings:
+        plan.set_reuse(R)
+        plan.set_skin_mode(speed)
+        plan.set_tuning(*lanes)
+        for rep in range(2):
+            got = _job(plan, st, T, K)[0]
+            want = fresh(R, speed, lanes)
+            for k, (a, b) in enumerate(zip(got, want)):
+                assert torch.equal(a, b), "R %d speed %s lanes %s replay %d output %d" % (R, speed, lanes, rep, k)
+        if prev is not None and (R, speed) != prev[0]:
+            # the settings change the summation order, so a stale graph would show
+            assert any(not torch.equal(a, b) for a, b in zip(got, prev[1]))
+        prev = ((R, speed), got)
