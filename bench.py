@@ -258,7 +258,7 @@ def measured_traffic(workload, kernel_symbol):
     return None
 
 
-def roofline(prof, dom, wl, per_state, reps, dim, n_particles, lanes=(4, 4), taped=False):
+def roofline(prof, dom, wl, per_state, reps, dim, n_particles, lanes=(4, 4), taped=False, speed_skins=False):
     """Roofline of the dominant kernel from its HIP-event launch times in the timed region.
 
     k_sweep / k_adj_sweep: ALU-bound; algorithmic flops per launch = flops per directed pair x
@@ -284,7 +284,7 @@ def roofline(prof, dom, wl, per_state, reps, dim, n_particles, lanes=(4, 4), tap
         achieved = bytes_per_launch / mean_launch_s / 1e9
         peak = PEAK_HBM_GBS
         tdt = "float" if wl.dtype == "f32" else "double"
-        traffic = measured_traffic(wl.name, "sph::k_build_list<%s,%d>" % (tdt, dim))
+        traffic = measured_traffic(wl.name, "sph::k_build_list<%s,%d,%s>" % (tdt, dim, "true" if speed_skins else "false"))
         return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": peak, "unit": "GB/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic,
                 "mean_launch_us": round(mean_launch_s * 1e6, 2), "launches": n_dom,
@@ -757,7 +757,7 @@ def measure_workload(name, dev, reps, warmup):
     status = plan.poll()
     assert np.all(status == 0), "device reported non-finite values or neighbour overflow: %s" % status
     dim = wl.sims[0].dim
-    roof = roofline(prof, dom, wl, per_state, reps, dim, n_part, tuple(lanes) + (R,), taped)
+    roof = roofline(prof, dom, wl, per_state, reps, dim, n_part, tuple(lanes) + (R,), taped, plan.speed_skins)
     ms = 1e3 * elapsed / reps
     log("%s: timed %d jobs, %.3f ms per job" % (wl.name, reps, ms))
     config = {"workload": wl.name, "dim": dim, "simulations": len(wl.sims), "particles": n_part,
