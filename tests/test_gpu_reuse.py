@@ -74,6 +74,29 @@ def test_reuse_rollout_gradient(orc, speed):
         assert np.abs(got - want).max() <= 1e-3 * np.abs(want).max()
 
 
+@pytest.mark.parametrize("dim,side,tape", [(2, 40, 4), (2, 40, 16), (3, 14, 4), (3, 14, 16)])
+def test_reuse_rollout_gradient_f64(orc, dim, side, tape):
+    """FP64 rollout gradient with reused lists (R = 4, speed-scaled skins), on the forward's tape
+    (tape 16) and with recomputed segments (tape 4), against the oracle: a pair that the filtered
+    forward or adjoint sweeps missed or counted twice would show far above FP64 rounding."""
+    from paper_2507_21684_amd.rollout import rollout
+    spec = SimSpec(dim, side, amplitude=1.3)
+    x, v, rho = _state(spec, 2, "f64")
+    plan = _plan([spec], "f64", skin=0.3, rebuild=4, tape_depth=tape, speed_skins=True)
+    gx0, gv0, gr0 = _gpu([x, v, rho], "f64")
+    for t in (gx0, gv0, gr0):
+        t.requires_grad_(True)
+    xT, vT, rT = rollout(plan, gx0, gv0, gr0, 16, 4)
+    loss = (vT ** 2).sum()
+    loss.backward()
+    assert np.all(plan.poll() == 0)
+    ref = orc.rollout(orc.Params(**spec.params()), x, v, rho, 16, 0)
+    assert float(loss) == pytest.approx(ref["loss"], rel=1e-11)
+    for got, want in ((gv0.grad, ref["gv0"]), (gx0.grad, ref["gx0"]), (gr0.grad, ref["grho0"])):
+        got = got.cpu().numpy()
+        assert np.abs(got - want).max() <= 1e-9 * np.abs(want).max()
+
+
 def test_filtered_pair_count_and_export_are_exact():
     spec = SimSpec(2, 40, amplitude=1.5)
     x, v, rho = _state(spec, 4)
