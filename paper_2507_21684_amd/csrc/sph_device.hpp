@@ -705,27 +705,45 @@ __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ c
             sh[1] = T(((coden >> (kStencilIdBits + 2)) & 3) - 1) * S.L;
             sh[2] = T(((coden >> (kStencilIdBits + 4)) & 3) - 1) * S.L;
             const T Aj = S.H + un.w;   // PERPAIR: H + h_j
+            // PERPAIR lists only need to hold a superset of the pairs within H (the sweeps test
+            // those exactly), so their distance takes the candidate's image once per chunk and
+            // contracted products; exact lists keep the predicate's own arithmetic
+            T ujs[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) ujs[k] = uj[k] + sh[k];
             if (c0 + 64 + lane < M) fetch(c0 + 64 + lane, jn, un, coden);  // next chunk in flight
             const unsigned long long vmask = __ballot(valid);
-            for (int p = 0; p < nb; ++p) {
+            int32_t* row = nbr + (int64_t)(i0 + pb) * width;
+            for (int p = 0; p < nb; ++p, row += width) {
                 T ui[3] = {T(0), T(0), T(0)};
                 const vec4_t<T> rp = pu[p];
                 unpack_u<T, DIM>(rp, ui);
-                T Rp2 = R2;
+                bool inr;
                 if (PERPAIR) {
                     const T Rp = Aj + rp.w;
-                    Rp2 = Rp * Rp;
+                    const T d0 = ui[0] - ujs[0];
+                    T r2 = d0 * d0;
+#pragma unroll
+                    for (int k = 1; k < DIM; ++k) {
+                        const T d = ui[k] - ujs[k];
+                        r2 = fma(d, d, r2);
+                    }
+                    inr = r2 < Rp * Rp;
+                } else {
+                    inr = dist2_exact<T, DIM>(ui, uj, sh) < R2;
                 }
-                const bool inr = dist2_exact<T, DIM>(ui, uj, sh) < Rp2;
                 const unsigned long long mask = __ballot(inr) & vmask;
                 const bool ok = valid & inr;
                 const int base = __builtin_amdgcn_readlane(cnt, p);
+                const int total = base + __popcll(mask);
                 // base plus the accepted lanes below this one
                 const unsigned pos = __builtin_amdgcn_mbcnt_hi(
                     unsigned(mask >> 32), __builtin_amdgcn_mbcnt_lo(unsigned(mask), unsigned(base)));
-                int32_t* row = nbr + (int64_t)(i0 + pb + p) * width;
-                if (ok && pos < unsigned(width)) row[pos] = jc;
-                const int total = base + __popcll(mask);
+                if (total <= width) {           // wave-uniform: the whole run fits the row
+                    if (ok) row[pos] = jc;
+                } else if (ok && pos < unsigned(width)) {
+                    row[pos] = jc;
+                }
                 cnt = (lane == p) ? total : cnt;  // lane p keeps p's count
             }
         }
