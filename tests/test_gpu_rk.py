@@ -107,13 +107,15 @@ def test_rk_batch_invariance():
         off += s.n
 
 
+@pytest.mark.parametrize("speed", [False, True])
 @pytest.mark.parametrize("scheme,dtype,dim,side", [("rk4", "f64", 2, 24), ("midpoint", "f32", 2, 40),
                                                    ("rk4", "f32", 3, 14)])
-def test_rk_stage_list_reuse_parity(orc, scheme, dtype, dim, side):
-    """With a skin, later stages keep the first stage's lists (filtered to r < H): same results."""
+def test_rk_stage_list_reuse_parity(orc, scheme, dtype, dim, side, speed):
+    """With a skin, later stages keep the first stage's lists (filtered to r < H): same results,
+    with uniform and with speed-scaled half skins."""
     spec = SimSpec(dim, side)
     x, v, rho = _state(spec, 3, dtype)
-    plan = _plan([spec], dtype, scheme, skin=0.1)
+    plan = _plan([spec], dtype, scheme, skin=0.1, speed_skins=speed)
     g = _gpu([x, v, rho], dtype)
     plan.step(*g, 3)
     assert np.all(plan.poll() == 0)

@@ -137,13 +137,15 @@ def test_symplectic_batch_invariance_and_graphs():
             off += s.n
 
 
+@pytest.mark.parametrize("speed", [False, True])
 @pytest.mark.parametrize("reuse,dtype", [(False, "f64"), (True, "f32")])
-def test_symplectic_with_a_skin(orc, reuse, dtype):
-    """With a skin the predictor state keeps the step's lists when the step evaluated f(u)."""
+def test_symplectic_with_a_skin(orc, reuse, dtype, speed):
+    """With a skin the predictor state keeps the step's lists when the step evaluated f(u)
+    (uniform and speed-scaled half skins)."""
     from paper_2507_21684_amd.rollout import rollout
     spec = SimSpec(2, 24)
     x, v, rho = _state(spec, 6, dtype)
-    plan = _plan([spec], dtype, reuse, tape_depth=3, skin=0.1)
+    plan = _plan([spec], dtype, reuse, tape_depth=3, skin=0.1, speed_skins=speed)
     gx0, gv0, gr0 = _gpu([x, v, rho], dtype)
     for t in (gx0, gv0, gr0):
         t.requires_grad_(True)
