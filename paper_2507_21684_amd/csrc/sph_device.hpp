@@ -1691,6 +1691,7 @@ struct AdjSelf {
     T v[3], a[3];   // velocity, abar / rho
     T rb, V, rho, p, ir, dp;
     T rbr;          // rbar rho
+    T Vir;          // V / rho
     T G[3];
 };
 
@@ -1737,7 +1738,8 @@ __device__ __forceinline__ void adj_pair(const PairConst<T>& c, const AdjSelf<T>
     const T X = cA * pij - (K.p + pj);
     const T beta = cA * inv * (Vj * aGk - Vk * aGj);
     const T gam = Vj * K.rbr + Vk * rbrj;
-    const T cdr = cD * sig * (rhok - rhoj) * (Vj * rbk - Vk * rbj);
+    const T drho = rhok - rhoj;
+    const T cdr = cD * sig * drho * (Vj * rbk - Vk * rbj);
     T w[3];
     T ew = 0;
 #pragma unroll
@@ -1746,14 +1748,18 @@ __device__ __forceinline__ void adj_pair(const PairConst<T>& c, const AdjSelf<T>
         ew += e[k] * w[k];
     }
     const T ce = cdr - T(2) * beta * pij + hF * ew;  // coefficient of e in the position cotangent
+    const T bg = beta + gam * gF;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-        acc.gx[k] = keep ? acc.gx[k] + (beta * u[k] + ce * e[k] + gF * w[k]) : acc.gx[k];
-        acc.gv[k] = keep ? acc.gv[k] + (beta + gam * gF) * e[k] : acc.gv[k];
+        acc.gx[k] = keep ? fma(gF, w[k], fma(ce, e[k], fma(beta, u[k], acc.gx[k]))) : acc.gx[k];
+        acc.gv[k] = keep ? fma(bg, e[k], acc.gv[k]) : acc.gv[k];
     }
-    const T phi2 = Vk * (-X * aGj + rbrj * uG + rbj * cD * (rhoj - rhok) * sij);
-    const T dgr = Vj * (aGk * (-K.dp - X * K.ir) + rbk * uG + rbk * cD * sij) - phi2 * K.ir +
-                  Vk * (aGj * K.dp - rbj * cD * sij);
+    // density cotangent: the (k,j) and (j,k) terms' density partials; the (j,k) momentum term
+    // enters through 1/rho_k as -(V_k / rho_k) P
+    const T cds = cD * sij;
+    const T rbjc = rbj * cds;
+    const T P = rbrj * uG - X * aGj - drho * rbjc;
+    const T dgr = Vj * (aGk * -(K.dp + X * K.ir) + rbk * (uG + cds)) - K.Vir * P + Vk * (aGj * K.dp - rbjc);
     acc.gr = keep ? acc.gr + dgr : acc.gr;
     if (RENORM) {
         const T cr = T(-0.5) * cD;
@@ -1820,6 +1826,7 @@ __global__ __launch_bounds__(256) void k_adj_sweep(int64_t N, int32_t width, con
         K.rbr = Bk.z;
         K.dp = Bk.w;
         K.ir = fast_rcp(K.rho);
+        K.Vir = K.V * K.ir;
     }
     K.G[0] = K.G[1] = K.G[2] = T(0);
     if (RENORM) {
