@@ -1112,12 +1112,16 @@ struct FwdNbr {
 // In 3D jd0 = (u, rho) and jd1 = (v, p), with V = m / rho recomputed as the writer computed it;
 // in 2D jd0 = (u, V, p V) and jd1 = (v, rho, p).  Two records per neighbour either way, since
 // the sweeps are bound by the vector L1's line rate, which counts gathers, not arithmetic.
-// d and r2 are the pair vector x_ij and its square; with keep false the
-// pair is computed but leaves acc unchanged (a select, not a branch).
-template <typename T, int DIM, bool RHOSUM, bool RENORM>
+// d and r2 are the pair vector x_ij and its square.  With keep false the pair leaves acc
+// unchanged: MASK = false selects the old sums, MASK = true zeroes the kernel factors (every
+// term carries gF or W) and adds, so the neighbour's records are consumed unconditionally and
+// their loads stay ahead of the pair terms.  No implicit contraction: the products that are fused
+// are written as fma, so a pair rounds the same whichever list position and lane count it has.
+template <typename T, int DIM, bool RHOSUM, bool RENORM, bool MASK = false>
 __device__ __forceinline__ void fwd_pair(const PairConst<T>& c, const T* vi, T rhoi, T pi, const FwdNbr<T, DIM>& nb,
                                          const T* Gi, const T* d, T r2, bool keep, FwdAcc<T, DIM>& acc)
 {
+#pragma clang fp contract(off)
     T vj[3];
     T Vj, pVj, rhoj;
     if (DIM == 3) {
@@ -1128,30 +1132,42 @@ __device__ __forceinline__ void fwd_pair(const PairConst<T>& c, const T* vi, T r
         Vj = nb.a.z; pVj = nb.a.w;
         vj[0] = nb.b.x; vj[1] = nb.b.y; rhoj = nb.b.z;
     }
-    T ue = 0;
+    T ue = (vi[0] - vj[0]) * d[0];
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) ue += (vi[k] - vj[k]) * d[k];
+    for (int k = 1; k < DIM; ++k) ue = fma(vi[k] - vj[k], d[k], ue);
     const T q = fast_sqrt(r2) * c.invH;
     const T t = T(1) - q;
     const T t2 = t * t;
     const T t4 = t2 * t2;
     const T t5 = t4 * t;
-    const T gF = c.kGF * (t5 * (T(1) + T(5) * q));  // grad W = gF x_ij
+    T gF = c.kGF * (t5 * fma(T(5), q, T(1)));  // grad W = gF x_ij
+    T wq = t4 * t2 * fma(q, fma(q, T(35.0 / 3.0), T(6)), T(1));   // W shape
+    if (MASK) {
+        const T kf = keep ? T(1) : T(0);
+        gF = gF * kf;
+        wq = wq * kf;
+    }
     const T inv = fast_rcp(r2 + c.epsH2);
     const T pij = ue * inv;
-    const T cg = ((c.cA * pij - pi) * Vj - pVj) * gF;
+    const T cg = fma(fma(c.cA, pij, -pi), Vj, -pVj) * gF;
+    const T rdv = fma(Vj, gF * ue, acc.rdv);
+    const T rdd = fma(Vj * (rhoi - rhoj), gF * r2 * inv, acc.rdd);
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) acc.ax[k] = keep ? acc.ax[k] + cg * d[k] : acc.ax[k];
-    acc.rdv = keep ? acc.rdv + Vj * (gF * ue) : acc.rdv;
-    acc.rdd = keep ? acc.rdd + Vj * (rhoi - rhoj) * (gF * r2 * inv) : acc.rdd;
-    if (RHOSUM) acc.rs = keep ? acc.rs + t4 * t2 * (T(1) + q * (T(6) + q * T(35.0 / 3.0))) : acc.rs;
+    for (int k = 0; k < DIM; ++k) {
+        const T ax = fma(cg, d[k], acc.ax[k]);
+        acc.ax[k] = (MASK || keep) ? ax : acc.ax[k];
+    }
+    acc.rdv = (MASK || keep) ? rdv : acc.rdv;
+    acc.rdd = (MASK || keep) ? rdd : acc.rdd;
+    if (RHOSUM) acc.rs = (MASK || keep) ? acc.rs + wq : acc.rs;
     if (RENORM) {
         // V_j (G_i + G_j) . grad_i W_ij of the renormalised diffusion
         const T Gj[3] = {nb.G.x, nb.G.y, nb.G.z};
-        T sg = T(0);
+        T sg = (Gi[0] + Gj[0]) * d[0];
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) sg += (Gi[k] + Gj[k]) * d[k];
-        acc.rdg = keep ? acc.rdg + Vj * (gF * sg) : acc.rdg;
+        for (int k = 1; k < DIM; ++k) sg = fma(Gi[k] + Gj[k], d[k], sg);
+        const T rdg = fma(Vj, gF * sg, acc.rdg);
+        acc.rdg = (MASK || keep) ? rdg : acc.rdg;
     }
 }
 
@@ -1175,9 +1191,12 @@ struct NextCells {
 // accumulators start at +0 and never become -0, so adding nothing and skipping agree
 // bitwise), which lets the compiler interleave the independent pairs of the group.  A 3D
 // sweep keeps every SIMD busy with many wavefronts, and this takes the per-pair exec-mask
-// branches out of its instruction stream.  In 2D all wavefronts of a typical launch are
-// resident at once and each lane has few groups; there the per-pair branches, which skip the
-// tail positions that no lane of the wavefront holds, measured faster.
+// branches out of its instruction stream.  In 2D with 2 or 8 lanes per particle the per-pair
+// branches, which skip the tail positions that no lane of the wavefront holds, measured faster.
+// In 2D with 4 lanes the list entries are read as quad chunks (a quarter of the entry loads, the
+// vector L1's line rate being the bound) and the pairs again go without branches, dropped ones
+// masked inside fwd_pair: with a branch per pair the compiler sinks a neighbour's gathers into
+// it behind a full wait for the loads in flight.
 template <typename T, int DIM, int MODE, int LPP, bool RENORM>
 __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const int32_t* __restrict__ nbr,
                                                const int32_t* __restrict__ nbr_count,
@@ -1228,10 +1247,23 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
         acc[q].rdv = acc[q].rdd = acc[q].rs = acc[q].rdg = T(0);
     }
     constexpr bool kSelect = DIM == 3;
+    // four lanes per particle: list entries as 16-byte chunks and a quad transpose (one load
+    // per lane and group of four positions instead of four), and no branch per position (the
+    // positions past the count read the particle itself and are masked like dropped pairs), so
+    // that no neighbour's gathers are sunk behind the pair terms of an earlier one
+    constexpr bool kQuad = LPP == 4 && U == 4 && !kSelect;
     int jn[U];
-    if (kSelect) load_entries_clamped<LPP, U>(row, width, r, 0, mcount, (int)i, jn);
+    int4 chunk = make_int4(0, 0, 0, 0);
+    if (kQuad) chunk = load_chunk4(row, width, 4 * r);
+    else if (kSelect) load_entries_clamped<LPP, U>(row, width, r, 0, mcount, (int)i, jn);
     else load_entries<LPP, U>(row, r, 0, mcount, (int)i, jn);
     for (int m0 = 0; m0 < mcount; m0 += U) {
+        if (kQuad) {
+            int t4[4];
+            quad_transpose(r, chunk, t4);
+#pragma unroll
+            for (int u = 0; u < U; ++u) jn[u] = (m0 + u < mcount) ? t4[u] : (int)i;
+        }
         int jj[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) jj[u] = jn[u];
@@ -1243,17 +1275,21 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t N, int32_t width, const i
             nb[u].b = ldo(jd1, j);
             if (RENORM) nb[u].G = ldo(jdG, j);
         }
-        if (kSelect) load_entries_clamped<LPP, U>(row, width, r, m0 + U, mcount, (int)i, jn);
+        if (kQuad) chunk = load_chunk4(row, width, 4 * (m0 + U) + 4 * r);
+        else if (kSelect) load_entries_clamped<LPP, U>(row, width, r, m0 + U, mcount, (int)i, jn);
         else load_entries<LPP, U>(row, r, m0 + U, mcount, (int)i, jn);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (!kSelect && m0 + u >= mcount) continue;
+            if (!kQuad && !kSelect && m0 + u >= mcount) continue;
             T d[3];
             const T r2 = r2_exact<T, DIM>(ui, nb[u].a, c.L, c.invL, d);
             const bool keep = (m0 + u < mcount) && (!filter || r2 < c.H2);
-            if (!kSelect && !keep) continue;
+            if (!kQuad && !kSelect && !keep) continue;
             accepted += keep ? 1 : 0;
-            fwd_pair<T, DIM, MODE == kModeRhs, RENORM>(c, vi, rhoi, pi, nb[u], Gi, d, r2, keep, acc[u % NQ]);
+            if (kQuad)
+                fwd_pair<T, DIM, MODE == kModeRhs, RENORM, true>(c, vi, rhoi, pi, nb[u], Gi, d, r2, keep, acc[u % NQ]);
+            else
+                fwd_pair<T, DIM, MODE == kModeRhs, RENORM>(c, vi, rhoi, pi, nb[u], Gi, d, r2, keep, acc[u % NQ]);
         }
     }
     T ax[3] = {0, 0, 0};
