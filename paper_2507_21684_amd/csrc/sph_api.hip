@@ -46,6 +46,7 @@ sph_status fail(sph_status code, const std::string& msg)
     } while (0)
 
 constexpr double kCellMargin = 1.0 + 1.0 / 1024.0;  // cell side exceeds H/sub by more than rounding
+constexpr int64_t kGroupedBuildCells = 65536;         // 2D plans with this many cell slots build by 2 x 2 groups
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -423,16 +424,36 @@ sph_status build_lists(sph_plan* P, int slot, hipStream_t st, bool exact = false
     const SlotLayout& L = P->slot[slot];
     P->list_of[slot] = slot;
     ProfScope prof(P, st, SPH_KERN_BUILD, true);
+    // one wavefront per cell; in 2D with enough cells to fill the GPU four times over, one per
+    // group of 2 x 2 cells, which shares the per-wavefront setup of cells with few particles
+    const bool group = D == 2 && P->ncell >= kGroupedBuildCells;
+    const unsigned groups = (unsigned)(group ? P->ncell / 4 : P->ncell);
     // lists with speed-scaled skins use the half skins of the sort that preceded this build
-    if (P->filter && P->speed_skins && !exact)
-        launch_k(&prof, k_build_list<T, D, true>, dim3((unsigned)P->ncell), dim3(64), st,
+    if (group) {
+        if (P->filter && P->speed_skins && !exact)
+            launch_k(&prof, k_build_list<T, D, true, true>, dim3(groups), dim3(64), st,
+                wsp<int32_t>(P, P->o_cell_sim), wsp<int32_t>(P, P->o_blk_coord), wsp<int32_t>(P, P->o_blk_rank),
+                wsp<SimConst<T>>(P, P->o_simc),
+                wsp<int32_t>(P, P->o_cell_start), wsp<vec4_t<T>>(P, L.jd0), P->width,
+                wsp<int32_t>(P, L.nbr), wsp<int32_t>(P, L.cnt), status, (unsigned long long*)nullptr, 0,
+                (const vec4_t<T>*)wsp<vec4_t<T>>(P, P->o_uref));
+        else
+            launch_k(&prof, k_build_list<T, D, false, true>, dim3(groups), dim3(64), st,
+                wsp<int32_t>(P, P->o_cell_sim), wsp<int32_t>(P, P->o_blk_coord), wsp<int32_t>(P, P->o_blk_rank),
+                wsp<SimConst<T>>(P, P->o_simc),
+                wsp<int32_t>(P, P->o_cell_start), wsp<vec4_t<T>>(P, L.jd0), P->width,
+                wsp<int32_t>(P, L.nbr), wsp<int32_t>(P, L.cnt), status,
+                P->filter ? nullptr : wsp<unsigned long long>(P, P->o_pairs), exact ? 1 : 0,
+                (const vec4_t<T>*)nullptr);
+    } else if (P->filter && P->speed_skins && !exact)
+        launch_k(&prof, k_build_list<T, D, true, false>, dim3(groups), dim3(64), st,
             wsp<int32_t>(P, P->o_cell_sim), wsp<int32_t>(P, P->o_blk_coord), wsp<int32_t>(P, P->o_blk_rank),
             wsp<SimConst<T>>(P, P->o_simc),
             wsp<int32_t>(P, P->o_cell_start), wsp<vec4_t<T>>(P, L.jd0), P->width,
             wsp<int32_t>(P, L.nbr), wsp<int32_t>(P, L.cnt), status, (unsigned long long*)nullptr, 0,
             (const vec4_t<T>*)wsp<vec4_t<T>>(P, P->o_uref));
     else
-        launch_k(&prof, k_build_list<T, D, false>, dim3((unsigned)P->ncell), dim3(64), st,
+        launch_k(&prof, k_build_list<T, D, false, false>, dim3(groups), dim3(64), st,
             wsp<int32_t>(P, P->o_cell_sim), wsp<int32_t>(P, P->o_blk_coord), wsp<int32_t>(P, P->o_blk_rank),
             wsp<SimConst<T>>(P, P->o_simc),
             wsp<int32_t>(P, P->o_cell_start), wsp<vec4_t<T>>(P, L.jd0), P->width,

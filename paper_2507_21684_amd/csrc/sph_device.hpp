@@ -92,13 +92,14 @@ __device__ __forceinline__ void stencil_offsets(int u, int sub, int* o)
     o[2] = (DIM == 3) ? (int)(v / (SW * SW)) - sub : 0;
 }
 
-template <int DIM, typename T>
+template <int DIM, typename T, int EXT = 0>
 __device__ __forceinline__ int32_t stencil_entry(const SimConst<T>& S, const int32_t* __restrict__ blk_rank,
                                                  const int* cc, int u)
 {
+    // EXT = 1: the (SW + 1)^DIM union stencil of a group of 2^DIM cells whose lowest cell is cc
     int o[3];
-    if (S.sub == 2) stencil_offsets<DIM, 5>(u, 2, o);
-    else stencil_offsets<DIM, 3>(u, 1, o);
+    if (S.sub == 2) stencil_offsets<DIM, 5 + EXT>(u, 2, o);
+    else stencil_offsets<DIM, 3 + EXT>(u, 1, o);
     int c[3] = {0, 0, 0}, sh[3] = {0, 0, 0};
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
@@ -596,7 +597,14 @@ constexpr int kCandTable = 2048;
 // gives each its rank, so the round appends a contiguous run to p's row, in candidate order.
 // Lane p keeps p's running count.  Lists are row-major: entry k of particle i is
 // nbr[i * width + k].
-template <typename T, int DIM, bool PERPAIR>
+// With GROUP (2D) a wavefront serves a group of 2 x 2 cells (cell slots c, c + 1, c + B,
+// c + B + 1 of a block, B = 4) over their 6 x 6 (or 4 x 4) union stencil, in the same lexicographic order:
+// a particle's own stencil cells are a sub-grid of it in the same relative order, and the extra
+// row and column of the union lie at least two cell sides, i.e. at least the list radius, away
+// from it, so the strict distance test rejects them (also where a small box repeats a cell in
+// the union under another periodic image).  Each particle's list is therefore the one of its own
+// cell, while the stencil setup and the candidate stream are shared by four cells.
+template <typename T, int DIM, bool PERPAIR, bool GROUP>
 __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ cell_sim,
                                                    const int32_t* __restrict__ blk_coord,
                                                    const int32_t* __restrict__ blk_rank,
@@ -617,14 +625,22 @@ __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ c
     __shared__ int32_t uc_code[128];
     __shared__ uint8_t uc_of[kCandTable];  // stencil cell of each of the first kCandTable candidates
 
-    const int gc = xcd_remap(blockIdx.x, gridDim.x);
+    constexpr bool kGroup = GROUP && DIM == 2;
+    constexpr int kExt = kGroup ? 1 : 0;
+    const int gw = xcd_remap(blockIdx.x, gridDim.x);
+    // lowest cell slot of the wavefront's cells (2D: group gw & 3 of block gw >> 2)
+    const int gc = kGroup ? (gw >> 2) * 16 + ((gw >> 1) & 1) * 8 + (gw & 1) * 2 : gw;
     const int lane = threadIdx.x;
     const int s = cell_sim[gc];
-    const int i0 = cell_start[gc], i1 = cell_start[gc + 1];
-    const int n = i1 - i0;
+    // particles: the range of cells gc (and gc + 1), then in 2D that of cells gc + 4, gc + 5
+    const int i0 = cell_start[gc];
+    const int n0 = cell_start[gc + (kGroup ? 2 : 1)] - i0;
+    const int i1 = kGroup ? cell_start[gc + 4] : 0;
+    const int n = n0 + (kGroup ? cell_start[gc + 6] - i1 : 0);
     if (n == 0) return;
     const SimConst<T> S = sims[s];
-    const int ncu = S.ncu;
+    const int sw1 = 2 * S.sub + 1 + kExt;
+    const int ncu = kGroup ? sw1 * sw1 : S.ncu;
     const T R2 = exact ? S.H2 : S.HL2;  // list radius: the support, or the support plus the skin
     // the cell's coordinates from its block and its place inside the block
     int cc[3];
@@ -646,7 +662,7 @@ __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ c
         const int u = lane + 64 * half;
         int first = 0, count = 0, code = 0;
         if (u < ncu) {
-            code = stencil_entry<DIM>(S, blk_rank, cc, u);
+            code = stencil_entry<DIM, T, kExt>(S, blk_rank, cc, u);
             const int id = code & kStencilIdMask;
             first = cell_start[id];
             count = cell_start[id + 1] - first;
@@ -685,13 +701,17 @@ __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ c
         u = rec[j];
     };
 
+    // sorted index of the wavefront's particle q (the two ranges in order)
+    auto pidx = [&](int q) { return q < n0 ? i0 + q : i1 + (q - n0); };
     int pairs_acc = 0;
     for (int pb = 0; pb < n; pb += 64) {
         const int nb = __builtin_amdgcn_readfirstlane((n - pb < 64) ? n - pb : 64);
+        // batch positions [0, split) are in the first range, [split, nb) in the second
+        const int split = __builtin_amdgcn_readfirstlane(n0 - pb < 0 ? 0 : (n0 - pb < nb ? n0 - pb : nb));
         __syncthreads();
-        if (lane < nb) pu[lane] = rec[i0 + pb + lane];
+        if (lane < nb) pu[lane] = rec[pidx(pb + lane)];
         __syncthreads();
-        int cnt = 0;  // lane p: entries of particle i0 + pb + p so far
+        int cnt = 0;  // lane p: entries of the batch's particle p so far
         int jn = 0, coden = 0;
         vec4_t<T> un;
         un.x = un.y = un.z = un.w = T(0);
@@ -713,8 +733,9 @@ __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ c
             for (int k = 0; k < 3; ++k) ujs[k] = uj[k] + sh[k];
             if (c0 + 64 + lane < M) fetch(c0 + 64 + lane, jn, un, coden);  // next chunk in flight
             const unsigned long long vmask = __ballot(valid);
-            int32_t* row = nbr + (int64_t)(i0 + pb) * width;
-            for (int p = 0; p < nb; ++p, row += width) {
+            // the rounds of batch positions [p0, p1), whose rows follow each other from row
+            auto rounds = [&](int p0, int p1, int32_t* row) {
+            for (int p = p0; p < p1; ++p, row += width) {
                 T ui[3] = {T(0), T(0), T(0)};
                 const vec4_t<T> rp = pu[p];
                 unpack_u<T, DIM>(rp, ui);
@@ -746,9 +767,12 @@ __global__ __launch_bounds__(64) void k_build_list(const int32_t* __restrict__ c
                 }
                 cnt = (lane == p) ? total : cnt;  // lane p keeps p's count
             }
+            };
+            rounds(0, split, nbr + (int64_t)(i0 + pb) * width);
+            if (kGroup) rounds(split, nb, nbr + (int64_t)pidx(pb + split) * width);
         }
         if (lane < nb) {
-            const int i = i0 + pb + lane;
+            const int i = pidx(pb + lane);
             nbr_count[i] = cnt;
             if (cnt > width) atomicOr(&status[s], kFlagOverflow);
             pairs_acc += cnt - 1;

@@ -163,6 +163,25 @@ def _exact_lists(orc, plan, st, spec):
     return off_r
 
 
+def _cell_slots_2d(spec, skin=0.0):
+    """Cell slots of a 2D plan (blocks of 4 x 4 cells of side >= H (1 + skin) / 2)."""
+    import math
+    nc = math.floor(2.0 * spec.box / (spec.H * (1.0 + skin) * (1.0 + 2.0 ** -10)))
+    nb = -(-nc // 4)
+    return nb * nb * 16
+
+
+def test_grouped_build_lists_bit_exact(orc):
+    """A 2D plan with at least 65 536 cell slots builds its lists by groups of 2 x 2 cells over
+    their union stencil; its lists still equal the oracle's element for element (512^2)."""
+    from paper_2507_21684_amd.lib import Plan
+    spec = SimSpec(2, 512)
+    assert _cell_slots_2d(spec) >= 65536
+    st = _f32(spec, 3)
+    plan = Plan([spec.params()], [spec.n], "f32", tape_depth=1, device=DEV)
+    _exact_lists(orc, plan, st, spec)
+
+
 @pytest.mark.parametrize("dim,side", [(2, 256), (3, 64)])
 def test_full_size_neighbor_lists_bit_exact(orc, dim, side):
     """Lists of the full-size initial states, and in 2D of the state the oracle reaches after 16

@@ -117,12 +117,14 @@ def test_filtered_pair_count_and_export_are_exact():
 
 
 @pytest.mark.parametrize("speed", [False, True])
-@pytest.mark.parametrize("dim,side,amp,skin,rebuild", [(2, 40, 1.5, 0.2, 4), (2, 32, 2.0, 0.4, 6), (3, 14, 1.2, 0.15, 4)])
+@pytest.mark.parametrize("dim,side,amp,skin,rebuild", [(2, 40, 1.5, 0.2, 4), (2, 32, 2.0, 0.4, 6), (3, 14, 1.2, 0.15, 4),
+                                                     (2, 768, 1.0, 0.3, 4)])
 def test_reused_lists_hold_every_pair_of_the_interval(dim, side, amp, skin, rebuild, speed):
     """Uniform and speed-scaled half skins: over a reuse interval the filtered sweeps count
     exactly the pairs that exact lists of the same states hold.  FP64, where the two
     trajectories differ only by summation order, far too little to move a pair across H.  The
-    cases put the fastest particle at about three quarters of its half skin."""
+    cases put the fastest particle at about three quarters of its half skin; the 768^2 case has
+    enough cells (87 616 slots) for the list build by groups of 2 x 2 cells."""
     spec = SimSpec(dim, side, amplitude=amp)
     st = _state(spec, 9, "f64")
     reused = _plan([spec], "f64", skin=skin, rebuild=rebuild, speed_skins=speed)
