@@ -284,7 +284,11 @@ def roofline(prof, dom, wl, per_state, reps, dim, n_particles, lanes=(4, 4), tap
         achieved = bytes_per_launch / mean_launch_s / 1e9
         peak = PEAK_HBM_GBS
         tdt = "float" if wl.dtype == "f32" else "double"
-        traffic = measured_traffic(wl.name, "sph::k_build_list<%s,%d,%s>" % (tdt, dim, "true" if speed_skins else "false"))
+        # the build kernel's last template argument: built by groups of 2 x 2 cells (large 2D plans)
+        sym = "sph::k_build_list<%s,%d,%s,%%s>" % (tdt, dim, "true" if speed_skins else "false")
+        traffic = measured_traffic(wl.name, sym % "true")
+        if traffic is None:
+            traffic = measured_traffic(wl.name, sym % "false")
         return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": peak, "unit": "GB/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic,
                 "mean_launch_us": round(mean_launch_s * 1e6, 2), "launches": n_dom,
